@@ -1,0 +1,116 @@
+/*
+ * or.h -- plain FP64 CPU oracle for checkerboard overrelaxation gauge fixing
+ * (Schroeck & Vogt, "Gauge fixing using overrelaxation and simulated annealing
+ * on GPUs", arXiv:1209.4008).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark call this library. The GPU library shares no
+ * code with it, and no product code path may route through it.
+ *
+ * Field layout (canonical, host memory): complex128, interleaved (re, im),
+ *   U[s][mu][a][b]  with  s = ((t*nz + z)*ny + y)*nx + x,
+ * i.e. double index ((s*4 + mu)*9 + 3*a + b)*2 + {0: re, 1: im}.
+ * dims = {nt, nz, ny, nx}; direction mu = 0 is t, mu = 1, 2, 3 are x, y, z.
+ * Boundaries are periodic; every extent must be even and >= 2 so that the
+ * two checkerboard sublattices share no link (Sec. 2, RED/BLACK
+ * decomposition). Parity of a site is (t + x + y + z) mod 2; RED = 0.
+ *
+ * Gauge: OR_LANDAU sums directions mu = 0..3 in K(x), F and theta;
+ * OR_COULOMB sums mu = 1..3 only and reports F and theta per timeslice.
+ * In both gauges the site transformation is applied to all four links
+ * U_mu(x) and U_mu(x - mu) (the temporal links of the Coulomb gauge are
+ * transformed in place so that the output is a gauge transform of the input).
+ *
+ * Functions returning int return 0 on success and a negative value on bad
+ * arguments (odd or too small extents, omega outside [1, 2), T <= 0).
+ */
+#ifndef GF_ORACLE_OR_H
+#define GF_ORACLE_OR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_LANDAU 0
+#define OR_COULOMB 1
+
+/* geometry ---------------------------------------------------------------- */
+int     or_check_dims(const int32_t dims[4]);
+int64_t or_volume(const int32_t dims[4]);
+int     or_num_threads(void);
+void    or_set_num_threads(int n);
+
+/* building blocks (exposed so that the tests can pin each step) ----------- */
+/* Quaternion (a0, a1, a2, a3) <-> SU(2) matrix [[a0+i a3, a2+i a1],
+ * [-a2+i a1, a0-i a3]].  Given a 3x3 complex M (18 doubles, row major) and a
+ * subgroup (i, j), q receives the quaternion (SU(2)-proportional) part of the
+ * 2x2 block M[{i,j},{i,j}]. */
+void or_su2_part(const double M[18], int i, int j, double q[4]);
+/* Overrelaxed local transformation s = g^omega from the unnormalised
+ * quaternion q of K^dagger (Sec. 2, overrelaxation paragraph; flop-count
+ * reading of Alg. 1): unit norm on output. Returns -1 if |q| is degenerate. */
+int  or_overrelax(const double q[4], double omega, double s[4]);
+/* K(x) of eq. (5) (sum over mu of U_mu(x) + U_mu(x-mu)^dagger) at site s. */
+void or_local_K(const double* U, const int32_t dims[4], int gauge, int64_t s, double K[18]);
+
+/* the hot path ------------------------------------------------------------ */
+/* One checkerboard half-sweep of overrelaxation over the sites of one parity
+ * (Alg. 1; omega = 1 is plain relaxation). */
+int  or_sweep(double* U, const int32_t dims[4], int gauge, int parity, double omega);
+/* Gauge functional eq. (3), normalised so that U = 1 gives 1. out[0] (Landau)
+ * or out[t], t < nt (Coulomb). Returns the Landau value or the mean over t. */
+double or_functional(const double* U, const int32_t dims[4], int gauge, double* out);
+/* Raw (unnormalised) sum Re sum_{x,mu in D} tr U_mu(x) of eq. (3). */
+double or_functional_raw(const double* U, const int32_t dims[4], int gauge);
+/* Precision theta of Sec. 2 computed from the lattice gauge potential A_mu
+ * (theta_A) and from the local sums K(x) (theta_K); same output convention as
+ * or_functional; the return value is the Landau value or the max over t. */
+double or_theta_A(const double* U, const int32_t dims[4], int gauge, double* out);
+double or_theta_K(const double* U, const int32_t dims[4], int gauge, double* out);
+/* Gram-Schmidt projection of each link back onto SU(3). */
+void   or_reunitarize(double* U, int64_t n_links);
+/* Average plaquette (1/3) Re tr of the elementary plaquette. */
+double or_plaquette(const double* U, const int32_t dims[4]);
+/* U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger, g[s][3][3] complex128 (eq. (4)). */
+int    or_gauge_transform(double* U, const int32_t dims[4], const double* g);
+
+/* Driver: sweeps (RED then BLACK) with a check every check_every sweeps,
+ * starting before the first sweep; at each check after the first, the field
+ * is first reunitarised if reunit_at_check != 0. Stops when theta < target
+ * (Coulomb: max over timeslices) or when max_sweeps is reached.
+ * Returns 0 if converged, 1 if not, <0 on bad arguments. */
+int or_fix(double* U, const int32_t dims[4], int gauge, double omega,
+           double theta_target, int32_t max_sweeps, int32_t check_every,
+           int32_t reunit_at_check, int32_t* sweeps_out, double* F_out,
+           double* theta_out);
+
+/* simulated annealing ----------------------------------------------------- */
+/* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11). */
+void or_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Kennedy-Pendleton draw of X0 with density ~ sqrt(1-X0^2) exp(alpha X0),
+ * using the same Philox streams as the annealing sweep for (site, sweep,
+ * subgroup). Returns the number of attempts used (0 if the cap was hit). */
+int  or_kp_draw(double alpha, uint64_t seed, uint64_t site, uint64_t sweep,
+                int subgroup, double* X0);
+/* Full SU(2) draw X (X0 as above, direction uniform) for the same streams. */
+int  or_heatbath_su2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep,
+                     int subgroup, double X[4]);
+/* Heatbath half-sweep of the annealing step at temperature T: the local
+ * transformation is drawn with weight exp(Re tr[g K] / T). n_capped (may be
+ * NULL) accumulates the number of subgroup updates that hit the attempt cap. */
+int  or_heatbath_half(double* U, const int32_t dims[4], int gauge, int parity,
+                      double T, uint64_t seed, uint64_t sweep, int64_t* n_capped);
+/* Microcanonical half-sweep: g = (local maximum)^2, which leaves Re tr[g K]
+ * unchanged. */
+int  or_micro_half(double* U, const int32_t dims[4], int gauge, int parity);
+/* One annealing step: heatbath RED, BLACK, then n_micro microcanonical
+ * sweeps (RED, BLACK each). */
+int  or_anneal_sweep(double* U, const int32_t dims[4], int gauge, double T,
+                     uint64_t seed, uint64_t sweep, int n_micro, int64_t* n_capped);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

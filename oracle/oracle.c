@@ -1,0 +1,726 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle for checkerboard overrelaxation gauge
+ * fixing and simulated annealing (Schroeck & Vogt, arXiv:1209.4008).
+ *
+ * TEST INFRASTRUCTURE. This file is the independent reference that the GPU
+ * library is checked against. It is called only from the test suite, the
+ * smoke check and the CPU baseline leg of the benchmark. It shares no code
+ * (no headers, helpers, tables or constants) with the GPU library.
+ *
+ * Style: every step is written out with full 3x3 complex matrices in the
+ * order the paper gives it, without blocking, fusion or reordering, so that a
+ * reader can check it against the paper by eye. Compiled -O2
+ * -ffp-contract=off (no FMA contraction, no fast-math); OpenMP only splits
+ * the sites of one checkerboard sublattice, which share no link, and all
+ * reductions are summed serially in site order (results do not depend on
+ * the thread count).
+ *
+ * Passages followed (sections/equations of the paper):
+ *   eq. (4)  gauge transformation U^g_mu(x) = g(x) U_mu(x) g(x+mu)^dagger
+ *   eq. (3)  Landau gauge functional F_g = Re sum_{mu,x} tr U^g_mu(x)
+ *   eq. (5)  K(x) = sum_mu U_mu(x) g(x+mu)^dag + U_mu(x-mu)^dag g(x-mu)^dag
+ *   eq. (6)  SU(2) local solution g = K^dag / sqrt(det K^dag), applied in the
+ *            three SU(2) subgroups of SU(3) (Sec. 2, Cabibbo-Marinari)
+ *   Sec. 2   overrelaxation g -> g^omega, omega in [1, 2)
+ *   Sec. 2   RED/BLACK checkerboard decomposition
+ *   eq. (7)  precision theta = (1/(V N_c)) sum_x tr[Delta(x) Delta(x)^dag]
+ *   Alg. 1   Overrelaxation (order of the steps, flop counts 60/19/84/84)
+ *   Sec. 1   simulated annealing as a preconditioner; Coulomb gauge
+ * Points where the paper is silent are filled with the readings documented
+ * next to the code that uses them (degenerate subgroups, theta's Delta,
+ * normalisation of F, form of g^omega, annealing weight and sampler).
+ */
+#include "or.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------- */
+/* complex numbers and 3x3 complex matrices                                   */
+/* ------------------------------------------------------------------------- */
+typedef struct { double re, im; } cx;
+typedef struct { cx m[3][3]; } mat3;
+
+static cx cx_make(double re, double im) { cx z; z.re = re; z.im = im; return z; }
+static cx cx_add(cx a, cx b) { return cx_make(a.re + b.re, a.im + b.im); }
+static cx cx_sub(cx a, cx b) { return cx_make(a.re - b.re, a.im - b.im); }
+static cx cx_mul(cx a, cx b) { return cx_make(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
+static cx cx_conj(cx a) { return cx_make(a.re, -a.im); }
+static double cx_abs2(cx a) { return a.re * a.re + a.im * a.im; }
+
+static mat3 mat_zero(void) { mat3 A; memset(&A, 0, sizeof A); return A; }
+static mat3 mat_unit(void) {
+  mat3 A = mat_zero();
+  for (int a = 0; a < 3; ++a) A.m[a][a] = cx_make(1.0, 0.0);
+  return A;
+}
+static mat3 mat_mul(const mat3* A, const mat3* B) {
+  mat3 C;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      cx acc = cx_make(0.0, 0.0);
+      for (int k = 0; k < 3; ++k) acc = cx_add(acc, cx_mul(A->m[a][k], B->m[k][b]));
+      C.m[a][b] = acc;
+    }
+  return C;
+}
+static mat3 mat_dag(const mat3* A) {
+  mat3 C;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) C.m[a][b] = cx_conj(A->m[b][a]);
+  return C;
+}
+static mat3 mat_add(const mat3* A, const mat3* B) {
+  mat3 C;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) C.m[a][b] = cx_add(A->m[a][b], B->m[a][b]);
+  return C;
+}
+static double mat_retr(const mat3* A) { return A->m[0][0].re + A->m[1][1].re + A->m[2][2].re; }
+
+/* ------------------------------------------------------------------------- */
+/* geometry: periodic 4D lattice, s = ((t*nz + z)*ny + y)*nx + x              */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t ext[4]; /* extent along direction mu: t, x, y, z */
+  int64_t V;
+} lat_t;
+
+int or_check_dims(const int32_t dims[4]) {
+  if (!dims) return -1;
+  for (int k = 0; k < 4; ++k)
+    if (dims[k] < 2 || (dims[k] & 1)) return -1; /* checkerboard needs even extents */
+  return 0;
+}
+
+int64_t or_volume(const int32_t dims[4]) {
+  return (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+}
+
+static lat_t make_lat(const int32_t dims[4]) {
+  lat_t L;
+  L.ext[0] = dims[0]; /* t */
+  L.ext[1] = dims[3]; /* x */
+  L.ext[2] = dims[2]; /* y */
+  L.ext[3] = dims[1]; /* z */
+  L.V = or_volume(dims);
+  return L;
+}
+
+static void site_coords(const lat_t* L, int64_t s, int64_t c[4]) {
+  c[1] = s % L->ext[1]; s /= L->ext[1];
+  c[2] = s % L->ext[2]; s /= L->ext[2];
+  c[3] = s % L->ext[3]; s /= L->ext[3];
+  c[0] = s;
+}
+
+static int64_t site_index(const lat_t* L, const int64_t c[4]) {
+  return ((c[0] * L->ext[3] + c[3]) * L->ext[2] + c[2]) * L->ext[1] + c[1];
+}
+
+static int site_parity(const lat_t* L, int64_t s) {
+  int64_t c[4];
+  site_coords(L, s, c);
+  return (int)((c[0] + c[1] + c[2] + c[3]) & 1);
+}
+
+/* neighbour x + step*mu_hat with periodic wrap */
+static int64_t neighbour(const lat_t* L, int64_t s, int mu, int step) {
+  int64_t c[4];
+  site_coords(L, s, c);
+  c[mu] = (c[mu] + step + L->ext[mu]) % L->ext[mu];
+  return site_index(L, c);
+}
+
+/* ------------------------------------------------------------------------- */
+/* link access in the canonical layout U[s][mu][3][3]                         */
+/* ------------------------------------------------------------------------- */
+static mat3 get_link(const double* U, int64_t s, int mu) {
+  mat3 A;
+  const double* p = U + ((s * 4 + mu) * 9) * 2;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) A.m[a][b] = cx_make(p[(3 * a + b) * 2], p[(3 * a + b) * 2 + 1]);
+  return A;
+}
+
+static void put_link(double* U, int64_t s, int mu, const mat3* A) {
+  double* p = U + ((s * 4 + mu) * 9) * 2;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      p[(3 * a + b) * 2] = A->m[a][b].re;
+      p[(3 * a + b) * 2 + 1] = A->m[a][b].im;
+    }
+}
+
+static mat3 mat_from18(const double M[18]) {
+  mat3 A;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) A.m[a][b] = cx_make(M[(3 * a + b) * 2], M[(3 * a + b) * 2 + 1]);
+  return A;
+}
+
+static void mat_to18(const mat3* A, double M[18]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      M[(3 * a + b) * 2] = A->m[a][b].re;
+      M[(3 * a + b) * 2 + 1] = A->m[a][b].im;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* SU(2) subgroups of SU(3) (Sec. 2, Cabibbo-Marinari)                        */
+/* ------------------------------------------------------------------------- */
+/* Subgroup order (0,1), (0,2), (1,2): the paper does not fix it. */
+static const int SG_I[3] = {0, 0, 1};
+static const int SG_J[3] = {1, 2, 2};
+
+/* Quaternion part of the (i,j) block, for the convention
+ *   a <-> [[a0 + i a3, a2 + i a1], [-a2 + i a1, a0 - i a3]].
+ * Any 2x2 complex block B splits as B = Q(a) + i Q(b) with real quaternions
+ * a, b; only a contributes to Re tr[g B] for g in SU(2), and a is what is
+ * returned here. For B in R * SU(2) the block equals Q(a). */
+void or_su2_part(const double M18[18], int i, int j, double q[4]) {
+  mat3 M = mat_from18(M18);
+  cx bii = M.m[i][i], bij = M.m[i][j], bji = M.m[j][i], bjj = M.m[j][j];
+  q[0] = 0.5 * (bii.re + bjj.re);
+  q[1] = 0.5 * (bij.im + bji.im);
+  q[2] = 0.5 * (bij.re - bji.re);
+  q[3] = 0.5 * (bii.im - bjj.im);
+}
+
+/* Embed the SU(2) element with quaternion a into SU(3) at rows/cols (i,j). */
+static mat3 embed_su2(const double a[4], int i, int j) {
+  mat3 G = mat_unit();
+  G.m[i][i] = cx_make(a[0], a[3]);
+  G.m[i][j] = cx_make(a[2], a[1]);
+  G.m[j][i] = cx_make(-a[2], a[1]);
+  G.m[j][j] = cx_make(a[0], -a[3]);
+  return G;
+}
+
+/* Below this |q|^2 the subgroup is skipped (G = 1): the paper does not say
+ * what to do with a vanishing local sum. */
+#define OR_DEGENERATE 1e-300
+
+/* Overrelaxation (Sec. 2): replace the local maximum g = q/|q| by g^omega.
+ * The paper only says the power is taken "to first or second order" and
+ * counts 19 flop for "g -> g^omega, project to SU(2)" (Alg. 1). The reading
+ * used here works on the unnormalised q = (q0, qv):
+ *   b = (omega q0^2 + |qv|^2) / (q0^2 + |qv|^2),
+ *   c = 1 / sqrt(q0^2 + b^2 |qv|^2),
+ *   s = (c q0, b c qv),
+ * which is unit-norm, equals q/|q| exactly at omega = 1, and for
+ * q ~ (cos phi, sin phi n) rotates by phi' with
+ * tan phi' = (1 + (omega-1) cos^2 phi) tan phi, i.e. phi' = omega phi to
+ * first order in phi. Its operation count is 19. */
+int or_overrelax(const double q[4], double omega, double s[4]) {
+  double a0sq = q[0] * q[0];
+  double avsq = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+  if (a0sq + avsq < OR_DEGENERATE) return -1;
+  double b = (omega * a0sq + avsq) / (a0sq + avsq);
+  double c = 1.0 / sqrt(a0sq + b * b * avsq);
+  s[0] = c * q[0];
+  s[1] = b * c * q[1];
+  s[2] = b * c * q[2];
+  s[3] = b * c * q[3];
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as     */
+/* easy as 1, 2, 3", SC'11): 10 rounds of the Philox S-box on a 4x32 counter  */
+/* with a 2x32 key bumped by the Weyl constants between rounds.               */
+/* ------------------------------------------------------------------------- */
+void or_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* uniform in (0, 1): (u + 1/2) 2^-32 */
+static double u01(uint32_t u) { return ((double)u + 0.5) * (1.0 / 4294967296.0); }
+
+/* Counter layout of the annealing draws (one Philox block per use):
+ *   key = (seed low 32 bits, seed high 32 bits)
+ *   ctr = (site index, sweep low 32 bits, tag, attempt)
+ *   tag = 0x1000 | kind << 8 | subgroup; kind 0 = KP trial, 1 = direction. */
+#define OR_TAG_KP(sg) (0x1000u | (0u << 8) | (uint32_t)(sg))
+#define OR_TAG_DIR(sg) (0x1000u | (1u << 8) | (uint32_t)(sg))
+#define OR_KP_MAX_ATTEMPTS 1024
+
+static void draw_block(uint64_t seed, uint64_t site, uint64_t sweep, uint32_t tag,
+                       uint32_t attempt, double u[4]) {
+  uint32_t ctr[4] = {(uint32_t)site, (uint32_t)sweep, tag, attempt};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t r[4];
+  or_philox4x32(ctr, key, r);
+  for (int k = 0; k < 4; ++k) u[k] = u01(r[k]);
+}
+
+/* Kennedy & Pendleton, Phys. Lett. B 156 (1985) 393: with
+ * lambda^2 = -(ln u1 + cos^2(2 pi u2) ln u3) / (2 alpha) (a Gamma(3/2)
+ * variate scaled by 1/(2 alpha)), accept when u4^2 <= 1 - lambda^2 and set
+ * X0 = 1 - 2 lambda^2; X0 then has density ~ sqrt(1 - X0^2) exp(alpha X0). */
+int or_kp_draw(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int sg, double* X0) {
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int a = 0; a < OR_KP_MAX_ATTEMPTS; ++a) {
+    double u[4];
+    draw_block(seed, site, sweep, OR_TAG_KP(sg), (uint32_t)a, u);
+    double cs = cos(two_pi * u[1]);
+    double lam2 = -(log(u[0]) + cs * cs * log(u[2])) / (2.0 * alpha);
+    if (u[3] * u[3] <= 1.0 - lam2) {
+      *X0 = 1.0 - 2.0 * lam2;
+      return a + 1;
+    }
+  }
+  return 0;
+}
+
+/* SU(2) element X with density ~ exp(alpha X0) under Haar measure: X0 from
+ * the Kennedy-Pendleton draw, (X1, X2, X3) uniform on the sphere of radius
+ * sqrt(1 - X0^2) from one more Philox block (cos theta = 2 u1 - 1,
+ * phi = 2 pi u2). Returns the attempts used, 0 if the cap was hit. */
+int or_heatbath_su2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int sg,
+                    double X[4]) {
+  double X0;
+  int n = or_kp_draw(alpha, seed, site, sweep, sg, &X0);
+  if (n == 0) return 0;
+  const double two_pi = 6.283185307179586476925286766559;
+  double d[4];
+  draw_block(seed, site, sweep, OR_TAG_DIR(sg), 0u, d);
+  double cth = 2.0 * d[0] - 1.0;
+  double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
+  double phi = two_pi * d[1];
+  double rad = sqrt(fmax(0.0, 1.0 - X0 * X0));
+  X[0] = X0;
+  X[1] = rad * sth * cos(phi);
+  X[2] = rad * sth * sin(phi);
+  X[3] = rad * cth;
+  return n;
+}
+
+/* ------------------------------------------------------------------------- */
+/* site update (Alg. 1 body) for overrelaxation, heatbath and microcanonical  */
+/* ------------------------------------------------------------------------- */
+enum { UPD_OR = 0, UPD_HB = 1, UPD_MICRO = 2 };
+typedef struct {
+  int kind;
+  double omega;
+  double T;
+  uint64_t seed, sweep;
+} upd_t;
+
+/* First direction entering K, F and theta: Landau all four, Coulomb the
+ * spatial ones (Sec. 1: Coulomb gauge d_i A_i = 0). */
+static int first_dir(int gauge) { return gauge == OR_COULOMB ? 1 : 0; }
+
+/* K(x)^dagger as written in the first line of the body of Alg. 1:
+ * sum_mu U_mu(x)^dagger + U_mu(x - mu). The stored links already carry the
+ * transformations of all previously updated sites, so the g(x +- mu) of
+ * eq. (5) are absorbed. */
+static mat3 local_Kdag(const double* U, const lat_t* L, int gauge, int64_t s) {
+  mat3 Kd = mat_zero();
+  for (int mu = first_dir(gauge); mu < 4; ++mu) {
+    mat3 Uf = get_link(U, s, mu);
+    mat3 Ub = get_link(U, neighbour(L, s, mu, -1), mu);
+    mat3 Ufd = mat_dag(&Uf);
+    Kd = mat_add(&Kd, &Ufd);
+    Kd = mat_add(&Kd, &Ub);
+  }
+  return Kd;
+}
+
+void or_local_K(const double* U, const int32_t dims[4], int gauge, int64_t s, double K[18]) {
+  lat_t L = make_lat(dims);
+  mat3 Kd = local_Kdag(U, &L, gauge, s);
+  mat3 Km = mat_dag(&Kd);
+  mat_to18(&Km, K);
+}
+
+/* returns the number of subgroup updates that hit the heatbath attempt cap */
+static int site_update(double* U, const lat_t* L, int gauge, int64_t s, const upd_t* u) {
+  int capped = 0;
+  for (int sg = 0; sg < 3; ++sg) {
+    int i = SG_I[sg], j = SG_J[sg];
+    /* Alg. 1: g(x) <- sum_mu {U_mu(x)^dag + U_mu(x - mu)}, recomputed for
+     * every subgroup from the current links (60 flop in the paper's count) */
+    mat3 Kd = local_Kdag(U, L, gauge, s);
+    double M18[18], q[4], g[4];
+    mat_to18(&Kd, M18);
+    /* project the (i,j) block to SU(2): by eq. (6) the maximiser of
+     * Re tr[g K] over the subgroup is the normalised quaternion part of K^dag */
+    or_su2_part(M18, i, j, q);
+    double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    if (qn2 < OR_DEGENERATE) continue;
+    mat3 G;
+    if (u->kind == UPD_OR) {
+      /* Alg. 1: g -> g^omega, project to SU(2) (19 flop) */
+      if (or_overrelax(q, u->omega, g) < 0) continue;
+      G = embed_su2(g, i, j);
+    } else if (u->kind == UPD_MICRO) {
+      /* microcanonical step: g = ghat^2, the reflection through the local
+       * maximum; it leaves Re tr[g K] unchanged */
+      double n = sqrt(qn2);
+      double qh[4] = {q[0] / n, q[1] / n, q[2] / n, q[3] / n};
+      mat3 Gh = embed_su2(qh, i, j);
+      G = mat_mul(&Gh, &Gh);
+    } else {
+      /* heatbath with weight exp(Re tr[g K] / T) on the subgroup. With
+       * Re tr[g K] = 2|q| X0 for g = X qhat, X is drawn with density
+       * ~ exp(alpha X0) under Haar measure, alpha = 2|q|/T. */
+      double n = sqrt(qn2);
+      double X[4];
+      if (or_heatbath_su2(2.0 * n / u->T, u->seed, (uint64_t)s, u->sweep, sg, X) == 0) {
+        ++capped;
+        continue;
+      }
+      double qh[4] = {q[0] / n, q[1] / n, q[2] / n, q[3] / n};
+      mat3 GX = embed_su2(X, i, j);
+      mat3 Gh = embed_su2(qh, i, j);
+      G = mat_mul(&GX, &Gh);
+    }
+    /* Alg. 1: for all mu, U_mu(x) <- g U_mu(x) and U_mu(x-mu) <- U_mu(x-mu) g^dag
+     * (84 + 84 flop); all four directions also in the Coulomb gauge */
+    mat3 Gd = mat_dag(&G);
+    for (int mu = 0; mu < 4; ++mu) {
+      int64_t sb = neighbour(L, s, mu, -1);
+      mat3 Uf = get_link(U, s, mu);
+      mat3 Ub = get_link(U, sb, mu);
+      mat3 Ufn = mat_mul(&G, &Uf);
+      mat3 Ubn = mat_mul(&Ub, &Gd);
+      put_link(U, s, mu, &Ufn);
+      put_link(U, sb, mu, &Ubn);
+    }
+  }
+  return capped;
+}
+
+static int half_sweep(double* U, const int32_t dims[4], int gauge, int parity, const upd_t* u,
+                      int64_t* n_capped) {
+  if (!U || or_check_dims(dims) != 0 || (parity != 0 && parity != 1)) return -1;
+  if (gauge != OR_LANDAU && gauge != OR_COULOMB) return -1;
+  lat_t L = make_lat(dims);
+  int64_t capped = 0;
+  /* Sec. 2: all sites of one sublattice are independent (no shared link) */
+#pragma omp parallel for schedule(static) reduction(+ : capped)
+  for (int64_t s = 0; s < L.V; ++s) {
+    if (site_parity(&L, s) != parity) continue;
+    capped += site_update(U, &L, gauge, s, u);
+  }
+  if (n_capped) *n_capped += capped;
+  return 0;
+}
+
+int or_sweep(double* U, const int32_t dims[4], int gauge, int parity, double omega) {
+  if (!(omega >= 1.0 && omega < 2.0)) return -1; /* Sec. 2: omega in [1, 2) */
+  upd_t u = {UPD_OR, omega, 0.0, 0, 0};
+  return half_sweep(U, dims, gauge, parity, &u, NULL);
+}
+
+int or_micro_half(double* U, const int32_t dims[4], int gauge, int parity) {
+  upd_t u = {UPD_MICRO, 0.0, 0.0, 0, 0};
+  return half_sweep(U, dims, gauge, parity, &u, NULL);
+}
+
+int or_heatbath_half(double* U, const int32_t dims[4], int gauge, int parity, double T,
+                     uint64_t seed, uint64_t sweep, int64_t* n_capped) {
+  if (!(T > 0.0) || !isfinite(T)) return -1;
+  upd_t u = {UPD_HB, 0.0, T, seed, sweep};
+  return half_sweep(U, dims, gauge, parity, &u, n_capped);
+}
+
+int or_anneal_sweep(double* U, const int32_t dims[4], int gauge, double T, uint64_t seed,
+                    uint64_t sweep, int n_micro, int64_t* n_capped) {
+  if (n_micro < 0) return -1;
+  int rc = 0;
+  for (int p = 0; p < 2 && rc == 0; ++p)
+    rc = or_heatbath_half(U, dims, gauge, p, T, seed, sweep, n_capped);
+  for (int k = 0; k < n_micro && rc == 0; ++k)
+    for (int p = 0; p < 2 && rc == 0; ++p) rc = or_micro_half(U, dims, gauge, p);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* reductions                                                                 */
+/* ------------------------------------------------------------------------- */
+double or_functional_raw(const double* U, const int32_t dims[4], int gauge) {
+  lat_t L = make_lat(dims);
+  double* per_site = (double*)malloc(sizeof(double) * (size_t)L.V);
+  int mu0 = first_dir(gauge);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < L.V; ++s) {
+    double acc = 0.0;
+    for (int mu = mu0; mu < 4; ++mu) {
+      mat3 A = get_link(U, s, mu);
+      acc += mat_retr(&A);
+    }
+    per_site[s] = acc;
+  }
+  double sum = 0.0;
+  for (int64_t s = 0; s < L.V; ++s) sum += per_site[s];
+  free(per_site);
+  return sum;
+}
+
+/* Eq. (3), normalised by N_c |D| V (Landau) or N_c |D| V_s per timeslice
+ * (Coulomb) so that the unit field gives exactly 1; the paper prints the
+ * unnormalised sum. */
+double or_functional(const double* U, const int32_t dims[4], int gauge, double* out) {
+  lat_t L = make_lat(dims);
+  int mu0 = first_dir(gauge);
+  double* per_site = (double*)malloc(sizeof(double) * (size_t)L.V);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < L.V; ++s) {
+    double acc = 0.0;
+    for (int mu = mu0; mu < 4; ++mu) {
+      mat3 A = get_link(U, s, mu);
+      acc += mat_retr(&A);
+    }
+    per_site[s] = acc;
+  }
+  double ret;
+  if (gauge == OR_LANDAU) {
+    double sum = 0.0;
+    for (int64_t s = 0; s < L.V; ++s) sum += per_site[s];
+    ret = sum / (3.0 * 4.0 * (double)L.V);
+    if (out) out[0] = ret;
+  } else {
+    int64_t nt = L.ext[0], Vs = L.V / nt;
+    double mean = 0.0;
+    for (int64_t t = 0; t < nt; ++t) {
+      double sum = 0.0;
+      for (int64_t k = 0; k < Vs; ++k) sum += per_site[t * Vs + k];
+      double Ft = sum / (3.0 * 3.0 * (double)Vs);
+      if (out) out[t] = Ft;
+      mean += Ft;
+    }
+    ret = mean / (double)nt;
+  }
+  free(per_site);
+  return ret;
+}
+
+/* Hermitian traceless part of (M - M^dag)/(2i): for M = U_mu(x) this is the
+ * lattice gauge potential A_mu(x) (U = exp(i a g A), eq. (2), to first order). */
+static mat3 traceless_antiherm(const mat3* M) {
+  mat3 A;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      cx d = cx_sub(M->m[a][b], cx_conj(M->m[b][a])); /* M - M^dag */
+      A.m[a][b] = cx_make(0.5 * d.im, -0.5 * d.re);   /* divided by 2i */
+    }
+  double tr3 = (A.m[0][0].re + A.m[1][1].re + A.m[2][2].re) / 3.0;
+  for (int a = 0; a < 3; ++a) A.m[a][a].re -= tr3;
+  return A;
+}
+
+static double tr_MMdag(const mat3* M) {
+  double acc = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) acc += cx_abs2(M->m[a][b]);
+  return acc;
+}
+
+/* Sum per-site contributions to theta (eq. (7)): Landau (1/(N_c V)) sum_x,
+ * Coulomb per timeslice (1/(N_c V_s)) sum_{x in t}. */
+static double finish_theta(const lat_t* L, int gauge, const double* per_site, double* out) {
+  if (gauge == OR_LANDAU) {
+    double sum = 0.0;
+    for (int64_t s = 0; s < L->V; ++s) sum += per_site[s];
+    double th = sum / (3.0 * (double)L->V);
+    if (out) out[0] = th;
+    return th;
+  }
+  int64_t nt = L->ext[0], Vs = L->V / nt;
+  double mx = 0.0;
+  for (int64_t t = 0; t < nt; ++t) {
+    double sum = 0.0;
+    for (int64_t k = 0; k < Vs; ++k) sum += per_site[t * Vs + k];
+    double th = sum / (3.0 * (double)Vs);
+    if (out) out[t] = th;
+    if (th > mx) mx = th;
+  }
+  return mx;
+}
+
+/* The paper uses Delta^g without defining it. Reading: the lattice
+ * divergence Delta(x) = sum_{mu in D} [A_mu(x) - A_mu(x - mu)] of the gauge
+ * potential of the current (already transformed) links. */
+double or_theta_A(const double* U, const int32_t dims[4], int gauge, double* out) {
+  lat_t L = make_lat(dims);
+  int mu0 = first_dir(gauge);
+  double* per_site = (double*)malloc(sizeof(double) * (size_t)L.V);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < L.V; ++s) {
+    mat3 D = mat_zero();
+    for (int mu = mu0; mu < 4; ++mu) {
+      mat3 Uf = get_link(U, s, mu);
+      mat3 Ub = get_link(U, neighbour(&L, s, mu, -1), mu);
+      mat3 Af = traceless_antiherm(&Uf);
+      mat3 Ab = traceless_antiherm(&Ub);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          D.m[a][b] = cx_add(D.m[a][b], cx_sub(Af.m[a][b], Ab.m[a][b]));
+    }
+    per_site[s] = tr_MMdag(&D);
+  }
+  double ret = finish_theta(&L, gauge, per_site, out);
+  free(per_site);
+  return ret;
+}
+
+/* Same quantity from K(x) of eq. (5): (K - K^dag)/(2i) equals
+ * sum_mu [(U_mu(x) - U_mu(x)^dag) - (U_mu(x-mu) - U_mu(x-mu)^dag)]/(2i),
+ * so its traceless part is Delta(x). */
+double or_theta_K(const double* U, const int32_t dims[4], int gauge, double* out) {
+  lat_t L = make_lat(dims);
+  double* per_site = (double*)malloc(sizeof(double) * (size_t)L.V);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < L.V; ++s) {
+    mat3 Kd = local_Kdag(U, &L, gauge, s);
+    mat3 K = mat_dag(&Kd);
+    mat3 D = traceless_antiherm(&K);
+    per_site[s] = tr_MMdag(&D);
+  }
+  double ret = finish_theta(&L, gauge, per_site, out);
+  free(per_site);
+  return ret;
+}
+
+/* Gram-Schmidt projection onto SU(3): normalise row 0, orthogonalise and
+ * normalise row 1, row 2 = conj(row0 x row1). The paper does not state how
+ * links are kept unitary; the last formula is also how a link stored as its
+ * first two rows is completed (Sec. 4.1, 12-real storage). */
+void or_reunitarize(double* U, int64_t n_links) {
+#pragma omp parallel for schedule(static)
+  for (int64_t l = 0; l < n_links; ++l) {
+    double* p = U + l * 18;
+    mat3 A = mat_from18(p);
+    double n0 = 0.0;
+    for (int b = 0; b < 3; ++b) n0 += cx_abs2(A.m[0][b]);
+    n0 = 1.0 / sqrt(n0);
+    for (int b = 0; b < 3; ++b) A.m[0][b] = cx_make(A.m[0][b].re * n0, A.m[0][b].im * n0);
+    cx ip = cx_make(0.0, 0.0); /* <row0, row1> = sum conj(u0) u1 */
+    for (int b = 0; b < 3; ++b) ip = cx_add(ip, cx_mul(cx_conj(A.m[0][b]), A.m[1][b]));
+    for (int b = 0; b < 3; ++b) A.m[1][b] = cx_sub(A.m[1][b], cx_mul(ip, A.m[0][b]));
+    double n1 = 0.0;
+    for (int b = 0; b < 3; ++b) n1 += cx_abs2(A.m[1][b]);
+    n1 = 1.0 / sqrt(n1);
+    for (int b = 0; b < 3; ++b) A.m[1][b] = cx_make(A.m[1][b].re * n1, A.m[1][b].im * n1);
+    A.m[2][0] = cx_conj(cx_sub(cx_mul(A.m[0][1], A.m[1][2]), cx_mul(A.m[0][2], A.m[1][1])));
+    A.m[2][1] = cx_conj(cx_sub(cx_mul(A.m[0][2], A.m[1][0]), cx_mul(A.m[0][0], A.m[1][2])));
+    A.m[2][2] = cx_conj(cx_sub(cx_mul(A.m[0][0], A.m[1][1]), cx_mul(A.m[0][1], A.m[1][0])));
+    mat_to18(&A, p);
+  }
+}
+
+double or_plaquette(const double* U, const int32_t dims[4]) {
+  lat_t L = make_lat(dims);
+  double* per_site = (double*)malloc(sizeof(double) * (size_t)L.V);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < L.V; ++s) {
+    double acc = 0.0;
+    for (int mu = 0; mu < 4; ++mu)
+      for (int nu = mu + 1; nu < 4; ++nu) {
+        mat3 A = get_link(U, s, mu);
+        mat3 B = get_link(U, neighbour(&L, s, mu, +1), nu);
+        mat3 C = get_link(U, neighbour(&L, s, nu, +1), mu);
+        mat3 D = get_link(U, s, nu);
+        mat3 Cd = mat_dag(&C), Dd = mat_dag(&D);
+        mat3 AB = mat_mul(&A, &B);
+        mat3 ABC = mat_mul(&AB, &Cd);
+        mat3 P = mat_mul(&ABC, &Dd);
+        acc += mat_retr(&P) / 3.0;
+      }
+    per_site[s] = acc;
+  }
+  double sum = 0.0;
+  for (int64_t s = 0; s < L.V; ++s) sum += per_site[s];
+  free(per_site);
+  return sum / (6.0 * (double)L.V);
+}
+
+/* eq. (4): U_mu(x) <- g(x) U_mu(x) g(x + mu)^dagger */
+int or_gauge_transform(double* U, const int32_t dims[4], const double* g) {
+  if (!U || !g || or_check_dims(dims) != 0) return -1;
+  lat_t L = make_lat(dims);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < L.V; ++s) {
+    mat3 gx = mat_from18(g + s * 18);
+    for (int mu = 0; mu < 4; ++mu) {
+      mat3 gn = mat_from18(g + neighbour(&L, s, mu, +1) * 18);
+      mat3 gnd = mat_dag(&gn);
+      mat3 A = get_link(U, s, mu);
+      mat3 B = mat_mul(&gx, &A);
+      mat3 C = mat_mul(&B, &gnd);
+      put_link(U, s, mu, &C);
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* driver: the while-theta loop of Alg. 1 with a check every check_every      */
+/* sweeps (Sec. 4.1 checks F_g and theta after every 100th iteration)        */
+/* ------------------------------------------------------------------------- */
+int or_fix(double* U, const int32_t dims[4], int gauge, double omega, double theta_target,
+           int32_t max_sweeps, int32_t check_every, int32_t reunit_at_check,
+           int32_t* sweeps_out, double* F_out, double* theta_out) {
+  if (!U || or_check_dims(dims) != 0 || check_every < 1 || max_sweeps < 0) return -1;
+  if (!(omega >= 1.0 && omega < 2.0)) return -1;
+  int64_t V = or_volume(dims);
+  int32_t sweeps = 0;
+  int converged = 0;
+  double F = 0.0, th = 0.0;
+  for (;;) {
+    if (sweeps > 0 && reunit_at_check) or_reunitarize(U, V * 4);
+    F = or_functional(U, dims, gauge, NULL);
+    th = or_theta_K(U, dims, gauge, NULL);
+    if (th < theta_target) { converged = 1; break; }
+    if (sweeps >= max_sweeps) break;
+    for (int32_t k = 0; k < check_every && sweeps < max_sweeps; ++k) {
+      or_sweep(U, dims, gauge, 0, omega);
+      or_sweep(U, dims, gauge, 1, omega);
+      ++sweeps;
+    }
+  }
+  if (sweeps_out) *sweeps_out = sweeps;
+  if (F_out) *F_out = F;
+  if (theta_out) *theta_out = th;
+  return converged ? 0 : 1;
+}
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

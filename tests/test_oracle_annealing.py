@@ -1,0 +1,152 @@
+"""Pins of the oracle's simulated-annealing pieces (heatbath + microcanonical).
+
+The annealing algorithm is not spelled out in the paper (it is named as a
+preconditioner in Sec. 1). The reading pinned here: weight exp(Re tr[g K]/T)
+per SU(2) subgroup, Kennedy-Pendleton sampling from Philox draws, and
+microcanonical reflections g = ghat^2.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+import inputs
+import oracle as O
+
+L, CLB = O.LANDAU, O.COULOMB
+
+
+def kp_cdf(alpha, x):
+    """CDF of the density ~ sqrt(1 - t^2) exp(alpha (t - 1)) on [-1, 1]."""
+    f = lambda t: math.sqrt(max(0.0, 1 - t * t)) * math.exp(alpha * (t - 1))
+    tot = integrate.quad(f, -1, 1, limit=200, points=[1 - 1e-3])[0]
+    return integrate.quad(f, -1, x, limit=200)[0] / tot
+
+
+@pytest.mark.parametrize("alpha", [0.5, 2.0, 10.0, 60.0])
+def test_kp_mean_and_histogram(alpha):
+    n = 20000
+    x = np.empty(n)
+    for k in range(n):
+        v, att = O.kp_draw(alpha, 1234, k, 7, 1)
+        assert att > 0
+        x[k] = v
+    # <X0> = I_2(alpha) / I_1(alpha) for density ~ sqrt(1 - x^2) exp(alpha x)
+    mean = special.iv(2, alpha) / special.iv(1, alpha)
+    assert abs(x.mean() - mean) < 5 * x.std() / math.sqrt(n)
+    # goodness of fit on 20 equiprobable-ish bins
+    qs = np.quantile(x, np.linspace(0, 1, 21))
+    qs[0], qs[-1] = -1.0, 1.0
+    cdf = np.array([kp_cdf(alpha, q) for q in qs])
+    expected = np.diff(cdf) * n
+    observed = np.histogram(x, bins=qs)[0]
+    chi2 = ((observed - expected) ** 2 / expected).sum()
+    assert stats.chi2.sf(chi2, df=19) > 1e-4
+
+
+def test_heatbath_su2_direction_isotropic():
+    n = 20000
+    X = np.array([O.heatbath_su2(3.0, 99, k, 1, 2)[0] for k in range(n)])
+    assert np.allclose(np.linalg.norm(X, axis=1), 1.0, atol=1e-14)
+    v = X[:, 1:]
+    se = 1.0 / math.sqrt(n)
+    assert np.all(np.abs(v.mean(axis=0)) < 5 * se)
+    m2 = (v ** 2).mean(axis=0)
+    want = (1 - (X[:, 0] ** 2).mean()) / 3
+    assert np.all(np.abs(m2 - want) < 0.05 * want)
+    # off-diagonal second moments vanish
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        assert abs((v[:, a] * v[:, b]).mean()) < 5 * se * math.sqrt(want)
+
+
+def test_draws_depend_on_every_counter_field():
+    base = O.heatbath_su2(2.0, 5, 10, 3, 1)[0]
+    for args in [(6, 10, 3, 1), (5, 11, 3, 1), (5, 10, 4, 1), (5, 10, 3, 2),
+                 ((1 << 32) + 5, 10, 3, 1)]:
+        assert not np.array_equal(O.heatbath_su2(2.0, *args)[0], base)
+    assert np.array_equal(O.heatbath_su2(2.0, 5, 10, 3, 1)[0], base)
+
+
+def test_lattice_heatbath_local_distribution():
+    """After a heatbath half-sweep, at each updated site the last subgroup
+    (1,2) has q'0/|q'| = X0 distributed with density ~ sqrt(1-x^2) exp(alpha x),
+    alpha = 2|q'|/T (|q'| = |q| since the update is unitary): the probability
+    integral transform must be uniform."""
+    dims = (8, 4, 4, 8)
+    U = inputs.config0(dims, 0.6, 31)
+    T = 0.9
+    O.heatbath_half(U, L, 0, T, seed=17, sweep=3)
+    nt, nz, ny, nx = dims
+    pit = []
+    for s in range(nt * nz * ny * nx):
+        x = s % nx
+        y = (s // nx) % ny
+        z = (s // (nx * ny)) % nz
+        t = s // (nx * ny * nz)
+        if (t + x + y + z) % 2:
+            continue
+        q = O.su2_part(O.local_K(U, L, s).conj().T, 1, 2)
+        nq = np.linalg.norm(q)
+        pit.append(kp_cdf(2 * nq / T, q[0] / nq))
+    assert len(pit) == 512
+    assert stats.kstest(pit, "uniform").pvalue > 1e-3
+
+
+@pytest.mark.parametrize("gauge", [L, CLB])
+def test_microcanonical_conserves_functional(gauge):
+    dims = (4, 4, 4, 4)
+    U = inputs.config0(dims, 0.6, 41)
+    F0 = O.functional(U, gauge)[1]
+    U0 = U.copy()
+    for p in (0, 1, 0, 1):
+        O.micro_half(U, gauge, p)
+    assert np.allclose(O.functional(U, gauge)[1], F0, rtol=0, atol=1e-14)
+    assert np.abs(U - U0).max() > 1e-2  # it does move the field
+    assert O.plaquette(U) == pytest.approx(O.plaquette(U0), abs=1e-13)
+
+
+def test_heatbath_cold_limit_is_relaxation():
+    """T -> 0: the heatbath draw concentrates on the local maximum (omega = 1)."""
+    dims = (4, 4, 4, 4)
+    U = inputs.config0(dims, 0.6, 42)
+    A, B = U.copy(), U.copy()
+    capped = O.heatbath_half(A, L, 0, 1e-9, seed=3, sweep=0)
+    O.sweep(B, L, 0, 1.0)
+    assert capped == 0
+    d = np.abs(A - B).max()
+    assert d < 1e-3 and d > 0
+
+
+def test_heatbath_hot_disorders_unit_field():
+    """A hot anneal drives the unit field (F = 1) far from the maximum."""
+    dims = (4, 4, 4, 4)
+    U = inputs.unit_field(dims)
+    capped = 0
+    for k in range(10):
+        capped += O.anneal_sweep(U, L, 4.0, seed=8, sweep=k, n_micro=1)
+    assert capped == 0
+    assert O.functional(U, L)[0] < 0.5
+    M = U.reshape(-1, 3, 3)
+    assert np.abs(M @ M.conj().transpose(0, 2, 1) - np.eye(3)).max() < 1e-13
+    assert O.plaquette(U) == pytest.approx(1.0, abs=1e-13)  # still pure gauge
+
+
+def test_anneal_resume_is_exact_and_seeded():
+    """Draws are keyed by the sweep index, so k sweeps then m more equal k + m."""
+    dims = (4, 2, 4, 2)
+    U0 = inputs.config0(dims, 0.6, 43)
+    A = U0.copy()
+    for k in range(4):
+        O.anneal_sweep(A, CLB, 1.0 - 0.2 * k, seed=5, sweep=k, n_micro=3)
+    B = U0.copy()
+    for k in range(2):
+        O.anneal_sweep(B, CLB, 1.0 - 0.2 * k, seed=5, sweep=k, n_micro=3)
+    B = B.copy()  # "checkpoint"
+    for k in range(2, 4):
+        O.anneal_sweep(B, CLB, 1.0 - 0.2 * k, seed=5, sweep=k, n_micro=3)
+    assert np.array_equal(A, B)
+    C = U0.copy()
+    for k in range(4):
+        O.anneal_sweep(C, CLB, 1.0 - 0.2 * k, seed=6, sweep=k, n_micro=3)
+    assert not np.array_equal(A, C)
