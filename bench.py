@@ -1,0 +1,251 @@
+"""Benchmark: Landau overrelaxation gauge fixing on one MI355X.
+
+Workload (default): a 32^4 SU(3) configuration from a quenched Wilson-action
+heatbath at beta = 6.0 (cold start, 300 sweeps, Philox seed 2), generated on
+the GPU before the timed region. One benchmark step is the whole hot path for
+that configuration: pack the canonical FP64 field into the FP32 12-real
+device layout, overrelaxation (omega = 1.7) with a check of F and theta every
+100 sweeps until theta < 1e-6, FP64 reunitarising conversion to the FP64
+12-real layout, FP64 sweeps until theta < 1e-14.
+
+value = site updates per second of the whole step (V x sweeps / step time).
+Also reported: the pure-FP64 time to theta < 1e-14 on the same input, the
+per-kernel rates of the four storage variants, the roofline of the dominant
+sweep kernel (HIP-event timings of its launches inside the timed region) and
+the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+FLOP_PER_SITE = 2253  # paper's count per site update (751 per SU(2) subgroup)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dims", type=str, default="32,32,32,32")
+    ap.add_argument("--beta", type=float, default=6.0)
+    ap.add_argument("--therm", type=int, default=300)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--omega", type=float, default=1.7)
+    ap.add_argument("--theta-switch", type=float, default=1e-6)
+    ap.add_argument("--theta-target", type=float, default=1e-14)
+    ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--max-sweeps", type=int, default=20000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP64-only comparison and the variant table")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1209_4008_amd as gf
+
+    dims = tuple(int(v) for v in args.dims.split(","))
+    V = int(np.prod(dims))
+    torch.cuda.set_device(0)
+    ctx = gf.Context(0)
+    stream = ctx.stream
+    log("device", torch.cuda.get_device_name(0), "lattice", dims)
+
+    # ---- input: heatbath configuration generated on the GPU (not timed) ----
+    t0 = time.time()
+    canon = inputs.gpu_heatbath(dims, args.beta, args.therm, args.seed, progress=100)
+    torch.cuda.synchronize()
+    log(f"heatbath input ready in {time.time() - t0:.1f} s")
+    g64c = gf.Geom.make(dims, gf.FP64, gf.R18)
+    P = ctx.empty_out(1)
+    tmp = ctx.empty_field(g64c)
+    ctx.pack(g64c, canon, tmp)
+    ctx.plaquette(tmp, g64c, P)
+    plaq = P.item()
+    del tmp
+    log(f"plaquette {plaq:.6f}")
+
+    glo = gf.Geom.make(dims, gf.FP32, gf.R12)
+    ghi = gf.Geom.make(dims, gf.FP64, gf.R12)
+    U_lo = ctx.empty_field(glo)
+    U_hi = ctx.empty_field(ghi)
+    params = gf.fix_params(omega=args.omega, theta_target=args.theta_target,
+                           theta_switch=args.theta_switch, max_sweeps=args.max_sweeps,
+                           check_every=args.check_every, flags=gf.FLAG_TIMING)
+
+    def step():
+        ctx.pack(glo, canon, U_lo)
+        return ctx.fix_mixed(U_lo, glo, U_hi, ghi, gf.LANDAU, params)
+
+    for k in range(args.warmup):
+        r = step()
+        log(f"warmup {k}: sweeps {r.sweeps} (fp32 {r.sweeps_lo}) theta {r.theta:.3e} "
+            f"wall {r.wall_ms:.1f} ms")
+    torch.cuda.synchronize()
+    results = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        results.append(step())
+        log(f"step {k}: sweeps {results[-1].sweeps} (fp32 {results[-1].sweeps_lo}) "
+            f"theta {results[-1].theta:.3e} F {results[-1].F:.12f}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+    sweeps = sum(r.sweeps for r in results)
+    value = V * sweeps / elapsed
+
+    # ---- dominant kernel: HIP-event timings of the sweep launches in the timed steps ----
+    kms = [sum(r.kernel_ms[i] for r in results) for i in range(4)]
+    kn = [sum(r.kernel_launches[i] for r in results) for i in range(4)]
+    bytes_per_site = {0: 16 * 12 * 4, 1: 16 * 12 * 8}  # FP32 R12, FP64 R12
+    dom = 0 if kms[0] >= kms[1] else 1
+    per_launch_bytes = (V // 2) * bytes_per_site[dom]
+    avg_ms = kms[dom] / max(kn[dom], 1)
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "kernel": "k_update_half<%s,R12,Landau,OR>" % ("float" if dom == 0 else "double"),
+                "avg_launch_us": round(avg_ms * 1e3, 2), "launches": kn[dom],
+                "bytes_per_launch": per_launch_bytes}
+
+    extras = {}
+    if not args.no_extras:
+        # pure FP64 (12 reals) on the same input, same cadence
+        gsave = ctx.empty_field(ghi)
+        ctx.pack(ghi, canon, gsave)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r64 = ctx.fix(gsave, ghi, gf.LANDAU, params)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        mixed = results[-1]
+        extras["fp64_only"] = {"time_ms": round(1e3 * t64, 2), "sweeps": r64.sweeps,
+                               "F": r64.F, "theta": r64.theta}
+        extras["mixed"] = {"time_ms": round(ms_per_step, 2), "sweeps": mixed.sweeps,
+                           "sweeps_fp32": mixed.sweeps_lo, "F": mixed.F, "theta": mixed.theta}
+        extras["mixed_speedup_vs_fp64"] = round(t64 / (ms_per_step * 1e-3), 4)
+        extras["final_F_rel_diff_mixed_vs_fp64"] = abs(mixed.F - r64.F) / abs(r64.F)
+        del gsave
+        # per-variant kernel rates: 100 sweeps each
+        var = {}
+        for prec, st in ((gf.FP32, gf.R12), (gf.FP32, gf.R18), (gf.FP64, gf.R12),
+                         (gf.FP64, gf.R18)):
+            g = gf.Geom.make(dims, prec, st)
+            f = ctx.empty_field(g)
+            ctx.pack(g, canon, f)
+            for _ in range(5):
+                ctx.sweep(f, g, gf.LANDAU, 0, args.omega)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            n = 100
+            e0.record(stream)
+            for k in range(n):
+                ctx.sweep(f, g, gf.LANDAU, 0, args.omega)
+                ctx.sweep(f, g, gf.LANDAU, 1, args.omega)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            sups = V * n / (ms * 1e-3)
+            gbs = sups * 16 * st * prec / 1e9
+            name = ("fp32" if prec == gf.FP32 else "fp64") + ("_r12" if st == gf.R12 else "_r18")
+            var[name] = {"site_updates_per_s": round(sups, 0), "gflops": round(sups * FLOP_PER_SITE / 1e9, 1),
+                         "GBps": round(gbs, 1), "frac_peak": round(gbs / PEAK_HBM_GBS, 4),
+                         "us_per_half_sweep": round(1e3 * ms / (2 * n), 2)}
+            del f
+        extras["variants"] = var
+        # plain copy of known size (calibrates achievable HBM bandwidth)
+        nbytes = 2 * 1024 ** 3
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        extras["copy_GBps"] = round(10 * 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        del a, b
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(canon, dims, args)
+
+    out = {
+        "metric": "Landau OR site-updates/s, HBM GB/s %peak; mixed vs FP64 time-to-theta<1e-14",
+        "value": round(value, 1),
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": "landau-gauge-fix %dx%dx%dx%d wilson-heatbath beta=%g (%d sweeps, seed %d), "
+                               "mixed fp32-r12 -> fp64-r12, omega=%g, theta<%g (switch %g)"
+                               % (dims + (args.beta, args.therm, args.seed, args.omega,
+                                          args.theta_target, args.theta_switch)),
+                   "lattice": list(dims), "beta": args.beta, "omega": args.omega,
+                   "check_every": args.check_every, "plaquette": round(plaq, 6),
+                   "sweeps_per_step": sweeps / args.steps,
+                   "gflops_2253": round(value * FLOP_PER_SITE / 1e9, 1)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    out.update(extras)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(canon, dims, args):
+    """The FP64 oracle, untuned, on the host cores: overrelaxation sweeps of the
+    same configuration, as many as fit in about args.cpu_seconds."""
+    import numpy as np
+
+    import oracle
+
+    U = canon.cpu().numpy().view(np.complex128).reshape(tuple(dims) + (4, 3, 3)).copy()
+    V = int(np.prod(dims))
+    threads = oracle.num_threads()
+    t0 = time.perf_counter()
+    oracle.sweep(U, oracle.LANDAU, 0, args.omega)
+    oracle.sweep(U, oracle.LANDAU, 1, args.omega)
+    one = time.perf_counter() - t0
+    n = max(1, int(args.cpu_seconds / max(one, 1e-6)) - 1)
+    t0 = time.perf_counter()
+    for _ in range(n):
+        oracle.sweep(U, oracle.LANDAU, 0, args.omega)
+        oracle.sweep(U, oracle.LANDAU, 1, args.omega)
+    dt = time.perf_counter() - t0
+    log(f"cpu oracle: {n} sweeps in {dt:.1f} s on {threads} threads")
+    return {"value": round(V * n / dt, 1), "unit": "site-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n} FP64 overrelaxation sweeps (omega {args.omega}) of the "
+                      f"{'x'.join(map(str, dims))} input, canonical 18-real layout"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * gf.h -- C ABI of libgf, an MI355X (gfx950) implementation of checkerboard
+ * overrelaxation gauge fixing with simulated-annealing preconditioning
+ * (Schroeck & Vogt, "Gauge fixing using overrelaxation and simulated
+ * annealing on GPUs", arXiv:1209.4008).
+ *
+ * Conventions used by every call
+ * ------------------------------
+ * Lattice: periodic, extents (nt, nz, ny, nx), each even and >= 2 (the
+ *   RED/BLACK decomposition of Sec. 2 needs even extents so that the sites of
+ *   one colour share no link), V = nt*nz*ny*nx <= 2^30. Direction mu = 0 is t,
+ *   mu = 1, 2, 3 are x, y, z. Canonical site index
+ *   s = ((t*nz + z)*ny + y)*nx + x; parity (t+x+y+z) mod 2, RED = 0.
+ * Canonical field (host or device, caller's choice where stated):
+ *   complex128 U[s][mu][a][b], i.e. 18 doubles per link, rows a, columns b.
+ * Device field (the layout every sweep works on, Sec. 4.1: the gauge field
+ *   is split into a RED and a BLACK block and the site index runs fastest):
+ *   complex elements of the precision `prec` (float2 or double2),
+ *     elem(p, mu, c, h) at offset ((p*4 + mu)*NC + c)*(V/2) + h,
+ *   p = parity, h = s >> 1 (the half index), c = 3a + b < NC,
+ *   NC = storage/2: 9 complex (18 reals) or 6 complex (12 reals: rows 0 and 1;
+ *   row 2 is rebuilt as conj(row0 x row1), Sec. 4.1). Size: gf_field_bytes().
+ * Gauge: GF_LANDAU uses mu = 0..3 in K(x), F and theta (eq. (3), (5), (7));
+ *   GF_COULOMB uses the spatial mu = 1..3 and reports F and theta per
+ *   timeslice (arrays of nt doubles). In both gauges each site
+ *   transformation is applied to all 8 links at the site, so the result is a
+ *   gauge transform of the input.
+ *
+ * Memory and streams: every pointer passed to a compute call is device memory
+ * owned by the caller; the library never frees it. Calls enqueue work on the
+ * context stream and return without waiting, except gf_fix, gf_fix_mixed,
+ * gf_batch_run and the *_host helpers, which synchronise that stream.
+ * A context is used by one host thread at a time.
+ *
+ * Errors: every call returns a gf_status. Arguments are validated on the host
+ * before anything is enqueued, so a call that returns an error has not
+ * touched device memory. gf_last_error() holds a message for the last failure
+ * on a context.
+ */
+#ifndef GF_H
+#define GF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gf_status;
+#define GF_OK 0
+#define GF_NOT_CONVERGED 1     /* driver stopped at max_sweeps (information) */
+#define GF_ERR_ARG (-1)        /* invalid argument (nothing enqueued)        */
+#define GF_ERR_UNSUPPORTED (-2)
+#define GF_ERR_DEVICE (-3)     /* no usable GPU                              */
+#define GF_ERR_HIP (-4)        /* HIP runtime error                          */
+#define GF_ERR_NONFINITE (-5)  /* F or theta became NaN or Inf               */
+#define GF_ERR_NOMEM (-6)
+
+#define GF_LANDAU 0
+#define GF_COULOMB 1
+#define GF_FP32 4
+#define GF_FP64 8
+#define GF_R12 12
+#define GF_R18 18
+
+typedef struct {
+  int32_t nt, nz, ny, nx; /* even, >= 2 */
+  int32_t prec;           /* GF_FP32 | GF_FP64 */
+  int32_t storage;        /* GF_R12 | GF_R18   */
+} gf_geom;
+
+typedef struct gf_ctx gf_ctx;
+
+/* ---- context and host-only helpers -------------------------------------- */
+/* Create a context on `device` enqueuing on `hip_stream` (a hipStream_t; NULL
+ * = the default stream). Fails with GF_ERR_DEVICE when no GPU is present. */
+gf_status gf_create(int device, void* hip_stream, gf_ctx** out);
+gf_status gf_destroy(gf_ctx* ctx);
+/* Message for the last failure on ctx, or for the last failed gf_create when
+ * ctx is NULL. Never NULL. */
+const char* gf_last_error(const gf_ctx* ctx);
+/* Host-only: GF_OK if geom is valid, GF_ERR_ARG otherwise. */
+gf_status gf_check_geom(const gf_geom* geom);
+/* Host-only: bytes of a device field, 4 V storage prec; 0 if geom invalid. */
+size_t gf_field_bytes(const gf_geom* geom);
+/* Host-only: runs the library's host-side self checks (index arithmetic);
+ * GF_OK when they pass. */
+gf_status gf_selftest_host(void);
+/* Library version string. */
+const char* gf_version(void);
+
+/* ---- layout (Sec. 4.1: RED/BLACK blocks, site index fastest, 12 reals) --- */
+/* Canonical FP64 field in device memory -> device field of geom's precision
+ * and storage (rounded to nearest for FP32; row 2 dropped for R12). */
+gf_status gf_pack(gf_ctx* ctx, const gf_geom* geom, const double* U_canon_dev, void* U_dev);
+/* Device field -> canonical FP64 field in device memory (row 2 rebuilt in
+ * FP64 for R12). */
+gf_status gf_unpack(gf_ctx* ctx, const gf_geom* geom, const void* U_dev, double* U_canon_dev);
+/* Device field -> device field of another precision/storage (same extents).
+ * With reunitarize != 0 each link is projected onto SU(3) by Gram-Schmidt in
+ * FP64 on the way. Source and destination must not overlap. */
+gf_status gf_convert(gf_ctx* ctx, const gf_geom* src, const void* U_src, const gf_geom* dst,
+                     void* U_dst, int32_t reunitarize);
+
+/* ---- the hot path ----------------------------------------------------------- */
+/* One checkerboard half-sweep of overrelaxation (Alg. 1) over the sites of
+ * `parity`: per site, K(x) of eq. (5) from its 8 links, then for the SU(2)
+ * subgroups (0,1), (0,2), (1,2) in turn the local maximum of eq. (6) raised to
+ * the power omega (Sec. 2; the 19-flop form s = (c r0, b c r) with
+ * b = (omega r0^2 + |r|^2)/(r0^2 + |r|^2), c = (r0^2 + b^2 |r|^2)^(-1/2)),
+ * and the product transformation applied to the 8 links in place.
+ * omega in [1, 2) (1 = plain relaxation); otherwise GF_ERR_ARG. */
+gf_status gf_sweep(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gauge, int32_t parity,
+                   double omega);
+/* Gauge functional eq. (3), normalised so that the unit field gives 1:
+ * F = Re sum_{x, mu in D} tr U_mu(x) / (3 |D| V) (Landau, F_dev[0]) or per
+ * timeslice / (9 V_s) (Coulomb, F_dev[0..nt-1]). Accumulated in FP64. */
+gf_status gf_functional(gf_ctx* ctx, const void* U, const gf_geom* geom, int32_t gauge,
+                        double* F_dev);
+/* Precision theta of eq. (7): theta = sum_x tr[Delta(x) Delta(x)^dag] / (3 V)
+ * with Delta(x) = sum_{mu in D} [A_mu(x) - A_mu(x - mu)], A_mu the traceless
+ * part of (U_mu - U_mu^dag)/(2i) (theta_dev[0], Landau) or per timeslice with
+ * V -> V_s (Coulomb, theta_dev[0..nt-1]). Accumulated in FP64. */
+gf_status gf_theta(gf_ctx* ctx, const void* U, const gf_geom* geom, int32_t gauge,
+                   double* theta_dev);
+/* F and theta in one pass over the field (what the drivers use). */
+gf_status gf_measure(gf_ctx* ctx, const void* U, const gf_geom* geom, int32_t gauge,
+                     double* F_dev, double* theta_dev);
+/* Project every link onto SU(3) by Gram-Schmidt in FP64 (rows 0, 1
+ * orthonormalised; row 2 = conj(row0 x row1) for R18). */
+gf_status gf_reunitarize(gf_ctx* ctx, void* U, const gf_geom* geom);
+/* Average plaquette (1/(6V)) sum Re tr U_P / 3, in FP64 (support: gauge
+ * invariant, so unchanged by every sweep). */
+gf_status gf_plaquette(gf_ctx* ctx, const void* U, const gf_geom* geom, double* P_dev);
+
+/* ---- simulated annealing (Sec. 1: preconditioner) ------------------------- */
+/* Heatbath half-sweep at temperature T > 0: per site and subgroup the SU(2)
+ * transformation is drawn with weight exp(Re tr[g K(x)] / T) (Kennedy-
+ * Pendleton, Philox4x32-10 keyed by seed, counter (site, sweep, tag,
+ * attempt); up to 1024 attempts, after which the subgroup is left unchanged). */
+gf_status gf_heatbath_half(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gauge,
+                           int32_t parity, double T, uint64_t seed, uint64_t sweep);
+/* Microcanonical half-sweep: g = (local maximum)^2, Re tr[g K] unchanged. */
+gf_status gf_micro_half(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gauge,
+                        int32_t parity);
+/* One annealing step: heatbath RED and BLACK at T, then n_micro
+ * microcanonical sweeps (RED, BLACK each). */
+gf_status gf_anneal_sweep(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gauge, double T,
+                          uint64_t seed, uint64_t sweep, int32_t n_micro);
+/* Philox4x32-10 of n counters (4 x u32 each, device) with key (seed low,
+ * seed high), into out (4 x u32 each, device). Support: the same generator
+ * the heatbath uses. */
+gf_status gf_philox(gf_ctx* ctx, const uint32_t* ctr_dev, uint64_t seed, uint32_t* out_dev,
+                    int64_t n);
+
+/* ---- drivers (the while-theta loop of Alg. 1) ------------------------------- */
+#define GF_FLAG_TIMING 1u    /* record hipEvent kernel timings into the result */
+#define GF_FLAG_GRAPH 2u     /* replay the sweeps between checks as a hipGraph */
+
+typedef struct {
+  double omega;            /* overrelaxation parameter, [1, 2)                         */
+  double theta_target;     /* stop when theta (Coulomb: max over t) < theta_target     */
+  double theta_switch;     /* gf_fix_mixed: leave the FP32 phase when theta < this     */
+  int32_t max_sweeps;      /* per phase                                                */
+  int32_t check_every;     /* sweeps between checks (Sec. 4.1 uses 100)                */
+  int32_t reunit_at_check; /* reunitarise before every check after the first           */
+  uint32_t flags;          /* GF_FLAG_*                                                */
+} gf_fix_params;
+
+typedef struct {
+  int32_t status;          /* GF_OK or GF_NOT_CONVERGED (or the error)           */
+  int32_t sweeps;          /* total sweeps (RED + BLACK = 1 sweep)               */
+  int32_t sweeps_lo;       /* gf_fix_mixed: sweeps of the FP32 phase              */
+  int32_t checks;          /* number of F/theta evaluations                       */
+  double F, theta;         /* at the last check (Coulomb: mean F, max theta)      */
+  double theta_at_switch;  /* gf_fix_mixed: theta when the FP32 phase ended        */
+  double wall_ms;          /* host wall time of the call                          */
+  /* GF_FLAG_TIMING: kernel time (ms) and launches: [0] FP32 sweeps, [1] FP64
+   * sweeps, [2] measurement, [3] reunitarisation and conversion */
+  double kernel_ms[4];
+  int64_t kernel_launches[4];
+} gf_fix_result;
+
+/* Sweeps U (in geom's precision) with a check (reunitarise, F, theta)
+ * before the first sweep and every check_every sweeps until theta <
+ * theta_target or max_sweeps. Synchronises the context stream. */
+gf_status gf_fix(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gauge,
+                 const gf_fix_params* params, gf_fix_result* result);
+/* Mixed precision: sweeps U_lo (FP32) until theta < theta_switch, converts it
+ * into U_hi (FP64) with FP64 Gram-Schmidt, then sweeps U_hi until
+ * theta < theta_target. U_lo holds the input and is overwritten. */
+gf_status gf_fix_mixed(gf_ctx* ctx, void* U_lo, const gf_geom* geom_lo, void* U_hi,
+                       const gf_geom* geom_hi, int32_t gauge, const gf_fix_params* params,
+                       gf_fix_result* result);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GF_H */

@@ -38,6 +38,7 @@ def lib():
             "or_overrelax": (C.c_int, [d, C.c_double, d]),
             "or_local_K": (None, [d, i32p, C.c_int, C.c_int64, d]),
             "or_sweep": (C.c_int, [d, i32p, C.c_int, C.c_int, C.c_double]),
+            "or_update_sites": (C.c_int, [d, i32p, C.c_int, C.c_double, i64p, C.c_int64]),
             "or_functional": (C.c_double, [d, i32p, C.c_int, d]),
             "or_functional_raw": (C.c_double, [d, i32p, C.c_int]),
             "or_theta_A": (C.c_double, [d, i32p, C.c_int, d]),
@@ -121,6 +122,14 @@ def sweep(U, gauge, parity, omega):
     rc = lib().or_sweep(_field(U), _dims(dims_of(U)), int(gauge), int(parity), float(omega))
     if rc != 0:
         raise ValueError("or_sweep: bad arguments")
+
+
+def update_sites(U, gauge, omega, sites):
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    rc = lib().or_update_sites(_field(U), _dims(dims_of(U)), int(gauge), float(omega),
+                               sites.ctypes.data_as(C.POINTER(C.c_int64)), int(sites.size))
+    if rc != 0:
+        raise ValueError("or_update_sites: bad arguments")
 
 
 def functional(U, gauge):

@@ -59,6 +59,9 @@ void or_local_K(const double* U, const int32_t dims[4], int gauge, int64_t s, do
 /* One checkerboard half-sweep of overrelaxation over the sites of one parity
  * (Alg. 1; omega = 1 is plain relaxation). */
 int  or_sweep(double* U, const int32_t dims[4], int gauge, int parity, double omega);
+/* The same update on a list of sites of one parity only (sampled checks). */
+int  or_update_sites(double* U, const int32_t dims[4], int gauge, double omega,
+                     const int64_t* sites, int64_t n);
 /* Gauge functional eq. (3), normalised so that U = 1 gives 1. out[0] (Landau)
  * or out[t], t < nt (Coulomb). Returns the Landau value or the mean over t. */
 double or_functional(const double* U, const int32_t dims[4], int gauge, double* out);

@@ -430,6 +430,23 @@ static int half_sweep(double* U, const int32_t dims[4], int gauge, int parity, c
   return 0;
 }
 
+/* Overrelaxation update of the listed sites only, each as in a half-sweep
+ * (all listed sites must have the same parity, so that none shares a link).
+ * Used to check large lattices on a sample of sites. */
+int or_update_sites(double* U, const int32_t dims[4], int gauge, double omega,
+                    const int64_t* sites, int64_t n) {
+  if (!U || !sites || or_check_dims(dims) != 0 || !(omega >= 1.0 && omega < 2.0)) return -1;
+  lat_t L = make_lat(dims);
+  if (n <= 0) return 0;
+  int p0 = site_parity(&L, sites[0]);
+  for (int64_t k = 0; k < n; ++k)
+    if (sites[k] < 0 || sites[k] >= L.V || site_parity(&L, sites[k]) != p0) return -1;
+  upd_t u = {UPD_OR, omega, 0.0, 0, 0};
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n; ++k) site_update(U, &L, gauge, sites[k], &u);
+  return 0;
+}
+
 int or_sweep(double* U, const int32_t dims[4], int gauge, int parity, double omega) {
   if (!(omega >= 1.0 && omega < 2.0)) return -1; /* Sec. 2: omega in [1, 2) */
   upd_t u = {UPD_OR, omega, 0.0, 0, 0};

@@ -1,0 +1,237 @@
+"""Python binding of libgf (MI355X checkerboard overrelaxation gauge fixing).
+
+Argument marshalling only: every step runs in the HIP kernels of libgf.so,
+called through its C ABI (include/gf.h). PyTorch is used for device memory and
+streams. There is no fallback: if libgf.so is missing or no GPU is present,
+the calls raise.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgf.so")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_ARG, ERR_UNSUPPORTED, ERR_DEVICE, ERR_HIP, ERR_NONFINITE, ERR_NOMEM = -1, -2, -3, -4, -5, -6
+LANDAU, COULOMB = 0, 1
+FP32, FP64 = 4, 8
+R12, R18 = 12, 18
+FLAG_TIMING, FLAG_GRAPH = 1, 2
+
+
+class GFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libgf status {status}: {msg}")
+        self.status = status
+
+
+class Geom(C.Structure):
+    _fields_ = [("nt", C.c_int32), ("nz", C.c_int32), ("ny", C.c_int32), ("nx", C.c_int32),
+                ("prec", C.c_int32), ("storage", C.c_int32)]
+
+    @classmethod
+    def make(cls, dims, prec=FP64, storage=R18):
+        nt, nz, ny, nx = (int(v) for v in dims)
+        return cls(nt, nz, ny, nx, int(prec), int(storage))
+
+    @property
+    def dims(self):
+        return (self.nt, self.nz, self.ny, self.nx)
+
+    @property
+    def volume(self):
+        return self.nt * self.nz * self.ny * self.nx
+
+
+class FixParams(C.Structure):
+    _fields_ = [("omega", C.c_double), ("theta_target", C.c_double),
+                ("theta_switch", C.c_double), ("max_sweeps", C.c_int32),
+                ("check_every", C.c_int32), ("reunit_at_check", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class FixResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("sweeps", C.c_int32), ("sweeps_lo", C.c_int32),
+                ("checks", C.c_int32), ("F", C.c_double), ("theta", C.c_double),
+                ("theta_at_switch", C.c_double), ("wall_ms", C.c_double),
+                ("kernel_ms", C.c_double * 4), ("kernel_launches", C.c_int64 * 4)]
+
+    def as_dict(self):
+        return {"status": self.status, "sweeps": self.sweeps, "sweeps_lo": self.sweeps_lo,
+                "checks": self.checks, "F": self.F, "theta": self.theta,
+                "theta_at_switch": self.theta_at_switch, "wall_ms": self.wall_ms,
+                "kernel_ms": list(self.kernel_ms),
+                "kernel_launches": list(self.kernel_launches)}
+
+
+# every symbol of include/gf.h with its ctypes signature
+_vp, _gp, _dp = C.c_void_p, C.POINTER(Geom), C.c_void_p
+SIGNATURES = {
+    "gf_create": (C.c_int32, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "gf_destroy": (C.c_int32, [_vp]),
+    "gf_last_error": (C.c_char_p, [_vp]),
+    "gf_check_geom": (C.c_int32, [_gp]),
+    "gf_field_bytes": (C.c_size_t, [_gp]),
+    "gf_selftest_host": (C.c_int32, []),
+    "gf_version": (C.c_char_p, []),
+    "gf_pack": (C.c_int32, [_vp, _gp, _dp, _dp]),
+    "gf_unpack": (C.c_int32, [_vp, _gp, _dp, _dp]),
+    "gf_convert": (C.c_int32, [_vp, _gp, _dp, _gp, _dp, C.c_int32]),
+    "gf_sweep": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.c_int32, C.c_double]),
+    "gf_functional": (C.c_int32, [_vp, _dp, _gp, C.c_int32, _dp]),
+    "gf_theta": (C.c_int32, [_vp, _dp, _gp, C.c_int32, _dp]),
+    "gf_measure": (C.c_int32, [_vp, _dp, _gp, C.c_int32, _dp, _dp]),
+    "gf_reunitarize": (C.c_int32, [_vp, _dp, _gp]),
+    "gf_plaquette": (C.c_int32, [_vp, _dp, _gp, _dp]),
+    "gf_heatbath_half": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.c_int32, C.c_double,
+                                     C.c_uint64, C.c_uint64]),
+    "gf_micro_half": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.c_int32]),
+    "gf_anneal_sweep": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.c_double, C.c_uint64,
+                                    C.c_uint64, C.c_int32]),
+    "gf_philox": (C.c_int32, [_vp, _dp, C.c_uint64, _dp, C.c_int64]),
+    "gf_fix": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.POINTER(FixParams),
+                           C.POINTER(FixResult)]),
+    "gf_fix_mixed": (C.c_int32, [_vp, _dp, _gp, _dp, _gp, C.c_int32, C.POINTER(FixParams),
+                                 C.POINTER(FixResult)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libgf.so (built by __graft_entry__.build() / paper_1209_4008_amd/build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1209_4008_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def field_bytes(geom):
+    return int(lib().gf_field_bytes(C.byref(geom)))
+
+
+def check_geom(geom):
+    return int(lib().gf_check_geom(C.byref(geom)))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A libgf context on the current CUDA(HIP) device and torch stream."""
+
+    def __init__(self, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise GFError(ERR_DEVICE, "no GPU available (libgf has no CPU path)")
+        self.torch = torch
+        if device is None:
+            device = torch.cuda.current_device()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = lib().gf_create(int(device), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != OK:
+            raise GFError(st, lib().gf_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow=(OK,)):
+        if st not in allow:
+            raise GFError(st, lib().gf_last_error(self.h).decode())
+        return st
+
+    # ---- memory helpers (torch as allocator) -------------------------------
+    def empty_field(self, geom):
+        n = field_bytes(geom)
+        if n == 0:
+            raise GFError(ERR_ARG, "invalid geometry")
+        return self.torch.empty(n, dtype=self.torch.uint8, device="cuda")
+
+    def empty_out(self, n):
+        return self.torch.zeros(n, dtype=self.torch.float64, device="cuda")
+
+    # ---- C ABI calls --------------------------------------------------------
+    def pack(self, geom, U_canon, U):
+        return self._check(lib().gf_pack(self.h, C.byref(geom), _ptr(U_canon), _ptr(U)))
+
+    def unpack(self, geom, U, U_canon):
+        return self._check(lib().gf_unpack(self.h, C.byref(geom), _ptr(U), _ptr(U_canon)))
+
+    def convert(self, gsrc, Usrc, gdst, Udst, reunitarize=True):
+        return self._check(lib().gf_convert(self.h, C.byref(gsrc), _ptr(Usrc), C.byref(gdst),
+                                            _ptr(Udst), int(bool(reunitarize))))
+
+    def sweep(self, U, geom, gauge, parity, omega):
+        return self._check(lib().gf_sweep(self.h, _ptr(U), C.byref(geom), int(gauge),
+                                          int(parity), float(omega)))
+
+    def measure(self, U, geom, gauge, F=None, theta=None):
+        return self._check(lib().gf_measure(self.h, _ptr(U), C.byref(geom), int(gauge),
+                                            _ptr(F), _ptr(theta)))
+
+    def functional(self, U, geom, gauge, F):
+        return self._check(lib().gf_functional(self.h, _ptr(U), C.byref(geom), int(gauge),
+                                               _ptr(F)))
+
+    def theta(self, U, geom, gauge, th):
+        return self._check(lib().gf_theta(self.h, _ptr(U), C.byref(geom), int(gauge), _ptr(th)))
+
+    def reunitarize(self, U, geom):
+        return self._check(lib().gf_reunitarize(self.h, _ptr(U), C.byref(geom)))
+
+    def plaquette(self, U, geom, P):
+        return self._check(lib().gf_plaquette(self.h, _ptr(U), C.byref(geom), _ptr(P)))
+
+    def heatbath_half(self, U, geom, gauge, parity, T, seed, sweep):
+        return self._check(lib().gf_heatbath_half(self.h, _ptr(U), C.byref(geom), int(gauge),
+                                                  int(parity), float(T), int(seed), int(sweep)))
+
+    def micro_half(self, U, geom, gauge, parity):
+        return self._check(lib().gf_micro_half(self.h, _ptr(U), C.byref(geom), int(gauge),
+                                               int(parity)))
+
+    def anneal_sweep(self, U, geom, gauge, T, seed, sweep, n_micro):
+        return self._check(lib().gf_anneal_sweep(self.h, _ptr(U), C.byref(geom), int(gauge),
+                                                 float(T), int(seed), int(sweep), int(n_micro)))
+
+    def philox(self, ctr, seed, out, n):
+        return self._check(lib().gf_philox(self.h, _ptr(ctr), int(seed), _ptr(out), int(n)))
+
+    def fix(self, U, geom, gauge, params):
+        r = FixResult()
+        self._check(lib().gf_fix(self.h, _ptr(U), C.byref(geom), int(gauge), C.byref(params),
+                                 C.byref(r)), allow=(OK, NOT_CONVERGED))
+        return r
+
+    def fix_mixed(self, U_lo, geom_lo, U_hi, geom_hi, gauge, params):
+        r = FixResult()
+        self._check(lib().gf_fix_mixed(self.h, _ptr(U_lo), C.byref(geom_lo), _ptr(U_hi),
+                                       C.byref(geom_hi), int(gauge), C.byref(params),
+                                       C.byref(r)), allow=(OK, NOT_CONVERGED))
+        return r
+
+
+def fix_params(omega=1.7, theta_target=1e-14, theta_switch=1e-6, max_sweeps=20000,
+               check_every=100, reunit_at_check=1, flags=0):
+    return FixParams(float(omega), float(theta_target), float(theta_switch), int(max_sweeps),
+                     int(check_every), int(reunit_at_check), int(flags))

@@ -1,0 +1,644 @@
+// gf_api.hip -- host side of libgf: context, argument validation, kernel
+// dispatch over (precision, storage, gauge) and the gauge-fixing drivers.
+// The C ABI is declared in include/gf.h.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/gf.h"
+#include "gf_kernels.hpp"
+
+using namespace gf;
+
+struct gf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char err[512] = {0};
+  double* partial = nullptr;  // per-block reduction partials
+  size_t partial_cap = 0;     // doubles
+  double* dev_out = nullptr;  // driver F/theta outputs (2 x out_cap doubles)
+  double* host_out = nullptr; // pinned copy of dev_out
+  size_t out_cap = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+static char g_create_err[512] = "no error";
+
+static gf_status fail(gf_ctx* c, gf_status st, const char* fmt, ...) {
+  char* dst = c ? c->err : g_create_err;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(dst, 512, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+#define HIP_OR_FAIL(ctx, expr)                                                       \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail((ctx), GF_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                               \
+  } while (0)
+
+static gf_status launch_check(gf_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, GF_ERR_HIP, "%s: launch failed: %s", what, hipGetErrorString(e));
+  return GF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+static FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  uint32_t l = 0;
+  while (((uint64_t)1 << l) < d) ++l;
+  f.d = d;
+  f.shift = 32 + l;
+  // m = ceil(2^(32+l) / d)
+  const unsigned __int128 num = (unsigned __int128)1 << (32 + l);
+  f.m = (uint64_t)((num + d - 1) / d);
+  return f;
+}
+
+static uint32_t host_fdiv(uint32_t n, const FastDiv& f) {
+  return (uint32_t)(((unsigned __int128)n * f.m) >> f.shift);
+}
+
+static int geom_ok(const gf_geom* g) {
+  if (!g) return 0;
+  const int32_t e[4] = {g->nt, g->nz, g->ny, g->nx};
+  for (int k = 0; k < 4; ++k)
+    if (e[k] < 2 || (e[k] & 1) || e[k] > 65536) return 0;
+  if (g->prec != GF_FP32 && g->prec != GF_FP64) return 0;
+  if (g->storage != GF_R12 && g->storage != GF_R18) return 0;
+  const uint64_t V = (uint64_t)g->nt * g->nz * g->ny * g->nx;
+  if (V > ((uint64_t)1 << 30)) return 0;
+  return 1;
+}
+
+static Lat make_lat(const gf_geom* g) {
+  Lat L;
+  L.nt = g->nt;
+  L.nz = g->nz;
+  L.ny = g->ny;
+  L.nx = g->nx;
+  L.hx = g->nx / 2;
+  L.vh = (uint32_t)((uint64_t)g->nt * g->nz * g->ny * g->nx / 2);
+  L.sy = L.hx;
+  L.sz = L.ny * L.hx;
+  L.st = L.nz * L.ny * L.hx;
+  L.div_hx = make_fastdiv(L.hx);
+  L.div_ny = make_fastdiv(L.ny);
+  L.div_nz = make_fastdiv(L.nz);
+  return L;
+}
+
+static int same_extents(const gf_geom* a, const gf_geom* b) {
+  return a->nt == b->nt && a->nz == b->nz && a->ny == b->ny && a->nx == b->nx;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch helpers
+// ---------------------------------------------------------------------------
+template <class F>
+static void with_type(const gf_geom* g, F&& f) {
+  if (g->prec == GF_FP32) {
+    if (g->storage == GF_R12)
+      f.template operator()<float, 6>();
+    else
+      f.template operator()<float, 9>();
+  } else {
+    if (g->storage == GF_R12)
+      f.template operator()<double, 6>();
+    else
+      f.template operator()<double, 9>();
+  }
+}
+
+static unsigned blocks_for(uint64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+static gf_status ensure_partial(gf_ctx* c, size_t n_doubles) {
+  if (n_doubles <= c->partial_cap) return GF_OK;
+  if (c->partial) HIP_OR_FAIL(c, hipFree(c->partial));
+  c->partial = nullptr;
+  c->partial_cap = 0;
+  HIP_OR_FAIL(c, hipMalloc(&c->partial, n_doubles * sizeof(double)));
+  c->partial_cap = n_doubles;
+  return GF_OK;
+}
+
+static gf_status ensure_out(gf_ctx* c, size_t n) {
+  if (n <= c->out_cap) return GF_OK;
+  if (c->dev_out) HIP_OR_FAIL(c, hipFree(c->dev_out));
+  if (c->host_out) HIP_OR_FAIL(c, hipHostFree(c->host_out));
+  c->dev_out = nullptr;
+  c->host_out = nullptr;
+  c->out_cap = 0;
+  HIP_OR_FAIL(c, hipMalloc(&c->dev_out, 2 * n * sizeof(double)));
+  HIP_OR_FAIL(c, hipHostMalloc(&c->host_out, 2 * n * sizeof(double), hipHostMallocDefault));
+  c->out_cap = n;
+  return GF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI (C linkage comes from the declarations in gf.h)
+// ---------------------------------------------------------------------------
+
+const char* gf_version(void) { return "libgf 0.1 (gfx950)"; }
+
+gf_status gf_check_geom(const gf_geom* geom) { return geom_ok(geom) ? GF_OK : GF_ERR_ARG; }
+
+size_t gf_field_bytes(const gf_geom* geom) {
+  if (!geom_ok(geom)) return 0;
+  const uint64_t V = (uint64_t)geom->nt * geom->nz * geom->ny * geom->nx;
+  return (size_t)(4 * V * (uint64_t)geom->storage * (uint64_t)geom->prec);
+}
+
+// The device index arithmetic (site_of, back_h, fwd_h) run on the host for
+// every site of a set of lattices, against the canonical definition
+// s = ((t*nz + z)*ny + y)*nx + x, parity (t+x+y+z) mod 2, h = s >> 1.
+static int selftest_lattice(int nt, int nz, int ny, int nx) {
+  gf_geom g = {nt, nz, ny, nx, GF_FP64, GF_R18};
+  const Lat L = make_lat(&g);
+  auto canon = [&](int64_t t, int64_t z, int64_t y, int64_t x) {
+    return ((t * nz + z) * ny + y) * nx + x;
+  };
+  for (int p = 0; p < 2; ++p)
+    for (uint32_t h = 0; h < L.vh; ++h) {
+      const Site S = site_of(L, h, p);
+      if (S.t >= (uint32_t)nt || S.z >= (uint32_t)nz || S.y >= (uint32_t)ny || S.x >= (uint32_t)nx)
+        return 0;
+      const int64_t s = canon(S.t, S.z, S.y, S.x);
+      if ((s >> 1) != h || (int)((S.t + S.z + S.y + S.x) & 1) != p || S.xodd != (S.x & 1)) return 0;
+      const int64_t c[4] = {S.t, S.x, S.y, S.z};
+      const int64_t e[4] = {nt, nx, ny, nz};
+      for (int mu = 0; mu < 4; ++mu) {
+        int64_t b[4] = {c[0], c[1], c[2], c[3]}, f[4] = {c[0], c[1], c[2], c[3]};
+        b[mu] = (b[mu] - 1 + e[mu]) % e[mu];
+        f[mu] = (f[mu] + 1) % e[mu];
+        const uint32_t hb = back_h(L, h, S, mu), hf = fwd_h(L, h, S, mu);
+        if (hb >= L.vh || hf >= L.vh) return 0;
+        if ((uint64_t)(canon(b[0], b[3], b[2], b[1]) >> 1) != hb) return 0;
+        if ((uint64_t)(canon(f[0], f[3], f[2], f[1]) >> 1) != hf) return 0;
+      }
+    }
+  return 1;
+}
+
+gf_status gf_selftest_host(void) {
+  // exact division for the divisors the geometry can produce
+  for (uint32_t d = 1; d <= 4096; d = d < 64 ? d + 1 : d + 37) {
+    const FastDiv f = make_fastdiv(d);
+    const uint32_t probes[] = {0u, 1u, d - 1, d, d + 1, 2 * d - 1, 1000003u, 0x7ffffffeu,
+                               0x7fffffffu, 123456789u};
+    for (uint32_t n : probes)
+      if (host_fdiv(n, f) != n / d || fdiv(n, f) != n / d) return GF_ERR_UNSUPPORTED;
+    for (uint32_t n = 0; n < 5000; ++n)
+      if (fdiv(n * 7919u, f) != (n * 7919u) / d) return GF_ERR_UNSUPPORTED;
+  }
+  const int shapes[][4] = {{2, 2, 2, 2}, {4, 4, 4, 4}, {6, 4, 2, 10}, {4, 6, 8, 10},
+                           {8, 2, 6, 4}, {2, 12, 2, 14}, {10, 6, 4, 2}, {24, 12, 12, 12}};
+  for (const auto& d : shapes)
+    if (!selftest_lattice(d[0], d[1], d[2], d[3])) return GF_ERR_UNSUPPORTED;
+  return GF_OK;
+}
+
+const char* gf_last_error(const gf_ctx* ctx) { return ctx ? ctx->err : g_create_err; }
+
+gf_status gf_create(int device, void* hip_stream, gf_ctx** out) {
+  if (!out) return fail(nullptr, GF_ERR_ARG, "gf_create: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0)
+    return fail(nullptr, GF_ERR_DEVICE, "gf_create: no GPU device available");
+  if (device < 0 || device >= n)
+    return fail(nullptr, GF_ERR_ARG, "gf_create: device %d out of range (%d devices)", device, n);
+  if (hipSetDevice(device) != hipSuccess)
+    return fail(nullptr, GF_ERR_DEVICE, "gf_create: hipSetDevice(%d) failed", device);
+  gf_ctx* c = new gf_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+    delete c;
+    return fail(nullptr, GF_ERR_HIP, "gf_create: hipEventCreate failed");
+  }
+  snprintf(c->err, sizeof c->err, "no error");
+  *out = c;
+  return GF_OK;
+}
+
+gf_status gf_destroy(gf_ctx* c) {
+  if (!c) return GF_ERR_ARG;
+  (void)hipSetDevice(c->device);
+  if (c->partial) (void)hipFree(c->partial);
+  if (c->dev_out) (void)hipFree(c->dev_out);
+  if (c->host_out) (void)hipHostFree(c->host_out);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+  return GF_OK;
+}
+
+#define CHECK_CTX(c)                                                    \
+  do {                                                                  \
+    if (!(c)) return GF_ERR_ARG;                                        \
+    if (hipSetDevice((c)->device) != hipSuccess)                        \
+      return fail((c), GF_ERR_DEVICE, "hipSetDevice(%d) failed", (c)->device); \
+  } while (0)
+
+#define CHECK_GEOM(c, g, what) \
+  if (!geom_ok(g)) return fail((c), GF_ERR_ARG, "%s: invalid geometry", what)
+
+gf_status gf_pack(gf_ctx* c, const gf_geom* g, const double* src, void* dst) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_pack");
+  if (!src || !dst) return fail(c, GF_ERR_ARG, "gf_pack: NULL pointer");
+  const Lat L = make_lat(g);
+  with_type(g, [&]<typename T, int NC>() {
+    hipLaunchKernelGGL((k_pack<T, NC>), dim3(blocks_for(2ull * L.vh), 4), dim3(kBlock), 0,
+                       c->stream, src, (v2<T>*)dst, L);
+  });
+  return launch_check(c, "gf_pack");
+}
+
+gf_status gf_unpack(gf_ctx* c, const gf_geom* g, const void* src, double* dst) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_unpack");
+  if (!src || !dst) return fail(c, GF_ERR_ARG, "gf_unpack: NULL pointer");
+  const Lat L = make_lat(g);
+  with_type(g, [&]<typename T, int NC>() {
+    hipLaunchKernelGGL((k_unpack<T, NC>), dim3(blocks_for(2ull * L.vh), 4), dim3(kBlock), 0,
+                       c->stream, (const v2<T>*)src, dst, L);
+  });
+  return launch_check(c, "gf_unpack");
+}
+
+template <typename Ts, int NCs>
+static void launch_convert_to(gf_ctx* c, const gf_geom* d, const void* src, void* dst,
+                              uint32_t vh, int reunit) {
+  with_type(d, [&]<typename Td, int NCd>() {
+    hipLaunchKernelGGL((k_convert<Ts, NCs, Td, NCd>), dim3(blocks_for(vh), 8), dim3(kBlock), 0,
+                       c->stream, (const v2<Ts>*)src, (v2<Td>*)dst, vh, reunit);
+  });
+}
+
+gf_status gf_convert(gf_ctx* c, const gf_geom* s, const void* src, const gf_geom* d, void* dst,
+                     int32_t reunitarize) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, s, "gf_convert(src)");
+  CHECK_GEOM(c, d, "gf_convert(dst)");
+  if (!same_extents(s, d)) return fail(c, GF_ERR_ARG, "gf_convert: extents differ");
+  if (!src || !dst) return fail(c, GF_ERR_ARG, "gf_convert: NULL pointer");
+  const size_t bs = gf_field_bytes(s), bd = gf_field_bytes(d);
+  const char *ps = (const char*)src, *pd = (const char*)dst;
+  if (ps < pd + bd && pd < ps + bs) return fail(c, GF_ERR_ARG, "gf_convert: buffers overlap");
+  const uint32_t vh = make_lat(s).vh;
+  with_type(s, [&]<typename Ts, int NCs>() {
+    launch_convert_to<Ts, NCs>(c, d, src, dst, vh, reunitarize ? 1 : 0);
+  });
+  return launch_check(c, "gf_convert");
+}
+
+gf_status gf_reunitarize(gf_ctx* c, void* U, const gf_geom* g) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_reunitarize");
+  if (!U) return fail(c, GF_ERR_ARG, "gf_reunitarize: NULL pointer");
+  const uint32_t vh = make_lat(g).vh;
+  with_type(g, [&]<typename T, int NC>() {
+    hipLaunchKernelGGL((k_reunitarize<T, NC>), dim3(blocks_for(vh), 8), dim3(kBlock), 0,
+                       c->stream, (v2<T>*)U, vh);
+  });
+  return launch_check(c, "gf_reunitarize");
+}
+
+template <class UpdF>
+static gf_status launch_update(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge,
+                               int32_t parity, UpdF make_upd, const char* what) {
+  const Lat L = make_lat(g);
+  const dim3 grid(blocks_for(L.vh));
+  with_type(g, [&]<typename T, int NC>() {
+    auto upd = make_upd.template operator()<T>();
+    if (gauge == GF_LANDAU)
+      hipLaunchKernelGGL((k_update_half<T, NC, kLandau, decltype(upd)>), grid, dim3(kBlock), 0,
+                         c->stream, (v2<T>*)U, L, (int)parity, upd);
+    else
+      hipLaunchKernelGGL((k_update_half<T, NC, kCoulomb, decltype(upd)>), grid, dim3(kBlock), 0,
+                         c->stream, (v2<T>*)U, L, (int)parity, upd);
+  });
+  return launch_check(c, what);
+}
+
+#define CHECK_GAUGE_PARITY(c, gauge, parity, what)                                    \
+  if ((gauge) != GF_LANDAU && (gauge) != GF_COULOMB)                                  \
+    return fail((c), GF_ERR_ARG, "%s: gauge must be GF_LANDAU or GF_COULOMB", what); \
+  if ((parity) != 0 && (parity) != 1) return fail((c), GF_ERR_ARG, "%s: parity must be 0 or 1", what)
+
+gf_status gf_sweep(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32_t parity,
+                   double omega) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_sweep");
+  CHECK_GAUGE_PARITY(c, gauge, parity, "gf_sweep");
+  if (!U) return fail(c, GF_ERR_ARG, "gf_sweep: NULL field");
+  if (!(omega >= 1.0 && omega < 2.0)) return fail(c, GF_ERR_ARG, "gf_sweep: omega must be in [1, 2)");
+  return launch_update(
+      c, U, g, gauge, parity,
+      [&]<typename T>() {
+        UpdOR<T> u;
+        u.omega = (T)omega;
+        return u;
+      },
+      "gf_sweep");
+}
+
+gf_status gf_micro_half(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32_t parity) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_micro_half");
+  CHECK_GAUGE_PARITY(c, gauge, parity, "gf_micro_half");
+  if (!U) return fail(c, GF_ERR_ARG, "gf_micro_half: NULL field");
+  return launch_update(
+      c, U, g, gauge, parity, [&]<typename T>() { return UpdMicro<T>(); }, "gf_micro_half");
+}
+
+gf_status gf_heatbath_half(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32_t parity,
+                           double T, uint64_t seed, uint64_t sweep) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_heatbath_half");
+  CHECK_GAUGE_PARITY(c, gauge, parity, "gf_heatbath_half");
+  if (!U) return fail(c, GF_ERR_ARG, "gf_heatbath_half: NULL field");
+  if (!(T > 0.0) || !std::isfinite(T)) return fail(c, GF_ERR_ARG, "gf_heatbath_half: T must be > 0");
+  return launch_update(
+      c, U, g, gauge, parity,
+      [&]<typename TT>() {
+        UpdHB<TT> u;
+        u.temp = (TT)T;
+        u.k0 = (uint32_t)seed;
+        u.k1 = (uint32_t)(seed >> 32);
+        u.sweep = (uint32_t)sweep;
+        return u;
+      },
+      "gf_heatbath_half");
+}
+
+gf_status gf_anneal_sweep(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, double T,
+                          uint64_t seed, uint64_t sweep, int32_t n_micro) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_anneal_sweep");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_anneal_sweep: bad gauge");
+  if (!U) return fail(c, GF_ERR_ARG, "gf_anneal_sweep: NULL field");
+  if (!(T > 0.0) || !std::isfinite(T)) return fail(c, GF_ERR_ARG, "gf_anneal_sweep: T must be > 0");
+  if (n_micro < 0) return fail(c, GF_ERR_ARG, "gf_anneal_sweep: n_micro < 0");
+  gf_status st;
+  for (int p = 0; p < 2; ++p)
+    if ((st = gf_heatbath_half(c, U, g, gauge, p, T, seed, sweep)) != GF_OK) return st;
+  for (int k = 0; k < n_micro; ++k)
+    for (int p = 0; p < 2; ++p)
+      if ((st = gf_micro_half(c, U, g, gauge, p)) != GF_OK) return st;
+  return GF_OK;
+}
+
+static gf_status measure_impl(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge,
+                              double* F, double* th) {
+  const Lat L = make_lat(g);
+  const uint32_t bpt = blocks_for(L.st);
+  gf_status st = ensure_partial(c, (size_t)2 * bpt * L.nt);
+  if (st != GF_OK) return st;
+  const dim3 grid(bpt, L.nt);
+  with_type(g, [&]<typename T, int NC>() {
+    if (gauge == GF_LANDAU)
+      hipLaunchKernelGGL((k_measure<T, NC, kLandau>), grid, dim3(kBlock), 0, c->stream,
+                         (const v2<T>*)U, L, c->partial);
+    else
+      hipLaunchKernelGGL((k_measure<T, NC, kCoulomb>), grid, dim3(kBlock), 0, c->stream,
+                         (const v2<T>*)U, L, c->partial);
+  });
+  const double V = 2.0 * L.vh, Vs = V / L.nt;
+  if (gauge == GF_LANDAU)
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial,
+                       bpt * L.nt, 12.0 * V, 3.0 * V, F, th);
+  else
+    hipLaunchKernelGGL(k_finish, dim3(L.nt), dim3(kBlock), 0, c->stream,
+                       (const double*)c->partial, bpt, 9.0 * Vs, 3.0 * Vs, F, th);
+  return launch_check(c, "gf_measure");
+}
+
+gf_status gf_measure(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, double* F,
+                     double* th) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_measure");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_measure: bad gauge");
+  if (!U || (!F && !th)) return fail(c, GF_ERR_ARG, "gf_measure: NULL pointer");
+  return measure_impl(c, U, g, gauge, F, th);
+}
+
+gf_status gf_functional(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, double* F) {
+  if (!F) return fail(c, GF_ERR_ARG, "gf_functional: NULL output");
+  return gf_measure(c, U, g, gauge, F, nullptr);
+}
+
+gf_status gf_theta(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, double* th) {
+  if (!th) return fail(c, GF_ERR_ARG, "gf_theta: NULL output");
+  return gf_measure(c, U, g, gauge, nullptr, th);
+}
+
+gf_status gf_plaquette(gf_ctx* c, const void* U, const gf_geom* g, double* P) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_plaquette");
+  if (!U || !P) return fail(c, GF_ERR_ARG, "gf_plaquette: NULL pointer");
+  const Lat L = make_lat(g);
+  const uint32_t nb = blocks_for(L.vh);
+  gf_status st = ensure_partial(c, (size_t)2 * nb);
+  if (st != GF_OK) return st;
+  with_type(g, [&]<typename T, int NC>() {
+    hipLaunchKernelGGL((k_plaquette<T, NC>), dim3(nb), dim3(kBlock), 0, c->stream,
+                       (const v2<T>*)U, L, c->partial);
+  });
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial, nb,
+                     6.0 * 2.0 * L.vh, 1.0, P, (double*)nullptr);
+  return launch_check(c, "gf_plaquette");
+}
+
+gf_status gf_philox(gf_ctx* c, const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t n) {
+  CHECK_CTX(c);
+  if (!ctr || !out || n < 0) return fail(c, GF_ERR_ARG, "gf_philox: bad arguments");
+  if (n == 0) return GF_OK;
+  hipLaunchKernelGGL(k_philox, dim3(blocks_for((uint64_t)n)), dim3(kBlock), 0, c->stream, ctr, out,
+                     n, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return launch_check(c, "gf_philox");
+}
+
+// ---------------------------------------------------------------------------
+// drivers
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Timer {
+  gf_ctx* c;
+  bool on;
+  double* ms;
+  int64_t* n;
+  gf_status begin() {
+    if (on) HIP_OR_FAIL(c, hipEventRecord(c->ev[0], c->stream));
+    return GF_OK;
+  }
+  // closes the interval; synchronises the end event and adds its time
+  gf_status end(int cat, int64_t launches) {
+    if (!on) return GF_OK;
+    HIP_OR_FAIL(c, hipEventRecord(c->ev[1], c->stream));
+    HIP_OR_FAIL(c, hipEventSynchronize(c->ev[1]));
+    float t = 0;
+    HIP_OR_FAIL(c, hipEventElapsedTime(&t, c->ev[0], c->ev[1]));
+    ms[cat] += t;
+    n[cat] += launches;
+    return GF_OK;
+  }
+};
+
+struct Phase {
+  int32_t sweeps = 0;
+  int32_t checks = 0;
+  int converged = 0;
+  double F = 0, theta = 0;
+};
+
+gf_status check_params(gf_ctx* c, const gf_fix_params* p) {
+  if (!p) return fail(c, GF_ERR_ARG, "gf_fix: NULL params");
+  if (!(p->omega >= 1.0 && p->omega < 2.0)) return fail(c, GF_ERR_ARG, "gf_fix: omega must be in [1, 2)");
+  if (p->max_sweeps < 0 || p->check_every < 1) return fail(c, GF_ERR_ARG, "gf_fix: bad sweep counts");
+  if (!(p->theta_target >= 0.0)) return fail(c, GF_ERR_ARG, "gf_fix: bad theta_target");
+  return GF_OK;
+}
+
+// reunitarise (optional), measure F and theta, copy to the host
+gf_status do_check(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, bool reunit, Timer& tm,
+                   Phase& ph) {
+  gf_status st;
+  const int nout = gauge == GF_COULOMB ? g->nt : 1;
+  if ((st = ensure_out(c, nout)) != GF_OK) return st;
+  if (reunit) {
+    if ((st = tm.begin()) != GF_OK) return st;
+    if ((st = gf_reunitarize(c, U, g)) != GF_OK) return st;
+    if ((st = tm.end(3, 1)) != GF_OK) return st;
+  }
+  if ((st = tm.begin()) != GF_OK) return st;
+  if ((st = measure_impl(c, U, g, gauge, c->dev_out, c->dev_out + c->out_cap)) != GF_OK) return st;
+  if ((st = tm.end(2, 2)) != GF_OK) return st;
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->host_out, c->dev_out, 2 * c->out_cap * sizeof(double),
+                                hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  double Fsum = 0, thmax = 0;
+  for (int t = 0; t < nout; ++t) {
+    const double F = c->host_out[t], th = c->host_out[c->out_cap + t];
+    if (!std::isfinite(F) || !std::isfinite(th))
+      return fail(c, GF_ERR_NONFINITE, "gf_fix: non-finite F or theta after %d sweeps", ph.sweeps);
+    Fsum += F;
+    thmax = th > thmax ? th : thmax;
+  }
+  ph.F = Fsum / nout;
+  ph.theta = thmax;
+  ph.checks++;
+  return GF_OK;
+}
+
+// sweeps `geom`'s field until theta < target or max_sweeps
+gf_status run_phase(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const gf_fix_params* p,
+                    double target, bool first_check_reunit, Timer& tm, Phase& ph) {
+  gf_status st;
+  const int cat = g->prec == GF_FP32 ? 0 : 1;
+  for (;;) {
+    const bool reunit = p->reunit_at_check && (ph.sweeps > 0 || first_check_reunit);
+    if ((st = do_check(c, U, g, gauge, reunit, tm, ph)) != GF_OK) return st;
+    if (ph.theta < target) {
+      ph.converged = 1;
+      return GF_OK;
+    }
+    if (ph.sweeps >= p->max_sweeps) return GF_OK;
+    const int32_t n = std::min(p->check_every, p->max_sweeps - ph.sweeps);
+    if ((st = tm.begin()) != GF_OK) return st;
+    for (int32_t k = 0; k < n; ++k) {
+      if ((st = gf_sweep(c, U, g, gauge, 0, p->omega)) != GF_OK) return st;
+      if ((st = gf_sweep(c, U, g, gauge, 1, p->omega)) != GF_OK) return st;
+    }
+    if ((st = tm.end(cat, 2 * (int64_t)n)) != GF_OK) return st;
+    ph.sweeps += n;
+  }
+}
+
+void init_result(gf_fix_result* r) {
+  memset(r, 0, sizeof *r);
+}
+
+}  // namespace
+
+gf_status gf_fix(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const gf_fix_params* p,
+                 gf_fix_result* r) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_fix");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_fix: bad gauge");
+  if (!U || !r) return fail(c, GF_ERR_ARG, "gf_fix: NULL pointer");
+  gf_status st = check_params(c, p);
+  if (st != GF_OK) return st;
+  init_result(r);
+  const auto t0 = std::chrono::steady_clock::now();
+  Timer tm{c, (p->flags & GF_FLAG_TIMING) != 0, r->kernel_ms, r->kernel_launches};
+  Phase ph;
+  st = run_phase(c, U, g, gauge, p, p->theta_target, false, tm, ph);
+  r->sweeps = ph.sweeps;
+  r->checks = ph.checks;
+  r->F = ph.F;
+  r->theta = ph.theta;
+  r->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (st != GF_OK) {
+    r->status = st;
+    return st;
+  }
+  r->status = ph.converged ? GF_OK : GF_NOT_CONVERGED;
+  return r->status;
+}
+
+gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
+                       const gf_geom* g_hi, int32_t gauge, const gf_fix_params* p,
+                       gf_fix_result* r) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g_lo, "gf_fix_mixed(lo)");
+  CHECK_GEOM(c, g_hi, "gf_fix_mixed(hi)");
+  if (g_lo->prec != GF_FP32 || g_hi->prec != GF_FP64)
+    return fail(c, GF_ERR_ARG, "gf_fix_mixed: needs an FP32 and an FP64 field");
+  if (!same_extents(g_lo, g_hi)) return fail(c, GF_ERR_ARG, "gf_fix_mixed: extents differ");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_fix_mixed: bad gauge");
+  if (!U_lo || !U_hi || !r) return fail(c, GF_ERR_ARG, "gf_fix_mixed: NULL pointer");
+  gf_status st = check_params(c, p);
+  if (st != GF_OK) return st;
+  if (!(p->theta_switch > 0.0)) return fail(c, GF_ERR_ARG, "gf_fix_mixed: theta_switch must be > 0");
+  init_result(r);
+  const auto t0 = std::chrono::steady_clock::now();
+  Timer tm{c, (p->flags & GF_FLAG_TIMING) != 0, r->kernel_ms, r->kernel_launches};
+  Phase lo;
+  st = run_phase(c, U_lo, g_lo, gauge, p, p->theta_switch, false, tm, lo);
+  Phase hi;
+  if (st == GF_OK) {
+    r->theta_at_switch = lo.theta;
+    if ((st = tm.begin()) == GF_OK && (st = gf_convert(c, g_lo, U_lo, g_hi, U_hi, 1)) == GF_OK &&
+        (st = tm.end(3, 1)) == GF_OK)
+      st = run_phase(c, U_hi, g_hi, gauge, p, p->theta_target, false, tm, hi);
+  }
+  r->sweeps_lo = lo.sweeps;
+  r->sweeps = lo.sweeps + hi.sweeps;
+  r->checks = lo.checks + hi.checks;
+  r->F = hi.checks ? hi.F : lo.F;
+  r->theta = hi.checks ? hi.theta : lo.theta;
+  r->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (st != GF_OK) {
+    r->status = st;
+    return st;
+  }
+  r->status = hi.converged ? GF_OK : GF_NOT_CONVERGED;
+  return r->status;
+}
+

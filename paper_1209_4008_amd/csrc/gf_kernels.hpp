@@ -1,0 +1,493 @@
+// gf_kernels.hpp -- HIP kernels of libgf for gfx950 (wave64, no MFMA: 3x3
+// complex products are far too small to be a dense contraction; the sweep is
+// bound by HBM traffic).
+//
+// Site update (Alg. 1 of the paper) as computed here:
+//   gather the 8 links of x (4 forward from the block of x's parity, 4
+//   backward from the other parity's block), K = sum_{mu in D} U_mu(x) +
+//   U_mu(x-mu)^dag (eq. (5) with the neighbours' transformations already in
+//   the links); for the subgroups (0,1), (0,2), (1,2): w = 2 x quaternion part
+//   of the (i,j) block of K^dag (whose normalisation is the local maximum of
+//   eq. (6)), s = update(w), K <- G(s) K and Gtot <- G(s) Gtot; finally
+//   U_mu(x) <- Gtot U_mu(x), U_mu(x-mu) <- U_mu(x-mu) Gtot^dag for all mu.
+// K <- G K is exact algebra (the links after the subgroup step sum to G K),
+// so this equals applying each subgroup to the 8 links in turn, with 1/3 of
+// the link arithmetic. Every link is read once and written once per
+// half-sweep.
+#pragma once
+
+#include "gf_device.hpp"
+
+namespace gf {
+
+constexpr int kBlock = 256;
+constexpr int kLandau = 0;
+constexpr int kCoulomb = 1;
+
+template <int GAUGE>
+struct FirstDir {
+  static constexpr int value = (GAUGE == kCoulomb) ? 1 : 0;
+};
+
+// ---------------------------------------------------------------------------
+// subgroup algebra
+// ---------------------------------------------------------------------------
+// w = 2 x quaternion part of the (I,J) block of K^dagger, for the convention
+// a <-> [[a0 + i a3, a2 + i a1], [-a2 + i a1, a0 - i a3]]
+template <typename T, int I, int J>
+__device__ __forceinline__ void subgroup_w(const Su3<T>& K, T w[4]) {
+  w[0] = K.e[I][I].re + K.e[J][J].re;
+  w[1] = -(K.e[I][J].im + K.e[J][I].im);
+  w[2] = K.e[J][I].re - K.e[I][J].re;
+  w[3] = K.e[J][J].im - K.e[I][I].im;
+}
+
+// M <- G(s) M on rows I, J
+template <typename T, int I, int J>
+__device__ __forceinline__ void left_su2(Su3<T>& M, const T s[4]) {
+  const Cx<T> gii = cx(s[0], s[3]), gij = cx(s[2], s[1]);
+  const Cx<T> gji = cx(-s[2], s[1]), gjj = cx(s[0], -s[3]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const Cx<T> mi = M.e[I][k], mj = M.e[J][k];
+    M.e[I][k] = cmac(cmul(gii, mi), gij, mj);
+    M.e[J][k] = cmac(cmul(gji, mi), gjj, mj);
+  }
+}
+
+// quaternion product for Q(a) Q(b) = Q(c)
+template <typename T>
+__device__ __forceinline__ void qmul(const T a[4], const T b[4], T c[4]) {
+  c[0] = a[0] * b[0] - (a[1] * b[1] + a[2] * b[2] + a[3] * b[3]);
+  c[1] = a[0] * b[1] + b[0] * a[1] - (a[2] * b[3] - a[3] * b[2]);
+  c[2] = a[0] * b[2] + b[0] * a[2] - (a[3] * b[1] - a[1] * b[3]);
+  c[3] = a[0] * b[3] + b[0] * a[3] - (a[1] * b[2] - a[2] * b[1]);
+}
+
+// ---- update policies: w -> SU(2) quaternion s (false: leave the subgroup) ----
+
+// Overrelaxation (Sec. 2, Alg. 1 "g -> g^omega, project to SU(2)", 19 flop):
+// b = (omega w0^2 + |wv|^2)/|w|^2, c = (w0^2 + b^2 |wv|^2)^(-1/2),
+// s = (c w0, b c wv); omega = 1 gives s = w/|w|.
+template <typename T>
+struct UpdOR {
+  T omega;
+  __device__ __forceinline__ bool operator()(const T w[4], uint32_t, int, T s[4]) const {
+    const T a0sq = w[0] * w[0];
+    const T avsq = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+    const T n = a0sq + avsq;
+    if (!(n > Tiny<T>::value)) return false;
+    const T b = (omega * a0sq + avsq) / n;
+    const T c = rsqrt_t(a0sq + b * b * avsq);
+    const T bc = b * c;
+    s[0] = c * w[0];
+    s[1] = bc * w[1];
+    s[2] = bc * w[2];
+    s[3] = bc * w[3];
+    return true;
+  }
+};
+
+// Microcanonical reflection: s = (w/|w|)^2, leaves Re tr[g K] unchanged.
+template <typename T>
+struct UpdMicro {
+  __device__ __forceinline__ bool operator()(const T w[4], uint32_t, int, T s[4]) const {
+    const T n2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+    if (!(n2 > Tiny<T>::value)) return false;
+    const T r = rsqrt_t(n2);
+    const T a0 = w[0] * r;
+    s[0] = a0 * a0 - (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) * (r * r);
+    s[1] = 2 * a0 * (w[1] * r);
+    s[2] = 2 * a0 * (w[2] * r);
+    s[3] = 2 * a0 * (w[3] * r);
+    return true;
+  }
+};
+
+// Heatbath with weight exp(Re tr[g K]/T): with g = X what, Re tr = |w| X0, so
+// X0 is drawn with density ~ sqrt(1 - X0^2) exp(alpha X0), alpha = |w|/T, by
+// Kennedy & Pendleton (Phys. Lett. B 156 (1985) 393), and (X1, X2, X3) is
+// uniform on the sphere of radius sqrt(1 - X0^2).
+// Philox: key (seed lo, seed hi), counter (site, sweep, tag, attempt),
+// tag = 0x1000 | kind << 8 | subgroup, kind 0 = trial, 1 = direction.
+constexpr uint32_t kTagKP = 0x1000u;
+constexpr uint32_t kTagDir = 0x1100u;
+constexpr uint32_t kMaxAttempts = 1024u;
+
+template <typename T>
+struct UpdHB {
+  T temp;
+  uint32_t k0, k1, sweep;
+  __device__ __forceinline__ bool operator()(const T w[4], uint32_t site, int sg, T s[4]) const {
+    const T n2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+    if (!(n2 > Tiny<T>::value)) return false;
+    const T n = sqrt_t(n2);
+    const T alpha = n / temp;
+    const T two_pi = (T)6.283185307179586476925286766559;
+    T X0 = 2;
+    for (uint32_t att = 0; att < kMaxAttempts; ++att) {
+      const U4 r = philox4x32_10(site, sweep, kTagKP | (uint32_t)sg, att, k0, k1);
+      const T u0 = unit_open<T>(r.v[0]), u1 = unit_open<T>(r.v[1]);
+      const T u2 = unit_open<T>(r.v[2]), u3 = unit_open<T>(r.v[3]);
+      const T cs = cos(two_pi * u1);
+      const T lam2 = -(log(u0) + cs * cs * log(u2)) / (2 * alpha);
+      if (u3 * u3 <= 1 - lam2) {
+        X0 = 1 - 2 * lam2;
+        break;
+      }
+    }
+    if (X0 > (T)1.5) return false;  // attempt cap: subgroup left unchanged
+    const U4 d = philox4x32_10(site, sweep, kTagDir | (uint32_t)sg, 0u, k0, k1);
+    const T d0 = unit_open<T>(d.v[0]), d1 = unit_open<T>(d.v[1]);
+    const T cth = 2 * d0 - 1;
+    const T sth = sqrt_t(fmax(T(0), 1 - cth * cth));
+    const T phi = two_pi * d1;
+    const T rad = sqrt_t(fmax(T(0), 1 - X0 * X0));
+    const T X[4] = {X0, rad * sth * cos(phi), rad * sth * sin(phi), rad * cth};
+    const T wh[4] = {w[0] / n, w[1] / n, w[2] / n, w[3] / n};
+    qmul(X, wh, s);
+    return true;
+  }
+};
+
+template <typename T, class Upd, int I, int J, int SG>
+__device__ __forceinline__ void subgroup_step(Su3<T>& K, Su3<T>& G, uint32_t site, const Upd& upd) {
+  T w[4], s[4];
+  subgroup_w<T, I, J>(K, w);
+  if (!upd(w, site, SG, s)) return;
+  left_su2<T, I, J>(K, s);
+  left_su2<T, I, J>(G, s);
+}
+
+// ---------------------------------------------------------------------------
+// half-sweep: one thread per site of the given parity
+// ---------------------------------------------------------------------------
+template <typename T, int NC, int GAUGE, class Upd>
+__global__ __launch_bounds__(kBlock) void k_update_half(v2<T>* __restrict__ U, const Lat L,
+                                                        const int parity, const Upd upd) {
+  const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+  if (h >= L.vh) return;
+  const Site S = site_of(L, h, parity);
+  const size_t blk = (size_t)NC * L.vh;
+  v2<T>* __restrict__ Pf = U + (size_t)parity * 4 * blk;
+  v2<T>* __restrict__ Pb = U + (size_t)(1 - parity) * 4 * blk;
+  uint32_t hb[4];
+  Su3<T> Uf[4], Ub[4];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    hb[mu] = back_h(L, h, S, mu);
+    load_link<T, NC>(Pf + mu * blk, L.vh, h, Uf[mu]);
+    load_link<T, NC>(Pb + mu * blk, L.vh, hb[mu], Ub[mu]);
+  }
+  Su3<T> K;
+  set_zero(K);
+#pragma unroll
+  for (int mu = FirstDir<GAUGE>::value; mu < 4; ++mu)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        K.e[a][b] = cadd(K.e[a][b], cadd(Uf[mu].e[a][b], cconj(Ub[mu].e[b][a])));
+  Su3<T> G;
+  set_unit(G);
+  const uint32_t site = 2 * h + S.xodd;
+  subgroup_step<T, Upd, 0, 1, 0>(K, G, site, upd);
+  subgroup_step<T, Upd, 0, 2, 1>(K, G, site, upd);
+  subgroup_step<T, Upd, 1, 2, 2>(K, G, site, upd);
+  constexpr int R = NC / 3;  // stored rows
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    Su3<T> A;
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        Cx<T> f = cmul(G.e[a][0], Uf[mu].e[0][b]);
+        f = cmac(f, G.e[a][1], Uf[mu].e[1][b]);
+        A.e[a][b] = cmac(f, G.e[a][2], Uf[mu].e[2][b]);
+      }
+    store_link<T, NC>(Pf + mu * blk, L.vh, h, A);
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        Cx<T> f = cx<T>(0, 0);
+        f = cmac_cb(f, Ub[mu].e[a][0], G.e[b][0]);
+        f = cmac_cb(f, Ub[mu].e[a][1], G.e[b][1]);
+        A.e[a][b] = cmac_cb(f, Ub[mu].e[a][2], G.e[b][2]);
+      }
+    store_link<T, NC>(Pb + mu * blk, L.vh, hb[mu], A);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions (FP64 accumulation, fixed order: wave shuffle, LDS, per-block
+// partials, then one finishing block per output)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// sum over the block (kBlock threads); result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kBlock / 64; ++k) r += lds[k];
+  __syncthreads();
+  return r;
+}
+
+template <typename T, int NC>
+__device__ __forceinline__ void load_link_f64(const v2<T>* __restrict__ blk, uint32_t vh,
+                                              uint32_t h, Su3<double>& A) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const v2<T> v = blk[(size_t)c * vh + h];
+    A.e[c / 3][c % 3] = cx<double>((double)v.x, (double)v.y);
+  }
+  if (NC == 6) rebuild_row2(A);
+}
+
+// grid (blocks per timeslice, nt); thread -> half index within timeslice t,
+// both parities. partial[(t*bpt + bx)*2 + {0: F, 1: theta}]
+template <typename T, int NC, int GAUGE>
+__global__ __launch_bounds__(kBlock) void k_measure(const v2<T>* __restrict__ U, const Lat L,
+                                                    double* __restrict__ partial) {
+  __shared__ double lds[kBlock / 64];
+  const uint32_t t = blockIdx.y;
+  const uint32_t ht = blockIdx.x * kBlock + threadIdx.x;
+  const size_t blk = (size_t)NC * L.vh;
+  double f = 0, th = 0;
+  if (ht < L.st) {
+    const uint32_t h = t * L.st + ht;
+#pragma unroll 1
+    for (int p = 0; p < 2; ++p) {
+      const Site S = site_of(L, h, p);
+      const v2<T>* Pf = U + (size_t)p * 4 * blk;
+      const v2<T>* Pb = U + (size_t)(1 - p) * 4 * blk;
+      Su3<double> K;
+      set_zero(K);
+#pragma unroll 1
+      for (int mu = FirstDir<GAUGE>::value; mu < 4; ++mu) {
+        Su3<double> A, B;
+        load_link_f64<T, NC>(Pf + mu * blk, L.vh, h, A);
+        load_link_f64<T, NC>(Pb + mu * blk, L.vh, back_h(L, h, S, mu), B);
+        f += A.e[0][0].re + A.e[1][1].re + A.e[2][2].re;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+            K.e[a][b] = cadd(K.e[a][b], cadd(A.e[a][b], cconj(B.e[b][a])));
+      }
+      // Delta = traceless part of (K - K^dag)/(2i); theta density tr[Delta Delta^dag]
+      const double d0 = K.e[0][0].im, d1 = K.e[1][1].im, d2 = K.e[2][2].im;
+      const double tr3 = (d0 + d1 + d2) / 3.0;
+      double acc = (d0 - tr3) * (d0 - tr3) + (d1 - tr3) * (d1 - tr3) + (d2 - tr3) * (d2 - tr3);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          if (a == b) continue;
+          const Cx<double> z = csub(K.e[a][b], cconj(K.e[b][a]));
+          acc += 0.25 * (z.re * z.re + z.im * z.im);
+        }
+      th += acc;
+    }
+  }
+  f = block_sum(f, lds);
+  th = block_sum(th, lds);
+  if (threadIdx.x == 0) {
+    const size_t o = ((size_t)t * gridDim.x + blockIdx.x) * 2;
+    partial[o] = f;
+    partial[o + 1] = th;
+  }
+}
+
+// one block per output group: sums n_per partial pairs starting at group*n_per
+__global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ partial,
+                                                   uint32_t n_per, double norm0, double norm1,
+                                                   double* __restrict__ out0,
+                                                   double* __restrict__ out1) {
+  __shared__ double lds[kBlock / 64];
+  const size_t base = (size_t)blockIdx.x * n_per;
+  double a = 0, b = 0;
+  for (uint32_t k = threadIdx.x; k < n_per; k += kBlock) {
+    a += partial[(base + k) * 2];
+    b += partial[(base + k) * 2 + 1];
+  }
+  a = block_sum(a, lds);
+  b = block_sum(b, lds);
+  if (threadIdx.x == 0) {
+    if (out0) out0[blockIdx.x] = a / norm0;
+    if (out1) out1[blockIdx.x] = b / norm1;
+  }
+}
+
+// average plaquette: partial[(bx)*2 + {0: sum Re tr U_P / 3, 1: 0}]
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_plaquette(const v2<T>* __restrict__ U, const Lat L,
+                                                      double* __restrict__ partial) {
+  __shared__ double lds[kBlock / 64];
+  const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+  const size_t blk = (size_t)NC * L.vh;
+  double acc = 0;
+  if (h < L.vh) {
+#pragma unroll 1
+    for (int p = 0; p < 2; ++p) {
+      const Site S = site_of(L, h, p);
+      const v2<T>* Pp = U + (size_t)p * 4 * blk;
+      const v2<T>* Po = U + (size_t)(1 - p) * 4 * blk;
+#pragma unroll 1
+      for (int mu = 0; mu < 4; ++mu)
+#pragma unroll 1
+        for (int nu = mu + 1; nu < 4; ++nu) {
+          Su3<double> A, B, C, D;
+          load_link_f64<T, NC>(Pp + mu * blk, L.vh, h, A);
+          load_link_f64<T, NC>(Po + nu * blk, L.vh, fwd_h(L, h, S, mu), B);
+          load_link_f64<T, NC>(Po + mu * blk, L.vh, fwd_h(L, h, S, nu), C);
+          load_link_f64<T, NC>(Pp + nu * blk, L.vh, h, D);
+          // Re tr[A B C^dag D^dag] = Re sum_{a,b} (A B)_{ab} (D C)^*_{ab}
+          double tr = 0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              Cx<double> ab = cx<double>(0, 0), dc = cx<double>(0, 0);
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                ab = cmac(ab, A.e[a][k], B.e[k][b]);
+                dc = cmac(dc, D.e[a][k], C.e[k][b]);
+              }
+              tr += ab.re * dc.re + ab.im * dc.im;
+            }
+          acc += tr / 3.0;
+        }
+    }
+  }
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) {
+    partial[(size_t)blockIdx.x * 2] = acc;
+    partial[(size_t)blockIdx.x * 2 + 1] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// layout conversion
+// ---------------------------------------------------------------------------
+// Gram-Schmidt in FP64 on rows 0, 1, then row 2 = conj(row0 x row1)
+__device__ __forceinline__ void gram_schmidt(Su3<double>& A) {
+  double n0 = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) n0 += A.e[0][b].re * A.e[0][b].re + A.e[0][b].im * A.e[0][b].im;
+  n0 = 1.0 / sqrt(n0);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) A.e[0][b] = cx(A.e[0][b].re * n0, A.e[0][b].im * n0);
+  Cx<double> ip = cx<double>(0, 0);  // sum conj(row0) row1
+#pragma unroll
+  for (int b = 0; b < 3; ++b) ip = cmac_cb(ip, A.e[1][b], A.e[0][b]);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) A.e[1][b] = csub(A.e[1][b], cmul(ip, A.e[0][b]));
+  double n1 = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) n1 += A.e[1][b].re * A.e[1][b].re + A.e[1][b].im * A.e[1][b].im;
+  n1 = 1.0 / sqrt(n1);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) A.e[1][b] = cx(A.e[1][b].re * n1, A.e[1][b].im * n1);
+  rebuild_row2(A);
+}
+
+template <typename Td, int NCd>
+__device__ __forceinline__ void store_link_from_f64(v2<Td>* __restrict__ blk, uint32_t vh,
+                                                    uint32_t h, const Su3<double>& A) {
+#pragma unroll
+  for (int c = 0; c < NCd; ++c) {
+    v2<Td> v;
+    v.x = (Td)A.e[c / 3][c % 3].re;
+    v.y = (Td)A.e[c / 3][c % 3].im;
+    blk[(size_t)c * vh + h] = v;
+  }
+}
+
+// grid (ceil(vh/kBlock), 8): blockIdx.y = p*4 + mu
+template <typename Ts, int NCs, typename Td, int NCd>
+__global__ __launch_bounds__(kBlock) void k_convert(const v2<Ts>* __restrict__ src,
+                                                    v2<Td>* __restrict__ dst, const uint32_t vh,
+                                                    const int reunit) {
+  const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+  if (h >= vh) return;
+  const size_t pm = blockIdx.y;
+  Su3<double> A;
+  load_link_f64<Ts, NCs>(src + pm * NCs * vh, vh, h, A);
+  if (reunit) gram_schmidt(A);
+  store_link_from_f64<Td, NCd>(dst + pm * NCd * vh, vh, h, A);
+}
+
+// in place: same buffer, each thread reads and then writes its own link
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_reunitarize(v2<T>* U, const uint32_t vh) {
+  const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+  if (h >= vh) return;
+  const size_t pm = blockIdx.y;
+  Su3<double> A;
+  load_link_f64<T, NC>(U + pm * NC * vh, vh, h, A);
+  gram_schmidt(A);
+  store_link_from_f64<T, NC>(U + pm * NC * vh, vh, h, A);
+}
+
+// canonical complex128 U[s][mu][3][3] -> device layout; grid (ceil(V/kBlock), 4)
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_pack(const double* __restrict__ src,
+                                                 v2<T>* __restrict__ dst, const Lat L) {
+  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= 2 * L.vh) return;
+  const int mu = blockIdx.y;
+  const uint32_t h = s >> 1;
+  const Site S = site_of(L, h, 0);
+  const int p = (int)((S.t + S.z + S.y + (s & 1u)) & 1u);
+  const double* q = src + ((size_t)s * 4 + mu) * 18;
+  v2<T>* d = dst + ((size_t)p * 4 + mu) * NC * L.vh;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    v2<T> v;
+    v.x = (T)q[2 * c];
+    v.y = (T)q[2 * c + 1];
+    d[(size_t)c * L.vh + h] = v;
+  }
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_unpack(const v2<T>* __restrict__ src,
+                                                   double* __restrict__ dst, const Lat L) {
+  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= 2 * L.vh) return;
+  const int mu = blockIdx.y;
+  const uint32_t h = s >> 1;
+  const Site S = site_of(L, h, 0);
+  const int p = (int)((S.t + S.z + S.y + (s & 1u)) & 1u);
+  Su3<double> A;
+  load_link_f64<T, NC>(src + ((size_t)p * 4 + mu) * NC * L.vh, L.vh, h, A);
+  double* q = dst + ((size_t)s * 4 + mu) * 18;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    q[2 * c] = A.e[c / 3][c % 3].re;
+    q[2 * c + 1] = A.e[c / 3][c % 3].im;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_philox(const uint32_t* __restrict__ ctr,
+                                                   uint32_t* __restrict__ out, const int64_t n,
+                                                   const uint32_t k0, const uint32_t k1) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const U4 r = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[4 * i + k] = r.v[k];
+}
+
+}  // namespace gf

@@ -1,0 +1,141 @@
+"""GPU parity of the drivers and of simulated annealing, plus sampled parity
+at the full benchmark sizes."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle as O
+import paper_1209_4008_amd as gf
+from gpu_helpers import (TOL, download, host_canon, oracle_input, say, site_parity, sites_links,
+                         upload)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = gf.Context()
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.mark.parametrize("storage", [gf.R18, gf.R12])
+def test_fix_config0_matches_oracle(ctx, storage):
+    """8^4, FP64, omega = 1.7, theta < 1e-12, max 2000 sweeps, check every 100."""
+    U = inputs.config0((8, 8, 8, 8), 0.3, 1)
+    say("fix config0 FP64", storage)
+    f, g = upload(ctx, U, gf.FP64, storage)
+    p = gf.fix_params(omega=1.7, theta_target=1e-12, max_sweeps=2000, check_every=100)
+    r = ctx.fix(f, g, gf.LANDAU, p)
+    ref = oracle_input(U, gf.FP64, storage)
+    ro = O.fix(ref, gf.LANDAU, 1.7, 1e-12, 2000, 100, 1)
+    assert r.status == gf.OK and ro["converged"]
+    assert r.sweeps == ro["sweeps"]
+    assert r.F == pytest.approx(ro["F"], rel=1e-10)
+    assert r.theta < 1e-12
+    assert np.abs(download(ctx, f, g) - ref).max() < 1e-9
+
+
+def test_fix_mixed_config0_matches_oracle(ctx):
+    U = inputs.config0((8, 8, 8, 8), 0.3, 1)
+    glo = gf.Geom.make(U.shape[:4], gf.FP32, gf.R12)
+    ghi = gf.Geom.make(U.shape[:4], gf.FP64, gf.R12)
+    flo, _ = upload(ctx, U, gf.FP32, gf.R12)
+    fhi = ctx.empty_field(ghi)
+    p = gf.fix_params(omega=1.7, theta_target=1e-14, theta_switch=1e-6, max_sweeps=4000,
+                      check_every=100, flags=gf.FLAG_TIMING)
+    r = ctx.fix_mixed(flo, glo, fhi, ghi, gf.LANDAU, p)
+    ref = oracle_input(U, gf.FP64, gf.R12)
+    ro = O.fix(ref, gf.LANDAU, 1.7, 1e-14, 4000, 100, 1)
+    say("mixed", r.as_dict(), ro)
+    assert r.status == gf.OK and ro["converged"]
+    assert r.sweeps_lo > 0 and r.sweeps > r.sweeps_lo
+    assert r.theta_at_switch < 1e-6 and r.theta < 1e-14
+    assert r.F == pytest.approx(ro["F"], rel=1e-10)
+    assert r.kernel_launches[0] == 2 * r.sweeps_lo
+    assert r.kernel_launches[1] == 2 * (r.sweeps - r.sweeps_lo)
+
+
+@pytest.mark.parametrize("prec,storage", [(gf.FP64, gf.R18), (gf.FP64, gf.R12)])
+def test_fix_coulomb_matches_oracle(ctx, prec, storage):
+    dims = (8, 4, 6, 4)
+    U = inputs.config0(dims, 0.4, 4)
+    f, g = upload(ctx, U, prec, storage)
+    p = gf.fix_params(omega=1.7, theta_target=1e-13, max_sweeps=3000, check_every=50)
+    r = ctx.fix(f, g, gf.COULOMB, p)
+    ref = oracle_input(U, prec, storage)
+    ro = O.fix(ref, gf.COULOMB, 1.7, 1e-13, 3000, 50, 1)
+    assert r.status == gf.OK and ro["converged"] and r.sweeps == ro["sweeps"]
+    F, th = ctx.empty_out(dims[0]), ctx.empty_out(dims[0])
+    ctx.measure(f, g, gf.COULOMB, F, th)
+    assert np.allclose(F.cpu().numpy(), O.functional(ref, gf.COULOMB)[1], rtol=1e-10)
+    assert np.all(th.cpu().numpy() < 1e-13)
+
+
+@pytest.mark.parametrize("gauge", [gf.LANDAU, gf.COULOMB])
+@pytest.mark.parametrize("storage", [gf.R18, gf.R12])
+def test_anneal_parity_fp64(ctx, gauge, storage):
+    """FP64 heatbath + microcanonical half-sweeps draw the same Philox numbers
+    as the oracle and take the same accept/reject decisions."""
+    dims = (4, 4, 6, 4)
+    U = inputs.config0(dims, 0.6, 21)
+    ref = oracle_input(U, gf.FP64, storage)
+    for k, T in enumerate([1.45, 0.8, 0.3, 0.01]):
+        f, g = upload(ctx, ref, gf.FP64, storage)
+        ctx.anneal_sweep(f, g, gauge, T, 777, k, 3)
+        O.anneal_sweep(ref, gauge, T, 777, k, 3)
+        err = np.abs(download(ctx, f, g) - ref).max()
+        assert err <= 1e-12, (k, T, err)
+
+
+def test_anneal_fp32_statistics(ctx):
+    """FP32 annealing: unitarity kept by the 12-real storage, plaquette
+    unchanged (gauge transformation), and a hot anneal disorders U = 1."""
+    dims = (8, 8, 8, 8)
+    U = inputs.unit_field(dims)
+    f, g = upload(ctx, U, gf.FP32, gf.R12)
+    for k in range(10):
+        ctx.anneal_sweep(f, g, gf.LANDAU, 4.0, 3, k, 1)
+    F, P = ctx.empty_out(1), ctx.empty_out(1)
+    ctx.functional(f, g, gf.LANDAU, F)
+    ctx.plaquette(f, g, P)
+    assert F.item() < 0.5
+    assert P.item() == pytest.approx(1.0, abs=1e-5)
+
+
+def _full_size_input(dims, beta, sweeps, seed):
+    import torch
+    say("generating", dims, beta, sweeps, seed)
+    d = inputs.gpu_heatbath(dims, beta, sweeps, seed)
+    torch.cuda.synchronize()
+    return host_canon(d, dims)
+
+
+@pytest.mark.parametrize("dims,beta,seed", [((32, 32, 32, 32), 6.0, 2), ((48, 48, 48, 48), 6.2, 3)])
+@pytest.mark.parametrize("prec", [gf.FP32, gf.FP64])
+def test_full_size_sampled_parity(ctx, dims, beta, seed, prec):
+    """One RED half-sweep at the benchmark sizes (12-real storage, the launch
+    the benchmark times); 256 sampled sites recomputed by the oracle."""
+    U = _full_size_input(dims, beta, 20, seed)
+    f, g = upload(ctx, U, prec, gf.R12)
+    ctx.sweep(f, g, gf.LANDAU, 0, 1.7)
+    got = download(ctx, f, g)
+    ref = oracle_input(U, prec, gf.R12)
+    rng = np.random.default_rng(seed)
+    V = int(np.prod(dims))
+    cand = rng.choice(V, size=1024, replace=False)
+    sites = [int(s) for s in cand if site_parity(dims, s) == 0][:256]
+    O.update_sites(ref, gf.LANDAU, 1.7, sites)
+    g4 = got.reshape(V, 4, 3, 3)
+    r4 = ref.reshape(V, 4, 3, 3)
+    err = max(np.abs(g4[s, mu] - r4[s, mu]).max() for s, mu in sites_links(dims, sites))
+    assert err <= TOL[prec], err
+    # and an untouched-parity property at any size: plaquette unchanged
+    P0, P1 = ctx.empty_out(1), ctx.empty_out(1)
+    f0, g0 = upload(ctx, U, prec, gf.R12)
+    ctx.plaquette(f0, g0, P0)
+    ctx.plaquette(f, g, P1)
+    assert P1.item() == pytest.approx(P0.item(), abs=1e-12 if prec == gf.FP64 else 1e-5)
