@@ -307,25 +307,25 @@ GEN_HD void heatbath_link(double* U, const Lat& L, int64_t s, int mu, double bet
     const double alpha = (beta / 3.0) * 2.0 * n;
     const uint32_t tagkp = kTagHeatbath | ((uint32_t)mu << 8) | (0u << 4) | (uint32_t)sg;
     const uint32_t tagdir = kTagHeatbath | ((uint32_t)mu << 8) | (1u << 4) | (uint32_t)sg;
-    double X0 = 2.0;
+    double lam2 = -1.0;
     for (uint32_t att = 0; att < 1024u; ++att) {
       double u[4];
       uniforms(seed, (uint32_t)s, sweep, tagkp, att, u);
       const double c = cos(kTwoPi * u[1]);
-      const double lam2 = -(log(u[0]) + c * c * log(u[2])) / (2.0 * alpha);
-      if (u[3] * u[3] <= 1.0 - lam2) {
-        X0 = 1.0 - 2.0 * lam2;
+      const double l2 = -(log(u[0]) + c * c * log(u[2])) / (2.0 * alpha);
+      if (u[3] * u[3] <= 1.0 - l2) {
+        lam2 = l2;
         break;
       }
     }
-    if (X0 > 1.5) continue;  // attempt cap hit: leave the link unchanged in this subgroup
+    if (lam2 < 0.0) continue;  // attempt cap hit: leave the link unchanged in this subgroup
     double d[4];
     uniforms(seed, (uint32_t)s, sweep, tagdir, 0u, d);
     const double cth = 2.0 * d[0] - 1.0;
     const double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
     const double phi = kTwoPi * d[1];
-    const double rad = sqrt(fmax(0.0, 1.0 - X0 * X0));
-    const double X[4] = {X0, rad * sth * cos(phi), rad * sth * sin(phi), rad * cth};
+    const double rad = 2.0 * sqrt(lam2 * (1.0 - lam2));  // sqrt(1 - X0^2) without cancellation
+    const double X[4] = {1.0 - 2.0 * lam2, rad * sth * cos(phi), rad * sth * sin(phi), rad * cth};
     const double qh[4] = {q[0] / n, q[1] / n, q[2] / n, q[3] / n};
     const m3 G = mm(embed(X, i, j), embed(qh, i, j));
     Ul = mm(G, Ul);

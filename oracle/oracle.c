@@ -279,8 +279,10 @@ static void draw_block(uint64_t seed, uint64_t site, uint64_t sweep, uint32_t ta
 /* Kennedy & Pendleton, Phys. Lett. B 156 (1985) 393: with
  * lambda^2 = -(ln u1 + cos^2(2 pi u2) ln u3) / (2 alpha) (a Gamma(3/2)
  * variate scaled by 1/(2 alpha)), accept when u4^2 <= 1 - lambda^2 and set
- * X0 = 1 - 2 lambda^2; X0 then has density ~ sqrt(1 - X0^2) exp(alpha X0). */
-int or_kp_draw(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int sg, double* X0) {
+ * X0 = 1 - 2 lambda^2; X0 then has density ~ sqrt(1 - X0^2) exp(alpha X0).
+ * Returns the attempts used (0 when the cap was hit) and lambda^2. */
+static int kp_lambda2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int sg,
+                      double* lam2_out) {
   const double two_pi = 6.283185307179586476925286766559;
   for (int a = 0; a < OR_KP_MAX_ATTEMPTS; ++a) {
     double u[4];
@@ -288,11 +290,18 @@ int or_kp_draw(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int s
     double cs = cos(two_pi * u[1]);
     double lam2 = -(log(u[0]) + cs * cs * log(u[2])) / (2.0 * alpha);
     if (u[3] * u[3] <= 1.0 - lam2) {
-      *X0 = 1.0 - 2.0 * lam2;
+      *lam2_out = lam2;
       return a + 1;
     }
   }
   return 0;
+}
+
+int or_kp_draw(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int sg, double* X0) {
+  double lam2;
+  int n = kp_lambda2(alpha, seed, site, sweep, sg, &lam2);
+  if (n) *X0 = 1.0 - 2.0 * lam2;
+  return n;
 }
 
 /* SU(2) element X with density ~ exp(alpha X0) under Haar measure: X0 from
@@ -301,8 +310,8 @@ int or_kp_draw(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int s
  * phi = 2 pi u2). Returns the attempts used, 0 if the cap was hit. */
 int or_heatbath_su2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int sg,
                     double X[4]) {
-  double X0;
-  int n = or_kp_draw(alpha, seed, site, sweep, sg, &X0);
+  double lam2;
+  int n = kp_lambda2(alpha, seed, site, sweep, sg, &lam2);
   if (n == 0) return 0;
   const double two_pi = 6.283185307179586476925286766559;
   double d[4];
@@ -310,8 +319,10 @@ int or_heatbath_su2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, 
   double cth = 2.0 * d[0] - 1.0;
   double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
   double phi = two_pi * d[1];
-  double rad = sqrt(fmax(0.0, 1.0 - X0 * X0));
-  X[0] = X0;
+  /* sqrt(1 - X0^2) = 2 lambda sqrt(1 - lambda^2) for X0 = 1 - 2 lambda^2,
+   * written without the cancellation of 1 - X0^2 near X0 = 1 */
+  double rad = 2.0 * sqrt(lam2 * (1.0 - lam2));
+  X[0] = 1.0 - 2.0 * lam2;
   X[1] = rad * sth * cos(phi);
   X[2] = rad * sth * sin(phi);
   X[3] = rad * cth;

@@ -124,28 +124,35 @@ struct UpdHB {
     const T n = sqrt_t(n2);
     const T alpha = n / temp;
     const T two_pi = (T)6.283185307179586476925286766559;
-    T X0 = 2;
+    T lam2 = -1;
     for (uint32_t att = 0; att < kMaxAttempts; ++att) {
       const U4 r = philox4x32_10(site, sweep, kTagKP | (uint32_t)sg, att, k0, k1);
       const T u0 = unit_open<T>(r.v[0]), u1 = unit_open<T>(r.v[1]);
       const T u2 = unit_open<T>(r.v[2]), u3 = unit_open<T>(r.v[3]);
       const T cs = cos(two_pi * u1);
-      const T lam2 = -(log(u0) + cs * cs * log(u2)) / (2 * alpha);
-      if (u3 * u3 <= 1 - lam2) {
-        X0 = 1 - 2 * lam2;
+      const T l2 = -(log(u0) + cs * cs * log(u2)) / (2 * alpha);
+      if (u3 * u3 <= 1 - l2) {
+        lam2 = l2;
         break;
       }
     }
-    if (X0 > (T)1.5) return false;  // attempt cap: subgroup left unchanged
+    if (lam2 < 0) return false;  // attempt cap: subgroup left unchanged
     const U4 d = philox4x32_10(site, sweep, kTagDir | (uint32_t)sg, 0u, k0, k1);
     const T d0 = unit_open<T>(d.v[0]), d1 = unit_open<T>(d.v[1]);
     const T cth = 2 * d0 - 1;
     const T sth = sqrt_t(fmax(T(0), 1 - cth * cth));
     const T phi = two_pi * d1;
-    const T rad = sqrt_t(fmax(T(0), 1 - X0 * X0));
-    const T X[4] = {X0, rad * sth * cos(phi), rad * sth * sin(phi), rad * cth};
+    // sqrt(1 - X0^2) = 2 lambda sqrt(1 - lambda^2) for X0 = 1 - 2 lambda^2
+    const T rad = 2 * sqrt_t(lam2 * (1 - lam2));
+    const T X[4] = {1 - 2 * lam2, rad * sth * cos(phi), rad * sth * sin(phi), rad * cth};
     const T wh[4] = {w[0] / n, w[1] / n, w[2] / n, w[3] / n};
     qmul(X, wh, s);
+    // renormalise: keeps repeated low-precision draws on SU(2)
+    const T rn = rsqrt_t(s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + s[3] * s[3]);
+    s[0] *= rn;
+    s[1] *= rn;
+    s[2] *= rn;
+    s[3] *= rn;
     return true;
   }
 };
