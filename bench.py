@@ -49,7 +49,85 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP64-only comparison and the variant table")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in lanes per site")
+    ap.add_argument("--probe", action="store_true",
+                    help="kernel probe for profilers: bandwidth probes of known size, then "
+                         "20 sweeps of each storage variant on a generated input")
     return ap.parse_args()
+
+
+def stream_probes(ctx, torch, nbytes=2 * 1024 ** 3, reps=10):
+    """Copy, in-place read-modify-write and read-only streams of known size."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.zeros_like(a)
+    out = {}
+    for kind, name, moved in ((0, "copy", 2), (1, "rmw", 2), (2, "read", 1)):
+        ctx.stream_probe(a, b, nbytes, kind)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            ctx.stream_probe(a, b, nbytes, kind)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        out[name + "_GBps"] = round(reps * moved * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, b
+    return out
+
+
+def variant_rates(ctx, torch, gf, canon, dims, omega, n=100):
+    V = 1
+    for d in dims:
+        V *= d
+    var = {}
+    for prec, st in ((gf.FP32, gf.R12), (gf.FP32, gf.R18), (gf.FP64, gf.R12), (gf.FP64, gf.R18)):
+        g = gf.Geom.make(dims, prec, st)
+        f = ctx.empty_field(g)
+        ctx.pack(g, canon, f)
+        for _ in range(4):
+            ctx.sweep(f, g, gf.LANDAU, 0, omega)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for k in range(n):
+            ctx.sweep(f, g, gf.LANDAU, 0, omega)
+            ctx.sweep(f, g, gf.LANDAU, 1, omega)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        sups = V * n / (ms * 1e-3)
+        gbs = sups * 16 * st * prec / 1e9
+        name = ("fp32" if prec == gf.FP32 else "fp64") + ("_r12" if st == gf.R12 else "_r18")
+        var[name] = {"site_updates_per_s": round(sups, 0),
+                     "gflops": round(sups * FLOP_PER_SITE / 1e9, 1),
+                     "GBps": round(gbs, 1), "frac_peak": round(gbs / PEAK_HBM_GBS, 4),
+                     "us_per_half_sweep": round(1e3 * ms / (2 * n), 2),
+                     "variant": dict(zip(("lanes_per_site", "nontemporal"),
+                                         ctx.get_sweep_variant(prec, st)))}
+        del f
+    return var
+
+
+def probe_main(args):
+    """Short fixed workload for rocprofv3 runs (kernel trace or counters)."""
+    import torch
+
+    import inputs
+    import paper_1209_4008_amd as gf
+
+    dims = tuple(int(v) for v in args.dims.split(","))
+    ctx = gf.Context(0)
+    log("probe: stream probes (2 GiB, 10 reps each)")
+    res = {"probe": stream_probes(ctx, torch)}
+    canon = inputs.gpu_config0(dims, 0.3, args.seed)
+    torch.cuda.synchronize()
+    if not args.no_tune:
+        for prec, st in ((gf.FP32, gf.R12), (gf.FP32, gf.R18), (gf.FP64, gf.R12), (gf.FP64, gf.R18)):
+            ctx.autotune(gf.Geom.make(dims, prec, st), gf.LANDAU)
+    log("probe: 20 sweeps per storage variant on", dims)
+    res["variants"] = variant_rates(ctx, torch, gf, canon, dims, args.omega, n=20)
+    ctx.close()
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -57,6 +135,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.probe:
+        probe_main(args)
+        return
     import numpy as np
     import torch
 
@@ -88,6 +169,15 @@ def main():
     ghi = gf.Geom.make(dims, gf.FP64, gf.R12)
     U_lo = ctx.empty_field(glo)
     U_hi = ctx.empty_field(ghi)
+    tuning = {}
+    if not args.no_tune:
+        for g in (glo, ghi):
+            best, ms = ctx.autotune(g, gf.LANDAU)
+            name = ("fp32" if g.prec == gf.FP32 else "fp64") + "_r12"
+            tuning[name] = {"lanes_per_site": best[0], "nontemporal": best[1],
+                            "us_per_half_sweep": {f"tps{k[0]}_nt{k[1]}": round(v * 1e3, 2)
+                                                  for k, v in ms.items()}}
+            log(f"autotune {name}: {tuning[name]}")
     params = gf.fix_params(omega=args.omega, theta_target=args.theta_target,
                            theta_switch=args.theta_switch, max_sweeps=args.max_sweeps,
                            check_every=args.check_every, flags=gf.FLAG_TIMING)
@@ -145,47 +235,9 @@ def main():
         extras["mixed_speedup_vs_fp64"] = round(t64 / (ms_per_step * 1e-3), 4)
         extras["final_F_rel_diff_mixed_vs_fp64"] = abs(mixed.F - r64.F) / abs(r64.F)
         del gsave
-        # per-variant kernel rates: 100 sweeps each
-        var = {}
-        for prec, st in ((gf.FP32, gf.R12), (gf.FP32, gf.R18), (gf.FP64, gf.R12),
-                         (gf.FP64, gf.R18)):
-            g = gf.Geom.make(dims, prec, st)
-            f = ctx.empty_field(g)
-            ctx.pack(g, canon, f)
-            for _ in range(5):
-                ctx.sweep(f, g, gf.LANDAU, 0, args.omega)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            n = 100
-            e0.record(stream)
-            for k in range(n):
-                ctx.sweep(f, g, gf.LANDAU, 0, args.omega)
-                ctx.sweep(f, g, gf.LANDAU, 1, args.omega)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            sups = V * n / (ms * 1e-3)
-            gbs = sups * 16 * st * prec / 1e9
-            name = ("fp32" if prec == gf.FP32 else "fp64") + ("_r12" if st == gf.R12 else "_r18")
-            var[name] = {"site_updates_per_s": round(sups, 0), "gflops": round(sups * FLOP_PER_SITE / 1e9, 1),
-                         "GBps": round(gbs, 1), "frac_peak": round(gbs / PEAK_HBM_GBS, 4),
-                         "us_per_half_sweep": round(1e3 * ms / (2 * n), 2)}
-            del f
-        extras["variants"] = var
-        # plain copy of known size (calibrates achievable HBM bandwidth)
-        nbytes = 2 * 1024 ** 3
-        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            b.copy_(a)
-        e1.record()
-        torch.cuda.synchronize()
-        extras["copy_GBps"] = round(10 * 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
-        del a, b
+        extras["variants"] = variant_rates(ctx, torch, gf, canon, dims, args.omega)
+        extras.update(stream_probes(ctx, torch))
+    extras["autotune"] = tuning
 
     cpu = None
     if not args.no_cpu:

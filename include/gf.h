@@ -154,6 +154,33 @@ gf_status gf_anneal_sweep(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gau
 gf_status gf_philox(gf_ctx* ctx, const uint32_t* ctr_dev, uint64_t seed, uint32_t* out_dev,
                     int64_t n);
 
+/* ---- tuning --------------------------------------------------------------- */
+/* Variant of the sweep kernels for one (precision, storage) pair on this
+ * context: tps = lanes per site (1, 2 or 4; with k lanes each lane owns the
+ * forward and backward links of 4/k directions and the lanes add their parts
+ * of K(x)), nontemporal = 1 to mark the link loads and stores as streaming.
+ * tps = 0 / nontemporal = -1 restore the built-in defaults. */
+gf_status gf_set_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t tps,
+                               int32_t nontemporal);
+gf_status gf_get_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t* tps,
+                               int32_t* nontemporal);
+/* Autotuner: times the overrelaxation half-sweep for geom (its extents,
+ * precision and storage) for the six variants (tps 1, 2, 4) x (nontemporal 0,
+ * 1) on a scratch field (allocated and freed inside the call; the caller's
+ * fields are not touched), keeps the fastest on this context and returns it.
+ * ms_out (NULL or 6 floats, index 3*nontemporal + log2(tps)) receives the
+ * mean time per half-sweep of each. Synchronises the context stream. */
+gf_status gf_autotune(gf_ctx* ctx, const gf_geom* geom, int32_t gauge, int32_t* tps_out,
+                      int32_t* nt_out, float* ms_out);
+
+/* Bandwidth probe (measurement support): streams `bytes` (a multiple of 16)
+ * with 16-byte accesses, one per thread. kind 0: copy src -> dst; kind 1:
+ * in-place nontemporal read-modify-write of dst (dst[i] = 2 dst[i]); kind 2:
+ * read src only (one partial sum per 256 elements is written to dst, which
+ * must hold bytes/2048 doubles). Enqueued on the context
+ * stream; time it with events around the call. */
+gf_status gf_stream_probe(gf_ctx* ctx, const void* src, void* dst, size_t bytes, int32_t kind);
+
 /* ---- drivers (the while-theta loop of Alg. 1) ------------------------------- */
 #define GF_FLAG_TIMING 1u    /* record hipEvent kernel timings into the result */
 #define GF_FLAG_GRAPH 2u     /* replay the sweeps between checks as a hipGraph */

@@ -89,6 +89,12 @@ SIGNATURES = {
     "gf_anneal_sweep": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.c_double, C.c_uint64,
                                     C.c_uint64, C.c_int32]),
     "gf_philox": (C.c_int32, [_vp, _dp, C.c_uint64, _dp, C.c_int64]),
+    "gf_set_sweep_variant": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "gf_get_sweep_variant": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32)]),
+    "gf_autotune": (C.c_int32, [_vp, _gp, C.c_int32, C.POINTER(C.c_int32),
+                                C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "gf_stream_probe": (C.c_int32, [_vp, _dp, _dp, C.c_size_t, C.c_int32]),
     "gf_fix": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.POINTER(FixParams),
                            C.POINTER(FixResult)]),
     "gf_fix_mixed": (C.c_int32, [_vp, _dp, _gp, _dp, _gp, C.c_int32, C.POINTER(FixParams),
@@ -216,6 +222,30 @@ class Context:
 
     def philox(self, ctr, seed, out, n):
         return self._check(lib().gf_philox(self.h, _ptr(ctr), int(seed), _ptr(out), int(n)))
+
+    def set_sweep_variant(self, prec, storage, tps=0, nontemporal=-1):
+        return self._check(lib().gf_set_sweep_variant(self.h, int(prec), int(storage), int(tps),
+                                                      int(nontemporal)))
+
+    def get_sweep_variant(self, prec, storage):
+        t, n = C.c_int32(0), C.c_int32(0)
+        self._check(lib().gf_get_sweep_variant(self.h, int(prec), int(storage), C.byref(t),
+                                               C.byref(n)))
+        return t.value, n.value
+
+    def autotune(self, geom, gauge=LANDAU):
+        """Time the six sweep variants for geom; keep the fastest on this context.
+        Returns ((tps, nontemporal), {(tps, nontemporal): ms per half-sweep})."""
+        t, n = C.c_int32(0), C.c_int32(0)
+        ms = (C.c_float * 6)()
+        self._check(lib().gf_autotune(self.h, C.byref(geom), int(gauge), C.byref(t), C.byref(n),
+                                      ms))
+        table = {(1 << (k % 3), k // 3): ms[k] for k in range(6)}
+        return (t.value, n.value), table
+
+    def stream_probe(self, src, dst, nbytes, kind):
+        return self._check(lib().gf_stream_probe(self.h, _ptr(src), _ptr(dst), int(nbytes),
+                                                 int(kind)))
 
     def fix(self, U, geom, gauge, params):
         r = FixResult()

@@ -25,6 +25,8 @@ struct gf_ctx {
   double* host_out = nullptr; // pinned copy of dev_out
   size_t out_cap = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  int tps[2][2] = {{0, 0}, {0, 0}};  // lanes per site [fp64][r18]; 0 = default
+  int nt[2][2] = {{-1, -1}, {-1, -1}};  // nontemporal accesses [fp64][r18]; -1 = default
 };
 
 static char g_create_err[512] = "no error";
@@ -318,19 +320,60 @@ gf_status gf_reunitarize(gf_ctx* c, void* U, const gf_geom* g) {
   return launch_check(c, "gf_reunitarize");
 }
 
+// lanes per site and nontemporal accesses of the sweep kernels, per
+// (precision, storage); the autotuner overwrites these per context
+static int default_tps(const gf_geom* g) { return g->prec == GF_FP64 ? 4 : 2; }
+static int default_nt(const gf_geom* g) { return g->prec == GF_FP64 ? 1 : 0; }
+
+template <typename T, int NC, int GAUGE, class Upd, bool NT>
+static void launch_update_v(gf_ctx* c, int tps, void* U, const Lat& L, int parity, const Upd& upd) {
+  const uint64_t n = (uint64_t)L.vh * (uint64_t)tps;
+  const dim3 grid(blocks_for(n));
+  switch (tps) {
+    case 1:
+      hipLaunchKernelGGL((k_update_half<T, NC, GAUGE, Upd, 1, NT>), grid, dim3(kBlock), 0, c->stream,
+                         (v2<T>*)U, L, parity, upd);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_update_half<T, NC, GAUGE, Upd, 2, NT>), grid, dim3(kBlock), 0, c->stream,
+                         (v2<T>*)U, L, parity, upd);
+      break;
+    default:
+      hipLaunchKernelGGL((k_update_half<T, NC, GAUGE, Upd, 4, NT>), grid, dim3(kBlock), 0, c->stream,
+                         (v2<T>*)U, L, parity, upd);
+      break;
+  }
+}
+
+template <typename T, int NC, int GAUGE, class Upd>
+static void launch_update_tps(gf_ctx* c, int tps, int nt, void* U, const Lat& L, int parity,
+                              const Upd& upd) {
+  if (nt)
+    launch_update_v<T, NC, GAUGE, Upd, true>(c, tps, U, L, parity, upd);
+  else
+    launch_update_v<T, NC, GAUGE, Upd, false>(c, tps, U, L, parity, upd);
+}
+
+static int ctx_tps(const gf_ctx* c, const gf_geom* g) {
+  const int t = c->tps[g->prec == GF_FP64][g->storage == GF_R18];
+  return t > 0 ? t : default_tps(g);
+}
+static int ctx_nt(const gf_ctx* c, const gf_geom* g) {
+  const int t = c->nt[g->prec == GF_FP64][g->storage == GF_R18];
+  return t >= 0 ? t : default_nt(g);
+}
+
 template <class UpdF>
 static gf_status launch_update(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge,
                                int32_t parity, UpdF make_upd, const char* what) {
   const Lat L = make_lat(g);
-  const dim3 grid(blocks_for(L.vh));
+  const int tps = ctx_tps(c, g), nt = ctx_nt(c, g);
   with_type(g, [&]<typename T, int NC>() {
     auto upd = make_upd.template operator()<T>();
     if (gauge == GF_LANDAU)
-      hipLaunchKernelGGL((k_update_half<T, NC, kLandau, decltype(upd)>), grid, dim3(kBlock), 0,
-                         c->stream, (v2<T>*)U, L, (int)parity, upd);
+      launch_update_tps<T, NC, kLandau>(c, tps, nt, U, L, (int)parity, upd);
     else
-      hipLaunchKernelGGL((k_update_half<T, NC, kCoulomb, decltype(upd)>), grid, dim3(kBlock), 0,
-                         c->stream, (v2<T>*)U, L, (int)parity, upd);
+      launch_update_tps<T, NC, kCoulomb>(c, tps, nt, U, L, (int)parity, upd);
   });
   return launch_check(c, what);
 }
@@ -471,6 +514,111 @@ gf_status gf_philox(gf_ctx* c, const uint32_t* ctr, uint64_t seed, uint32_t* out
   hipLaunchKernelGGL(k_philox, dim3(blocks_for((uint64_t)n)), dim3(kBlock), 0, c->stream, ctr, out,
                      n, (uint32_t)seed, (uint32_t)(seed >> 32));
   return launch_check(c, "gf_philox");
+}
+
+// ---------------------------------------------------------------------------
+// tuning
+// ---------------------------------------------------------------------------
+static int tps_ok(int32_t t) { return t == 1 || t == 2 || t == 4; }
+static int ps_ok(int32_t prec, int32_t storage) {
+  return (prec == GF_FP32 || prec == GF_FP64) && (storage == GF_R12 || storage == GF_R18);
+}
+
+gf_status gf_set_sweep_variant(gf_ctx* c, int32_t prec, int32_t storage, int32_t tps,
+                               int32_t nontemporal) {
+  if (!c) return GF_ERR_ARG;
+  if (!ps_ok(prec, storage)) return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: bad precision or storage");
+  if (tps != 0 && !tps_ok(tps)) return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: tps must be 0, 1, 2 or 4");
+  if (nontemporal < -1 || nontemporal > 1) return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: nontemporal must be -1, 0 or 1");
+  c->tps[prec == GF_FP64][storage == GF_R18] = tps;
+  c->nt[prec == GF_FP64][storage == GF_R18] = nontemporal;
+  return GF_OK;
+}
+
+gf_status gf_get_sweep_variant(gf_ctx* c, int32_t prec, int32_t storage, int32_t* tps,
+                               int32_t* nontemporal) {
+  if (!c || !tps || !nontemporal) return GF_ERR_ARG;
+  if (!ps_ok(prec, storage)) return fail(c, GF_ERR_ARG, "gf_get_sweep_variant: bad precision or storage");
+  gf_geom g = {2, 2, 2, 2, prec, storage};
+  *tps = ctx_tps(c, &g);
+  *nontemporal = ctx_nt(c, &g);
+  return GF_OK;
+}
+
+gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, int32_t* tps_out,
+                      int32_t* nt_out, float* ms_out) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_autotune");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_autotune: bad gauge");
+  const size_t bytes = gf_field_bytes(g);
+  void* scratch = nullptr;
+  HIP_OR_FAIL(c, hipMalloc(&scratch, bytes));
+  const Lat L = make_lat(g);
+  with_type(g, [&]<typename T, int NC>() {
+    hipLaunchKernelGGL((k_fill_unit<T, NC>), dim3(blocks_for(L.vh), 8), dim3(kBlock), 0,
+                       c->stream, (v2<T>*)scratch, L.vh);
+  });
+  const int reps = 20;
+  float best = 1e30f;
+  int best_tps = default_tps(g), best_nt = default_nt(g);
+  const int i64 = g->prec == GF_FP64, i18 = g->storage == GF_R18;
+  const int saved_tps = c->tps[i64][i18], saved_nt = c->nt[i64][i18];
+  gf_status st = GF_OK;
+  for (int k = 0; k < 6 && st == GF_OK; ++k) {
+    c->tps[i64][i18] = 1 << (k % 3);
+    c->nt[i64][i18] = k / 3;
+    for (int w = 0; w < 2 && st == GF_OK; ++w) st = gf_sweep(c, scratch, g, gauge, w & 1, 1.5);
+    if (st != GF_OK) break;
+    if (hipEventRecord(c->ev[0], c->stream) != hipSuccess) st = GF_ERR_HIP;
+    for (int w = 0; w < 2 * reps && st == GF_OK; ++w) st = gf_sweep(c, scratch, g, gauge, w & 1, 1.5);
+    if (st != GF_OK) break;
+    float ms = 0;
+    if (hipEventRecord(c->ev[1], c->stream) != hipSuccess || hipEventSynchronize(c->ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) != hipSuccess) {
+      st = fail(c, GF_ERR_HIP, "gf_autotune: event timing failed");
+      break;
+    }
+    ms /= (float)(2 * reps);
+    if (ms_out) ms_out[k] = ms;
+    if (ms < best) {
+      best = ms;
+      best_tps = 1 << (k % 3);
+      best_nt = k / 3;
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(scratch);
+  if (st != GF_OK) {
+    c->tps[i64][i18] = saved_tps;
+    c->nt[i64][i18] = saved_nt;
+    return st;
+  }
+  c->tps[i64][i18] = best_tps;
+  c->nt[i64][i18] = best_nt;
+  if (tps_out) *tps_out = best_tps;
+  if (nt_out) *nt_out = best_nt;
+  return GF_OK;
+}
+
+gf_status gf_stream_probe(gf_ctx* c, const void* src, void* dst, size_t bytes, int32_t kind) {
+  CHECK_CTX(c);
+  if (!dst || (kind != 1 && !src) || (bytes % 16) != 0 || kind < 0 || kind > 2)
+    return fail(c, GF_ERR_ARG, "gf_stream_probe: bad arguments");
+  const size_t n = bytes / 16;
+  if (n == 0) return GF_OK;
+  if (n > ((size_t)1 << 36)) return fail(c, GF_ERR_ARG, "gf_stream_probe: too large");
+  const unsigned grid = blocks_for(n);
+  if (kind == 2 && bytes < (size_t)grid * sizeof(double))
+    return fail(c, GF_ERR_ARG, "gf_stream_probe: dst too small for the partial sums");
+  if (kind == 0)
+    hipLaunchKernelGGL(k_probe_copy, dim3(grid), dim3(kBlock), 0, c->stream, (const double2*)src,
+                       (double2*)dst, n);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_probe_rmw, dim3(grid), dim3(kBlock), 0, c->stream, (v2<double>*)dst, n);
+  else
+    hipLaunchKernelGGL(k_probe_read, dim3(grid), dim3(kBlock), 0, c->stream, (const double2*)src,
+                       (double*)dst, n);
+  return launch_check(c, "gf_stream_probe");
 }
 
 // ---------------------------------------------------------------------------

@@ -126,18 +126,21 @@ __device__ __forceinline__ void rebuild_row2(Su3<T>& A) {
 // ---------------------------------------------------------------------------
 // device layout: elem(p, mu, c, h) at ((p*4 + mu)*NC + c)*vh + h
 // ---------------------------------------------------------------------------
-template <typename T, int NC>
+// NT = true marks the accesses nontemporal (streaming: each link is read and
+// written once per half-sweep, with no reuse to keep in the caches)
+template <typename T, int NC, bool NT = false>
 __device__ __forceinline__ void load_link(const v2<T>* __restrict__ blk, uint32_t vh, uint32_t h,
                                           Su3<T>& A) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const v2<T> v = blk[(size_t)c * vh + h];
+    const v2<T>* p = blk + (size_t)c * vh + h;
+    const v2<T> v = NT ? __builtin_nontemporal_load(p) : *p;
     A.e[c / 3][c % 3] = cx<T>(v.x, v.y);
   }
   if (NC == 6) rebuild_row2(A);
 }
 
-template <typename T, int NC>
+template <typename T, int NC, bool NT = false>
 __device__ __forceinline__ void store_link(v2<T>* __restrict__ blk, uint32_t vh, uint32_t h,
                                            const Su3<T>& A) {
 #pragma unroll
@@ -145,7 +148,11 @@ __device__ __forceinline__ void store_link(v2<T>* __restrict__ blk, uint32_t vh,
     v2<T> v;
     v.x = A.e[c / 3][c % 3].re;
     v.y = A.e[c / 3][c % 3].im;
-    blk[(size_t)c * vh + h] = v;
+    v2<T>* p = blk + (size_t)c * vh + h;
+    if (NT)
+      __builtin_nontemporal_store(v, p);
+    else
+      *p = v;
   }
 }
 

@@ -167,34 +167,98 @@ __device__ __forceinline__ void subgroup_step(Su3<T>& K, Su3<T>& G, uint32_t sit
 }
 
 // ---------------------------------------------------------------------------
-// half-sweep: one thread per site of the given parity
+// lane exchange inside a quad (DPP quad_perm): value of lane (l ^ MASK)
 // ---------------------------------------------------------------------------
-template <typename T, int NC, int GAUGE, class Upd>
+template <int MASK>
+__device__ __forceinline__ int quad_xor_i(int v) {
+  // quad_perm selectors: xor 1 -> [1,0,3,2] = 0xB1, xor 2 -> [2,3,0,1] = 0x4E
+  constexpr int ctrl = (MASK == 1) ? 0xB1 : 0x4E;
+  return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, false);
+}
+template <int MASK>
+__device__ __forceinline__ float quad_xor(float v) {
+  return __builtin_bit_cast(float, quad_xor_i<MASK>(__builtin_bit_cast(int, v)));
+}
+template <int MASK>
+__device__ __forceinline__ double quad_xor(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = quad_xor_i<MASK>((int)(uint32_t)b);
+  const int hi = quad_xor_i<MASK>((int)(uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// sum of K over the TPS lanes of one site; every lane ends with the same bits
+// (each step adds two partial sums, and addition is commutative)
+template <typename T, int TPS>
+__device__ __forceinline__ void lane_sum(Su3<T>& K) {
+  if (TPS >= 2) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        K.e[a][b].re += quad_xor<1>(K.e[a][b].re);
+        K.e[a][b].im += quad_xor<1>(K.e[a][b].im);
+      }
+  }
+  if (TPS >= 4) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        K.e[a][b].re += quad_xor<2>(K.e[a][b].re);
+        K.e[a][b].im += quad_xor<2>(K.e[a][b].im);
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// half-sweep over the sites of one parity, TPS lanes per site (1, 2 or 4):
+// lane r of a site owns the directions mu = r*(4/TPS) ... (r+1)*(4/TPS)-1,
+// i.e. their forward links U_mu(x) and backward links U_mu(x-mu). The lanes
+// form their partial sums of K, add them across the site's lanes, compute the
+// same subgroup transformations, and each updates and stores its own links.
+// ---------------------------------------------------------------------------
+template <typename T, int NC, int GAUGE, class Upd, int TPS, bool NT>
 __global__ __launch_bounds__(kBlock) void k_update_half(v2<T>* __restrict__ U, const Lat L,
                                                         const int parity, const Upd upd) {
-  const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
-  if (h >= L.vh) return;
+  static_assert(TPS == 1 || TPS == 2 || TPS == 4, "lanes per site");
+  constexpr int DPL = 4 / TPS;  // directions per lane
+  const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t h = gid / TPS;
+  const int r = (int)(gid % TPS);
+  if (h >= L.vh) return;  // a site's lanes are all in range or all out
   const Site S = site_of(L, h, parity);
   const size_t blk = (size_t)NC * L.vh;
   v2<T>* __restrict__ Pf = U + (size_t)parity * 4 * blk;
   v2<T>* __restrict__ Pb = U + (size_t)(1 - parity) * 4 * blk;
-  uint32_t hb[4];
-  Su3<T> Uf[4], Ub[4];
+  uint32_t hb[DPL];
+  Su3<T> Uf[DPL], Ub[DPL];
 #pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-    hb[mu] = back_h(L, h, S, mu);
-    load_link<T, NC>(Pf + mu * blk, L.vh, h, Uf[mu]);
-    load_link<T, NC>(Pb + mu * blk, L.vh, hb[mu], Ub[mu]);
+  for (int d = 0; d < DPL; ++d) {
+    const int mu = r * DPL + d;
+    hb[d] = back_h(L, h, S, mu);
+    load_link<T, NC, NT>(Pf + mu * blk, L.vh, h, Uf[d]);
+    load_link<T, NC, NT>(Pb + mu * blk, L.vh, hb[d], Ub[d]);
   }
   Su3<T> K;
   set_zero(K);
 #pragma unroll
-  for (int mu = FirstDir<GAUGE>::value; mu < 4; ++mu)
+  for (int d = 0; d < DPL; ++d) {
+    const int mu = r * DPL + d;
+    if (TPS == 1 && mu < FirstDir<GAUGE>::value) continue;
+    const T on = (mu >= FirstDir<GAUGE>::value) ? T(1) : T(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b)
-        K.e[a][b] = cadd(K.e[a][b], cadd(Uf[mu].e[a][b], cconj(Ub[mu].e[b][a])));
+      for (int b = 0; b < 3; ++b) {
+        const Cx<T> v = cadd(Uf[d].e[a][b], cconj(Ub[d].e[b][a]));
+        if (TPS == 1)
+          K.e[a][b] = cadd(K.e[a][b], v);
+        else
+          K.e[a][b] = cx(fma(on, v.re, K.e[a][b].re), fma(on, v.im, K.e[a][b].im));
+      }
+  }
+  lane_sum<T, TPS>(K);
   Su3<T> G;
   set_unit(G);
   const uint32_t site = 2 * h + S.xodd;
@@ -203,27 +267,28 @@ __global__ __launch_bounds__(kBlock) void k_update_half(v2<T>* __restrict__ U, c
   subgroup_step<T, Upd, 1, 2, 2>(K, G, site, upd);
   constexpr int R = NC / 3;  // stored rows
 #pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
+  for (int d = 0; d < DPL; ++d) {
+    const int mu = r * DPL + d;
     Su3<T> A;
 #pragma unroll
     for (int a = 0; a < R; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        Cx<T> f = cmul(G.e[a][0], Uf[mu].e[0][b]);
-        f = cmac(f, G.e[a][1], Uf[mu].e[1][b]);
-        A.e[a][b] = cmac(f, G.e[a][2], Uf[mu].e[2][b]);
+        Cx<T> f = cmul(G.e[a][0], Uf[d].e[0][b]);
+        f = cmac(f, G.e[a][1], Uf[d].e[1][b]);
+        A.e[a][b] = cmac(f, G.e[a][2], Uf[d].e[2][b]);
       }
-    store_link<T, NC>(Pf + mu * blk, L.vh, h, A);
+    store_link<T, NC, NT>(Pf + mu * blk, L.vh, h, A);
 #pragma unroll
     for (int a = 0; a < R; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
         Cx<T> f = cx<T>(0, 0);
-        f = cmac_cb(f, Ub[mu].e[a][0], G.e[b][0]);
-        f = cmac_cb(f, Ub[mu].e[a][1], G.e[b][1]);
-        A.e[a][b] = cmac_cb(f, Ub[mu].e[a][2], G.e[b][2]);
+        f = cmac_cb(f, Ub[d].e[a][0], G.e[b][0]);
+        f = cmac_cb(f, Ub[d].e[a][1], G.e[b][1]);
+        A.e[a][b] = cmac_cb(f, Ub[d].e[a][2], G.e[b][2]);
       }
-    store_link<T, NC>(Pb + mu * blk, L.vh, hb[mu], A);
+    store_link<T, NC, NT>(Pb + mu * blk, L.vh, hb[d], A);
   }
 }
 
@@ -485,6 +550,45 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const v2<T>* __restrict__ src
     q[2 * c] = A.e[c / 3][c % 3].re;
     q[2 * c + 1] = A.e[c / 3][c % 3].im;
   }
+}
+
+// the unit field in the device layout (scratch fields of the autotuner)
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_fill_unit(v2<T>* __restrict__ U, const uint32_t vh) {
+  const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+  if (h >= vh) return;
+  const size_t pm = blockIdx.y;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    v2<T> v;
+    v.x = (c % 4 == 0) ? T(1) : T(0);  // c = 0, 4, 8 are the diagonal
+    v.y = 0;
+    U[(pm * NC + c) * vh + h] = v;
+  }
+}
+
+// bandwidth probes: 16-byte elements, one per thread
+__global__ __launch_bounds__(kBlock) void k_probe_copy(const double2* __restrict__ a,
+                                                       double2* __restrict__ b, const size_t n) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+__global__ __launch_bounds__(kBlock) void k_probe_rmw(v2<double>* __restrict__ b, const size_t n) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  v2<double> v = __builtin_nontemporal_load(b + i);
+  v.x *= 2.0;
+  v.y *= 2.0;
+  __builtin_nontemporal_store(v, b + i);
+}
+__global__ __launch_bounds__(kBlock) void k_probe_read(const double2* __restrict__ a,
+                                                       double* __restrict__ out, const size_t n) {
+  __shared__ double lds[kBlock / 64];
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  double acc = 0;
+  if (i < n) acc = a[i].x + a[i].y;
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) out[blockIdx.x] = acc;
 }
 
 __global__ __launch_bounds__(kBlock) void k_philox(const uint32_t* __restrict__ ctr,

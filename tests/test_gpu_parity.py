@@ -68,6 +68,26 @@ def test_pack_unpack_roundtrip(ctx, prec, storage):
 def test_half_sweep_parity(ctx, dims, prec, storage, gauge):
     U = inputs.config0(dims, 0.6, 11)
     say("half-sweep", dims, prec, storage, gauge)
+    _half_sweep_check(ctx, U, prec, storage, gauge)
+
+
+@pytest.mark.parametrize("nt", [0, 1])
+@pytest.mark.parametrize("tps", [1, 2, 4])
+@pytest.mark.parametrize("gauge", [gf.LANDAU, gf.COULOMB])
+@pytest.mark.parametrize("prec,storage", COMBOS)
+@pytest.mark.parametrize("dims", [(6, 4, 2, 10), (4, 6, 8, 10)])
+def test_half_sweep_parity_variants(ctx, dims, prec, storage, gauge, tps, nt):
+    """Every variant of the sweep kernel (lanes per site x nontemporal) against the oracle."""
+    U = inputs.config0(dims, 0.6, 17)
+    say("half-sweep variant", tps, nt, dims, prec, storage, gauge)
+    ctx.set_sweep_variant(prec, storage, tps, nt)
+    try:
+        _half_sweep_check(ctx, U, prec, storage, gauge)
+    finally:
+        ctx.set_sweep_variant(prec, storage, 0, -1)
+
+
+def _half_sweep_check(ctx, U, prec, storage, gauge):
     f, g = upload(ctx, U, prec, storage)
     ref = oracle_input(U, prec, storage)
     for p in (0, 1):
