@@ -3,10 +3,12 @@
 Workload (default): a 32^4 SU(3) configuration from a quenched Wilson-action
 heatbath at beta = 6.0 (cold start, 300 sweeps, Philox seed 2), generated on
 the GPU before the timed region. One benchmark step is the whole hot path for
-that configuration: pack the canonical FP64 field into the FP32 12-real
-device layout, overrelaxation (omega = 1.7) with a check of F and theta every
-100 sweeps until theta < 1e-6, FP64 reunitarising conversion to the FP64
-12-real layout, FP64 sweeps until theta < 1e-14.
+that configuration: pack the canonical FP64 field into the FP64 12-real
+device layout, conversion to FP32, FP32 overrelaxation
+(omega = 1.7) with a check of F and theta every 100 sweeps until
+theta < 1e-6 while the accumulated gauge transformation is tracked, that
+transformation applied in FP64 to the FP64 input, FP64 sweeps until
+theta < 1e-14.
 
 value = site updates per second of the whole step (V x sweeps / step time).
 Also reported: the pure-FP64 time to theta < 1e-14 on the same input, the
@@ -49,7 +51,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP64-only comparison and the variant table")
-    ap.add_argument("--no-tune", action="store_true", help="keep the built-in lanes per site")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in sweep variants")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch the sweeps between checks one by one instead of replaying a "
+                         "captured hipGraph")
     ap.add_argument("--probe", action="store_true",
                     help="kernel probe for profilers: bandwidth probes of known size, then "
                          "20 sweeps of each storage variant on a generated input")
@@ -108,6 +113,19 @@ def variant_rates(ctx, torch, gf, canon, dims, omega, n=100):
     return var
 
 
+def hbm_traffic(kname, dims):
+    """HBM bytes per launch of kname from the committed counter summary, or None
+    when there is none for this lattice or the kernel sources changed since."""
+    from paper_1209_4008_amd import prof_summary
+
+    path = os.path.join(ROOT, "profiles", "sweep_hbm_counters_%s.md" % "x".join(map(str, dims)))
+    data = prof_summary.load_counters(path)
+    if not data or data.get("kernel_source_hash") != prof_summary.kernel_source_hash():
+        return None
+    k = data["kernels"].get(kname)
+    return round(k["traffic_bytes"]) if k else None
+
+
 def probe_main(args):
     """Short fixed workload for rocprofv3 runs (kernel trace or counters)."""
     import torch
@@ -123,7 +141,11 @@ def probe_main(args):
     torch.cuda.synchronize()
     if not args.no_tune:
         for prec, st in ((gf.FP32, gf.R12), (gf.FP32, gf.R18), (gf.FP64, gf.R12), (gf.FP64, gf.R18)):
-            ctx.autotune(gf.Geom.make(dims, prec, st), gf.LANDAU)
+            g = gf.Geom.make(dims, prec, st)
+            f = ctx.empty_field(g)
+            ctx.pack(g, canon, f)
+            ctx.autotune(g, gf.LANDAU, U_like=f)
+            del f
     log("probe: 20 sweeps per storage variant on", dims)
     res["variants"] = variant_rates(ctx, torch, gf, canon, dims, args.omega, n=20)
     ctx.close()
@@ -171,19 +193,21 @@ def main():
     U_hi = ctx.empty_field(ghi)
     tuning = {}
     if not args.no_tune:
-        for g in (glo, ghi):
-            best, ms = ctx.autotune(g, gf.LANDAU)
+        for g, f in ((glo, U_lo), (ghi, U_hi)):
+            ctx.pack(g, canon, f)
+            best, ms = ctx.autotune(g, gf.LANDAU, U_like=f)
             name = ("fp32" if g.prec == gf.FP32 else "fp64") + "_r12"
             tuning[name] = {"lanes_per_site": best[0], "nontemporal": best[1],
                             "us_per_half_sweep": {f"tps{k[0]}_nt{k[1]}": round(v * 1e3, 2)
                                                   for k, v in ms.items()}}
             log(f"autotune {name}: {tuning[name]}")
+    flags = gf.FLAG_TIMING | (0 if args.no_graph else gf.FLAG_GRAPH)
     params = gf.fix_params(omega=args.omega, theta_target=args.theta_target,
                            theta_switch=args.theta_switch, max_sweeps=args.max_sweeps,
-                           check_every=args.check_every, flags=gf.FLAG_TIMING)
+                           check_every=args.check_every, flags=flags)
 
     def step():
-        ctx.pack(glo, canon, U_lo)
+        ctx.pack(ghi, canon, U_hi)
         return ctx.fix_mixed(U_lo, glo, U_hi, ghi, gf.LANDAU, params)
 
     for k in range(args.warmup):
@@ -206,15 +230,20 @@ def main():
     # ---- dominant kernel: HIP-event timings of the sweep launches in the timed steps ----
     kms = [sum(r.kernel_ms[i] for r in results) for i in range(4)]
     kn = [sum(r.kernel_launches[i] for r in results) for i in range(4)]
-    bytes_per_site = {0: 16 * 12 * 4, 1: 16 * 12 * 8}  # FP32 R12, FP64 R12
+    # FP32 R12 sweep with the gauge transformation tracked (+2 x 12 reals), FP64 R12 sweep
+    bytes_per_site = {0: 16 * 12 * 4 + 2 * 12 * 4, 1: 16 * 12 * 8}
     dom = 0 if kms[0] >= kms[1] else 1
     per_launch_bytes = (V // 2) * bytes_per_site[dom]
     avg_ms = kms[dom] / max(kn[dom], 1)
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    tps, nt = ctx.get_sweep_variant(gf.FP32 if dom == 0 else gf.FP64, gf.R12)
+    kname = "k_update_half<%s,6,0,UpdOR,%d,%s,%s>" % (
+        "float" if dom == 0 else "double", tps, "true" if nt else "false",
+        "true" if dom == 0 else "false")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                "kernel": "k_update_half<%s,R12,Landau,OR>" % ("float" if dom == 0 else "double"),
-                "avg_launch_us": round(avg_ms * 1e3, 2), "launches": kn[dom],
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": hbm_traffic(kname, dims),
+                "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 3), "launches": kn[dom],
                 "bytes_per_launch": per_launch_bytes}
 
     extras = {}

@@ -166,12 +166,14 @@ gf_status gf_get_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32
                                int32_t* nontemporal);
 /* Autotuner: times the overrelaxation half-sweep for geom (its extents,
  * precision and storage) for the six variants (tps 1, 2, 4) x (nontemporal 0,
- * 1) on a scratch field (allocated and freed inside the call; the caller's
- * fields are not touched), keeps the fastest on this context and returns it.
- * ms_out (NULL or 6 floats, index 3*nontemporal + log2(tps)) receives the
- * mean time per half-sweep of each. Synchronises the context stream. */
-gf_status gf_autotune(gf_ctx* ctx, const gf_geom* geom, int32_t gauge, int32_t* tps_out,
-                      int32_t* nt_out, float* ms_out);
+ * 1) on a scratch field (allocated and freed inside the call) that starts as
+ * a copy of U_like (a device field of geom; NULL: the unit field), keeps the
+ * fastest on this context and returns it. The caller's fields are not
+ * modified. ms_out (NULL or 6 floats, index 3*nontemporal + log2(tps))
+ * receives the mean time per half-sweep of each. Synchronises the context
+ * stream. */
+gf_status gf_autotune(gf_ctx* ctx, const gf_geom* geom, int32_t gauge, const void* U_like,
+                      int32_t* tps_out, int32_t* nt_out, float* ms_out);
 
 /* Bandwidth probe (measurement support): streams `bytes` (a multiple of 16)
  * with 16-byte accesses, one per thread. kind 0: copy src -> dst; kind 1:
@@ -184,6 +186,7 @@ gf_status gf_stream_probe(gf_ctx* ctx, const void* src, void* dst, size_t bytes,
 /* ---- drivers (the while-theta loop of Alg. 1) ------------------------------- */
 #define GF_FLAG_TIMING 1u    /* record hipEvent kernel timings into the result */
 #define GF_FLAG_GRAPH 2u     /* replay the sweeps between checks as a hipGraph */
+#define GF_FLAG_NO_TRACK 4u  /* gf_fix_mixed: do not track g in the FP32 phase   */
 
 typedef struct {
   double omega;            /* overrelaxation parameter, [1, 2)                         */
@@ -193,30 +196,49 @@ typedef struct {
   int32_t check_every;     /* sweeps between checks (Sec. 4.1 uses 100)                */
   int32_t reunit_at_check; /* reunitarise before every check after the first           */
   uint32_t flags;          /* GF_FLAG_*                                                */
+  /* simulated annealing before the overrelaxation (Sec. 1: a preconditioner
+   * that raises the chance of reaching the global maximum of F) */
+  int32_t sa_steps;        /* 0: none; else steps k = 0..sa_steps-1 of gf_anneal_sweep */
+  int32_t sa_micro;        /* microcanonical sweeps per step                           */
+  int32_t sa_reunit_every; /* reunitarise after every this many steps (0: never)       */
+  int32_t sa_reserved;     /* must be 0                                                */
+  double sa_T0, sa_T1;     /* linear schedule T_k = T0 + (T1 - T0) k / (sa_steps - 1)  */
+  uint64_t seed;           /* Philox key of the heatbath draws (sweep index = k)       */
 } gf_fix_params;
 
 typedef struct {
   int32_t status;          /* GF_OK or GF_NOT_CONVERGED (or the error)           */
-  int32_t sweeps;          /* total sweeps (RED + BLACK = 1 sweep)               */
+  int32_t sweeps;          /* total overrelaxation sweeps (RED + BLACK = 1)      */
   int32_t sweeps_lo;       /* gf_fix_mixed: sweeps of the FP32 phase              */
   int32_t checks;          /* number of F/theta evaluations                       */
   double F, theta;         /* at the last check (Coulomb: mean F, max theta)      */
   double theta_at_switch;  /* gf_fix_mixed: theta when the FP32 phase ended        */
   double wall_ms;          /* host wall time of the call                          */
   /* GF_FLAG_TIMING: kernel time (ms) and launches: [0] FP32 sweeps, [1] FP64
-   * sweeps, [2] measurement, [3] reunitarisation and conversion */
-  double kernel_ms[4];
-  int64_t kernel_launches[4];
+   * sweeps, [2] measurement, [3] reunitarisation and conversion, [4]
+   * annealing (heatbath and microcanonical half-sweeps), [5] reserved */
+  double kernel_ms[6];
+  int64_t kernel_launches[6];
+  int32_t sa_steps;        /* annealing steps done                                 */
+  int32_t reserved;
 } gf_fix_result;
 
-/* Sweeps U (in geom's precision) with a check (reunitarise, F, theta)
- * before the first sweep and every check_every sweeps until theta <
- * theta_target or max_sweeps. Synchronises the context stream. */
+/* Runs the annealing schedule of params (if sa_steps > 0), then sweeps U (in
+ * geom's precision) with a check (reunitarise, F, theta) before the first
+ * sweep and every check_every sweeps until theta < theta_target or
+ * max_sweeps. Synchronises the context stream. */
 gf_status gf_fix(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gauge,
                  const gf_fix_params* params, gf_fix_result* result);
-/* Mixed precision: sweeps U_lo (FP32) until theta < theta_switch, converts it
- * into U_hi (FP64) with FP64 Gram-Schmidt, then sweeps U_hi until
- * theta < theta_target. U_lo holds the input and is overwritten. */
+/* Mixed precision. U_hi (FP64) holds the input and receives the result;
+ * U_lo (FP32, same extents, must not overlap U_hi) is workspace. The input is
+ * converted to FP32 and swept until theta < theta_switch while the
+ * accumulated site transformations g(x) are tracked (FP32, held by the
+ * context); then g is projected onto SU(3) in FP64 and applied to the FP64
+ * input, U_hi <- g(x) U_hi g(x+mu)^dag, so the FP64 phase starts exactly on
+ * the gauge orbit of the input, and U_hi is swept until theta <
+ * theta_target. With GF_FLAG_NO_TRACK the FP32 field itself is converted back
+ * (reunitarised in FP64) instead; its gauge-invariant content then carries
+ * the FP32 rounding of the first phase. */
 gf_status gf_fix_mixed(gf_ctx* ctx, void* U_lo, const gf_geom* geom_lo, void* U_hi,
                        const gf_geom* geom_hi, int32_t gauge, const gf_fix_params* params,
                        gf_fix_result* result);

@@ -39,6 +39,8 @@ def lib():
             "or_local_K": (None, [d, i32p, C.c_int, C.c_int64, d]),
             "or_sweep": (C.c_int, [d, i32p, C.c_int, C.c_int, C.c_double]),
             "or_update_sites": (C.c_int, [d, i32p, C.c_int, C.c_double, i64p, C.c_int64]),
+            "or_heatbath_sites": (C.c_int, [d, i32p, C.c_int, C.c_double, C.c_uint64,
+                                            C.c_uint64, i64p, C.c_int64]),
             "or_functional": (C.c_double, [d, i32p, C.c_int, d]),
             "or_functional_raw": (C.c_double, [d, i32p, C.c_int]),
             "or_theta_A": (C.c_double, [d, i32p, C.c_int, d]),
@@ -130,6 +132,15 @@ def update_sites(U, gauge, omega, sites):
                                sites.ctypes.data_as(C.POINTER(C.c_int64)), int(sites.size))
     if rc != 0:
         raise ValueError("or_update_sites: bad arguments")
+
+
+def heatbath_sites(U, gauge, T, seed, sweep, sites):
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    rc = lib().or_heatbath_sites(_field(U), _dims(dims_of(U)), int(gauge), float(T), int(seed),
+                                 int(sweep), sites.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 int(sites.size))
+    if rc != 0:
+        raise ValueError("or_heatbath_sites: bad arguments")
 
 
 def functional(U, gauge):

@@ -62,6 +62,9 @@ int  or_sweep(double* U, const int32_t dims[4], int gauge, int parity, double om
 /* The same update on a list of sites of one parity only (sampled checks). */
 int  or_update_sites(double* U, const int32_t dims[4], int gauge, double omega,
                      const int64_t* sites, int64_t n);
+/* The annealing heatbath update on a list of sites of one parity only. */
+int  or_heatbath_sites(double* U, const int32_t dims[4], int gauge, double T, uint64_t seed,
+                       uint64_t sweep, const int64_t* sites, int64_t n);
 /* Gauge functional eq. (3), normalised so that U = 1 gives 1. out[0] (Landau)
  * or out[t], t < nt (Coulomb). Returns the Landau value or the mean over t. */
 double or_functional(const double* U, const int32_t dims[4], int gauge, double* out);

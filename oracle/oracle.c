@@ -458,6 +458,22 @@ int or_update_sites(double* U, const int32_t dims[4], int gauge, double omega,
   return 0;
 }
 
+/* Heatbath update (annealing step at temperature T, draws keyed by seed and
+ * sweep) of the listed sites of one parity only (sampled checks). */
+int or_heatbath_sites(double* U, const int32_t dims[4], int gauge, double T, uint64_t seed,
+                      uint64_t sweep, const int64_t* sites, int64_t n) {
+  if (!U || !sites || or_check_dims(dims) != 0 || !(T > 0.0)) return -1;
+  lat_t L = make_lat(dims);
+  if (n <= 0) return 0;
+  int p0 = site_parity(&L, sites[0]);
+  for (int64_t k = 0; k < n; ++k)
+    if (sites[k] < 0 || sites[k] >= L.V || site_parity(&L, sites[k]) != p0) return -1;
+  upd_t u = {UPD_HB, 0.0, T, seed, sweep};
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n; ++k) site_update(U, &L, gauge, sites[k], &u);
+  return 0;
+}
+
 int or_sweep(double* U, const int32_t dims[4], int gauge, int parity, double omega) {
   if (!(omega >= 1.0 && omega < 2.0)) return -1; /* Sec. 2: omega in [1, 2) */
   upd_t u = {UPD_OR, omega, 0.0, 0, 0};

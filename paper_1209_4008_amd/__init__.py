@@ -16,7 +16,7 @@ ERR_ARG, ERR_UNSUPPORTED, ERR_DEVICE, ERR_HIP, ERR_NONFINITE, ERR_NOMEM = -1, -2
 LANDAU, COULOMB = 0, 1
 FP32, FP64 = 4, 8
 R12, R18 = 12, 18
-FLAG_TIMING, FLAG_GRAPH = 1, 2
+FLAG_TIMING, FLAG_GRAPH, FLAG_NO_TRACK = 1, 2, 4
 
 
 class GFError(RuntimeError):
@@ -47,21 +47,24 @@ class FixParams(C.Structure):
     _fields_ = [("omega", C.c_double), ("theta_target", C.c_double),
                 ("theta_switch", C.c_double), ("max_sweeps", C.c_int32),
                 ("check_every", C.c_int32), ("reunit_at_check", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("sa_steps", C.c_int32), ("sa_micro", C.c_int32),
+                ("sa_reunit_every", C.c_int32), ("sa_reserved", C.c_int32),
+                ("sa_T0", C.c_double), ("sa_T1", C.c_double), ("seed", C.c_uint64)]
 
 
 class FixResult(C.Structure):
     _fields_ = [("status", C.c_int32), ("sweeps", C.c_int32), ("sweeps_lo", C.c_int32),
                 ("checks", C.c_int32), ("F", C.c_double), ("theta", C.c_double),
                 ("theta_at_switch", C.c_double), ("wall_ms", C.c_double),
-                ("kernel_ms", C.c_double * 4), ("kernel_launches", C.c_int64 * 4)]
+                ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_int64 * 6),
+                ("sa_steps", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {"status": self.status, "sweeps": self.sweeps, "sweeps_lo": self.sweeps_lo,
                 "checks": self.checks, "F": self.F, "theta": self.theta,
                 "theta_at_switch": self.theta_at_switch, "wall_ms": self.wall_ms,
                 "kernel_ms": list(self.kernel_ms),
-                "kernel_launches": list(self.kernel_launches)}
+                "kernel_launches": list(self.kernel_launches), "sa_steps": self.sa_steps}
 
 
 # every symbol of include/gf.h with its ctypes signature
@@ -92,7 +95,7 @@ SIGNATURES = {
     "gf_set_sweep_variant": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "gf_get_sweep_variant": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int32)]),
-    "gf_autotune": (C.c_int32, [_vp, _gp, C.c_int32, C.POINTER(C.c_int32),
+    "gf_autotune": (C.c_int32, [_vp, _gp, C.c_int32, _dp, C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "gf_stream_probe": (C.c_int32, [_vp, _dp, _dp, C.c_size_t, C.c_int32]),
     "gf_fix": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.POINTER(FixParams),
@@ -233,13 +236,14 @@ class Context:
                                                C.byref(n)))
         return t.value, n.value
 
-    def autotune(self, geom, gauge=LANDAU):
-        """Time the six sweep variants for geom; keep the fastest on this context.
+    def autotune(self, geom, gauge=LANDAU, U_like=None):
+        """Time the six sweep variants for geom on a copy of U_like (None: the
+        unit field); keep the fastest on this context.
         Returns ((tps, nontemporal), {(tps, nontemporal): ms per half-sweep})."""
         t, n = C.c_int32(0), C.c_int32(0)
         ms = (C.c_float * 6)()
-        self._check(lib().gf_autotune(self.h, C.byref(geom), int(gauge), C.byref(t), C.byref(n),
-                                      ms))
+        self._check(lib().gf_autotune(self.h, C.byref(geom), int(gauge), _ptr(U_like),
+                                      C.byref(t), C.byref(n), ms))
         table = {(1 << (k % 3), k // 3): ms[k] for k in range(6)}
         return (t.value, n.value), table
 
@@ -262,6 +266,9 @@ class Context:
 
 
 def fix_params(omega=1.7, theta_target=1e-14, theta_switch=1e-6, max_sweeps=20000,
-               check_every=100, reunit_at_check=1, flags=0):
+               check_every=100, reunit_at_check=1, flags=0, sa_steps=0, sa_micro=3,
+               sa_reunit_every=10, sa_T0=1.45, sa_T1=0.01, seed=0):
     return FixParams(float(omega), float(theta_target), float(theta_switch), int(max_sweeps),
-                     int(check_every), int(reunit_at_check), int(flags))
+                     int(check_every), int(reunit_at_check), int(flags), int(sa_steps),
+                     int(sa_micro), int(sa_reunit_every), 0, float(sa_T0), float(sa_T1),
+                     int(seed))

@@ -27,6 +27,10 @@ struct gf_ctx {
   hipEvent_t ev[2] = {nullptr, nullptr};
   int tps[2][2] = {{0, 0}, {0, 0}};  // lanes per site [fp64][r18]; 0 = default
   int nt[2][2] = {{-1, -1}, {-1, -1}};  // nontemporal accesses [fp64][r18]; -1 = default
+  void* gbuf = nullptr;  // gauge-transformation field of the mixed driver
+  size_t gbuf_cap = 0;   // bytes
+  hipStream_t capture = nullptr;  // private stream for hipGraph capture
+  std::vector<hipEvent_t> pool;   // driver timing events, pairs (start, end)
 };
 
 static char g_create_err[512] = "no error";
@@ -242,6 +246,9 @@ gf_status gf_destroy(gf_ctx* c) {
   if (c->partial) (void)hipFree(c->partial);
   if (c->dev_out) (void)hipFree(c->dev_out);
   if (c->host_out) (void)hipHostFree(c->host_out);
+  if (c->gbuf) (void)hipFree(c->gbuf);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
+  for (auto& e : c->pool) (void)hipEventDestroy(e);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete c;
@@ -354,6 +361,27 @@ static void launch_update_tps(gf_ctx* c, int tps, int nt, void* U, const Lat& L,
     launch_update_v<T, NC, GAUGE, Upd, false>(c, tps, U, L, parity, upd);
 }
 
+// FP32 half-sweep (any update) that also accumulates g(x) <- Gtot g(x) into Gx
+template <int NC, int GAUGE, bool NT, class Upd>
+static void launch_tracked_v(gf_ctx* c, int tps, void* U, void* Gx, const Lat& L, int parity,
+                             const Upd& upd) {
+  const dim3 grid(blocks_for((uint64_t)L.vh * (uint64_t)tps));
+  switch (tps) {
+    case 1:
+      hipLaunchKernelGGL((k_update_half<float, NC, GAUGE, Upd, 1, NT, true>), grid, dim3(kBlock), 0,
+                         c->stream, (v2<float>*)U, L, parity, upd, (v2<float>*)Gx);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_update_half<float, NC, GAUGE, Upd, 2, NT, true>), grid, dim3(kBlock), 0,
+                         c->stream, (v2<float>*)U, L, parity, upd, (v2<float>*)Gx);
+      break;
+    default:
+      hipLaunchKernelGGL((k_update_half<float, NC, GAUGE, Upd, 4, NT, true>), grid, dim3(kBlock), 0,
+                         c->stream, (v2<float>*)U, L, parity, upd, (v2<float>*)Gx);
+      break;
+  }
+}
+
 static int ctx_tps(const gf_ctx* c, const gf_geom* g) {
   const int t = c->tps[g->prec == GF_FP64][g->storage == GF_R18];
   return t > 0 ? t : default_tps(g);
@@ -398,6 +426,53 @@ gf_status gf_sweep(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32_t 
         return u;
       },
       "gf_sweep");
+}
+
+// FP32 half-sweep with g tracking (mixed-precision driver)
+template <class Upd>
+static gf_status update_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32_t gauge,
+                                int32_t parity, const Upd& upd, const char* what) {
+  const Lat L = make_lat(g);
+  const int tps = ctx_tps(c, g), nt = ctx_nt(c, g);
+  auto go = [&]<int NC>() {
+    if (gauge == GF_LANDAU) {
+      if (nt) launch_tracked_v<NC, kLandau, true>(c, tps, U, Gx, L, parity, upd);
+      else launch_tracked_v<NC, kLandau, false>(c, tps, U, Gx, L, parity, upd);
+    } else {
+      if (nt) launch_tracked_v<NC, kCoulomb, true>(c, tps, U, Gx, L, parity, upd);
+      else launch_tracked_v<NC, kCoulomb, false>(c, tps, U, Gx, L, parity, upd);
+    }
+  };
+  if (g->storage == GF_R12)
+    go.template operator()<6>();
+  else
+    go.template operator()<9>();
+  return launch_check(c, what);
+}
+
+static gf_status sweep_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32_t gauge,
+                               int32_t parity, double omega) {
+  UpdOR<float> upd;
+  upd.omega = (float)omega;
+  return update_tracked(c, U, Gx, g, gauge, parity, upd, "tracked overrelaxation");
+}
+
+// one annealing step on an FP32 field with g tracking
+static gf_status anneal_step_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32_t gauge,
+                                     double T, uint64_t seed, uint64_t sweep, int32_t n_micro) {
+  UpdHB<float> hb;
+  hb.temp = (float)T;
+  hb.k0 = (uint32_t)seed;
+  hb.k1 = (uint32_t)(seed >> 32);
+  hb.sweep = (uint32_t)sweep;
+  gf_status st;
+  for (int p = 0; p < 2; ++p)
+    if ((st = update_tracked(c, U, Gx, g, gauge, p, hb, "tracked heatbath")) != GF_OK) return st;
+  UpdMicro<float> mc;
+  for (int k = 0; k < n_micro; ++k)
+    for (int p = 0; p < 2; ++p)
+      if ((st = update_tracked(c, U, Gx, g, gauge, p, mc, "tracked microcanonical")) != GF_OK) return st;
+  return GF_OK;
 }
 
 gf_status gf_micro_half(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32_t parity) {
@@ -545,8 +620,8 @@ gf_status gf_get_sweep_variant(gf_ctx* c, int32_t prec, int32_t storage, int32_t
   return GF_OK;
 }
 
-gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, int32_t* tps_out,
-                      int32_t* nt_out, float* ms_out) {
+gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, const void* U_like,
+                      int32_t* tps_out, int32_t* nt_out, float* ms_out) {
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_autotune");
   if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_autotune: bad gauge");
@@ -554,10 +629,17 @@ gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, int32_t* tps_o
   void* scratch = nullptr;
   HIP_OR_FAIL(c, hipMalloc(&scratch, bytes));
   const Lat L = make_lat(g);
-  with_type(g, [&]<typename T, int NC>() {
-    hipLaunchKernelGGL((k_fill_unit<T, NC>), dim3(blocks_for(L.vh), 8), dim3(kBlock), 0,
-                       c->stream, (v2<T>*)scratch, L.vh);
-  });
+  if (U_like) {
+    if (hipMemcpyAsync(scratch, U_like, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+      (void)hipFree(scratch);
+      return fail(c, GF_ERR_HIP, "gf_autotune: copy of the sample field failed");
+    }
+  } else {
+    with_type(g, [&]<typename T, int NC>() {
+      hipLaunchKernelGGL((k_fill_unit<T, NC>), dim3(blocks_for(L.vh), 8), dim3(kBlock), 0,
+                         c->stream, (v2<T>*)scratch, L.vh);
+    });
+  }
   const int reps = 20;
   float best = 1e30f;
   int best_tps = default_tps(g), best_nt = default_nt(g);
@@ -626,24 +708,50 @@ gf_status gf_stream_probe(gf_ctx* c, const void* src, void* dst, size_t bytes, i
 // ---------------------------------------------------------------------------
 namespace {
 
+// Kernel timing of the drivers: each timed interval records a pair of pool
+// events on the context stream; elapsed times are read at the driver's own
+// synchronisation points (flush), so timing adds no host waits.
 struct Timer {
   gf_ctx* c;
   bool on;
   double* ms;
   int64_t* n;
+  struct Pending {
+    int cat;
+    int64_t launches;
+  };
+  std::vector<Pending> pending;
+  size_t used = 0;  // events of the pool in use
   gf_status begin() {
-    if (on) HIP_OR_FAIL(c, hipEventRecord(c->ev[0], c->stream));
+    if (!on) return GF_OK;
+    while (c->pool.size() < used + 2) {
+      hipEvent_t e;
+      HIP_OR_FAIL(c, hipEventCreate(&e));
+      c->pool.push_back(e);
+    }
+    HIP_OR_FAIL(c, hipEventRecord(c->pool[used], c->stream));
     return GF_OK;
   }
-  // closes the interval; synchronises the end event and adds its time
   gf_status end(int cat, int64_t launches) {
     if (!on) return GF_OK;
-    HIP_OR_FAIL(c, hipEventRecord(c->ev[1], c->stream));
-    HIP_OR_FAIL(c, hipEventSynchronize(c->ev[1]));
-    float t = 0;
-    HIP_OR_FAIL(c, hipEventElapsedTime(&t, c->ev[0], c->ev[1]));
-    ms[cat] += t;
-    n[cat] += launches;
+    HIP_OR_FAIL(c, hipEventRecord(c->pool[used + 1], c->stream));
+    used += 2;
+    pending.push_back({cat, launches});
+    if (used >= 4096) return flush();
+    return GF_OK;
+  }
+  // waits for the last recorded event and adds up the pending intervals
+  gf_status flush() {
+    if (!on || pending.empty()) return GF_OK;
+    HIP_OR_FAIL(c, hipEventSynchronize(c->pool[used - 1]));
+    for (size_t k = 0; k < pending.size(); ++k) {
+      float t = 0;
+      HIP_OR_FAIL(c, hipEventElapsedTime(&t, c->pool[2 * k], c->pool[2 * k + 1]));
+      ms[pending[k].cat] += t;
+      n[pending[k].cat] += pending[k].launches;
+    }
+    pending.clear();
+    used = 0;
     return GF_OK;
   }
 };
@@ -660,6 +768,32 @@ gf_status check_params(gf_ctx* c, const gf_fix_params* p) {
   if (!(p->omega >= 1.0 && p->omega < 2.0)) return fail(c, GF_ERR_ARG, "gf_fix: omega must be in [1, 2)");
   if (p->max_sweeps < 0 || p->check_every < 1) return fail(c, GF_ERR_ARG, "gf_fix: bad sweep counts");
   if (!(p->theta_target >= 0.0)) return fail(c, GF_ERR_ARG, "gf_fix: bad theta_target");
+  if (p->sa_steps < 0 || p->sa_micro < 0 || p->sa_reunit_every < 0 || p->sa_reserved != 0)
+    return fail(c, GF_ERR_ARG, "gf_fix: bad annealing parameters");
+  if (p->sa_steps > 0 && (!(p->sa_T0 > 0.0) || !(p->sa_T1 > 0.0) || !std::isfinite(p->sa_T0) ||
+                          !std::isfinite(p->sa_T1)))
+    return fail(c, GF_ERR_ARG, "gf_fix: annealing temperatures must be > 0");
+  return GF_OK;
+}
+
+// the annealing schedule of p on U (with g tracking when Gx != NULL)
+gf_status run_anneal(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const gf_fix_params* p,
+                     Timer& tm, int32_t* done, void* Gx = nullptr) {
+  gf_status st;
+  *done = 0;
+  for (int32_t k = 0; k < p->sa_steps; ++k) {
+    const double T = p->sa_steps > 1
+                         ? p->sa_T0 + (p->sa_T1 - p->sa_T0) * (double)k / (double)(p->sa_steps - 1)
+                         : p->sa_T0;
+    if ((st = tm.begin()) != GF_OK) return st;
+    st = Gx ? anneal_step_tracked(c, U, Gx, g, gauge, T, p->seed, (uint64_t)k, p->sa_micro)
+            : gf_anneal_sweep(c, U, g, gauge, T, p->seed, (uint64_t)k, p->sa_micro);
+    if (st != GF_OK) return st;
+    if ((st = tm.end(4, 2 + 2 * (int64_t)p->sa_micro)) != GF_OK) return st;
+    if (p->sa_reunit_every > 0 && (k + 1) % p->sa_reunit_every == 0)
+      if ((st = gf_reunitarize(c, U, g)) != GF_OK) return st;
+    *done = k + 1;
+  }
   return GF_OK;
 }
 
@@ -680,6 +814,7 @@ gf_status do_check(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, bool reu
   HIP_OR_FAIL(c, hipMemcpyAsync(c->host_out, c->dev_out, 2 * c->out_cap * sizeof(double),
                                 hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if ((st = tm.flush()) != GF_OK) return st;
   double Fsum = 0, thmax = 0;
   for (int t = 0; t < nout; ++t) {
     const double F = c->host_out[t], th = c->host_out[c->out_cap + t];
@@ -694,11 +829,63 @@ gf_status do_check(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, bool reu
   return GF_OK;
 }
 
+// enqueue n sweeps (RED then BLACK each) on the context stream
+gf_status enqueue_sweeps(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, double omega,
+                         int32_t n, void* Gx) {
+  gf_status st;
+  for (int32_t k = 0; k < n; ++k)
+    for (int par = 0; par < 2; ++par) {
+      st = Gx ? sweep_tracked(c, U, Gx, g, gauge, par, omega) : gf_sweep(c, U, g, gauge, par, omega);
+      if (st != GF_OK) return st;
+    }
+  return GF_OK;
+}
+
+// a captured block of n sweeps, replayed between checks
+struct SweepGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int32_t n = 0;
+  ~SweepGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+gf_status capture_sweeps(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, double omega,
+                         int32_t n, void* Gx, SweepGraph& sg) {
+  if (!c->capture) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+  hipStream_t saved = c->stream;
+  c->stream = c->capture;
+  hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
+  gf_status st = GF_OK;
+  if (e != hipSuccess) {
+    c->stream = saved;
+    return fail(c, GF_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  st = enqueue_sweeps(c, U, g, gauge, omega, n, Gx);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(c->capture, &graph);
+  c->stream = saved;
+  if (st != GF_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(c, GF_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  sg.graph = graph;
+  HIP_OR_FAIL(c, hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0));
+  sg.n = n;
+  return GF_OK;
+}
+
 // sweeps `geom`'s field until theta < target or max_sweeps
 gf_status run_phase(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const gf_fix_params* p,
-                    double target, bool first_check_reunit, Timer& tm, Phase& ph) {
+                    double target, bool first_check_reunit, Timer& tm, Phase& ph,
+                    void* Gx = nullptr) {
   gf_status st;
   const int cat = g->prec == GF_FP32 ? 0 : 1;
+  const bool use_graph = (p->flags & GF_FLAG_GRAPH) != 0;
+  SweepGraph sg;
   for (;;) {
     const bool reunit = p->reunit_at_check && (ph.sweeps > 0 || first_check_reunit);
     if ((st = do_check(c, U, g, gauge, reunit, tm, ph)) != GF_OK) return st;
@@ -708,11 +895,13 @@ gf_status run_phase(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const g
     }
     if (ph.sweeps >= p->max_sweeps) return GF_OK;
     const int32_t n = std::min(p->check_every, p->max_sweeps - ph.sweeps);
+    if (use_graph && n == p->check_every && !sg.exec)
+      if ((st = capture_sweeps(c, U, g, gauge, p->omega, n, Gx, sg)) != GF_OK) return st;
     if ((st = tm.begin()) != GF_OK) return st;
-    for (int32_t k = 0; k < n; ++k) {
-      if ((st = gf_sweep(c, U, g, gauge, 0, p->omega)) != GF_OK) return st;
-      if ((st = gf_sweep(c, U, g, gauge, 1, p->omega)) != GF_OK) return st;
-    }
+    if (use_graph && sg.exec && n == sg.n)
+      HIP_OR_FAIL(c, hipGraphLaunch(sg.exec, c->stream));
+    else if ((st = enqueue_sweeps(c, U, g, gauge, p->omega, n, Gx)) != GF_OK)
+      return st;
     if ((st = tm.end(cat, 2 * (int64_t)n)) != GF_OK) return st;
     ph.sweeps += n;
   }
@@ -736,7 +925,9 @@ gf_status gf_fix(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const gf_f
   const auto t0 = std::chrono::steady_clock::now();
   Timer tm{c, (p->flags & GF_FLAG_TIMING) != 0, r->kernel_ms, r->kernel_launches};
   Phase ph;
-  st = run_phase(c, U, g, gauge, p, p->theta_target, false, tm, ph);
+  st = run_anneal(c, U, g, gauge, p, tm, &r->sa_steps);
+  if (st == GF_OK) st = run_phase(c, U, g, gauge, p, p->theta_target, false, tm, ph);
+  if (st == GF_OK) st = tm.flush();
   r->sweeps = ph.sweeps;
   r->checks = ph.checks;
   r->F = ph.F;
@@ -761,21 +952,60 @@ gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
   if (!same_extents(g_lo, g_hi)) return fail(c, GF_ERR_ARG, "gf_fix_mixed: extents differ");
   if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_fix_mixed: bad gauge");
   if (!U_lo || !U_hi || !r) return fail(c, GF_ERR_ARG, "gf_fix_mixed: NULL pointer");
+  {
+    const char *a = (const char*)U_lo, *b = (const char*)U_hi;
+    if (a < b + gf_field_bytes(g_hi) && b < a + gf_field_bytes(g_lo))
+      return fail(c, GF_ERR_ARG, "gf_fix_mixed: buffers overlap");
+  }
   gf_status st = check_params(c, p);
   if (st != GF_OK) return st;
   if (!(p->theta_switch > 0.0)) return fail(c, GF_ERR_ARG, "gf_fix_mixed: theta_switch must be > 0");
+  const bool track = (p->flags & GF_FLAG_NO_TRACK) == 0;
+  const Lat L = make_lat(g_lo);
+  if (track) {
+    const size_t gbytes = (size_t)2 * L.vh * 6 * sizeof(float) * 2;
+    if (gbytes > c->gbuf_cap) {
+      if (c->gbuf) HIP_OR_FAIL(c, hipFree(c->gbuf));
+      c->gbuf = nullptr;
+      c->gbuf_cap = 0;
+      HIP_OR_FAIL(c, hipMalloc(&c->gbuf, gbytes));
+      c->gbuf_cap = gbytes;
+    }
+  }
   init_result(r);
   const auto t0 = std::chrono::steady_clock::now();
   Timer tm{c, (p->flags & GF_FLAG_TIMING) != 0, r->kernel_ms, r->kernel_launches};
-  Phase lo;
-  st = run_phase(c, U_lo, g_lo, gauge, p, p->theta_switch, false, tm, lo);
-  Phase hi;
+  Phase lo, hi;
+  // FP64 input -> FP32 working copy; g = 1
+  if ((st = tm.begin()) == GF_OK && (st = gf_convert(c, g_hi, U_hi, g_lo, U_lo, 0)) == GF_OK) {
+    if (track)
+      hipLaunchKernelGGL((k_fill_unit<float, 6>), dim3(blocks_for(L.vh), 2), dim3(kBlock), 0,
+                         c->stream, (v2<float>*)c->gbuf, L.vh);
+    st = launch_check(c, "gf_fix_mixed: init");
+    if (st == GF_OK) st = tm.end(3, track ? 2 : 1);
+  }
+  if (st == GF_OK) st = run_anneal(c, U_lo, g_lo, gauge, p, tm, &r->sa_steps, track ? c->gbuf : nullptr);
+  if (st == GF_OK)
+    st = run_phase(c, U_lo, g_lo, gauge, p, p->theta_switch, false, tm, lo, track ? c->gbuf : nullptr);
   if (st == GF_OK) {
     r->theta_at_switch = lo.theta;
-    if ((st = tm.begin()) == GF_OK && (st = gf_convert(c, g_lo, U_lo, g_hi, U_hi, 1)) == GF_OK &&
-        (st = tm.end(3, 1)) == GF_OK)
-      st = run_phase(c, U_hi, g_hi, gauge, p, p->theta_target, false, tm, hi);
+    // back to FP64: either the original field transformed by g (projected onto
+    // SU(3) in FP64), or the FP32 field itself reunitarised in FP64
+    if ((st = tm.begin()) == GF_OK) {
+      if (track) {
+        with_type(g_hi, [&]<typename T, int NC>() {
+          hipLaunchKernelGGL((k_apply_gauge<T, NC, float>), dim3(blocks_for(L.vh), 2), dim3(kBlock),
+                             0, c->stream, (v2<T>*)U_hi, (const v2<float>*)c->gbuf, L);
+        });
+        st = launch_check(c, "gf_fix_mixed: apply g");
+      } else {
+        st = gf_convert(c, g_lo, U_lo, g_hi, U_hi, 1);
+      }
+    }
+    if (st == GF_OK) st = tm.end(3, 1);
+    if (st == GF_OK) st = run_phase(c, U_hi, g_hi, gauge, p, p->theta_target, false, tm, hi);
   }
+  if (st == GF_OK) st = tm.flush();
   r->sweeps_lo = lo.sweeps;
   r->sweeps = lo.sweeps + hi.sweeps;
   r->checks = lo.checks + hi.checks;
@@ -789,4 +1019,3 @@ gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
   r->status = hi.converged ? GF_OK : GF_NOT_CONVERGED;
   return r->status;
 }
-

@@ -218,9 +218,13 @@ __device__ __forceinline__ void lane_sum(Su3<T>& K) {
 // form their partial sums of K, add them across the site's lanes, compute the
 // same subgroup transformations, and each updates and stores its own links.
 // ---------------------------------------------------------------------------
-template <typename T, int NC, int GAUGE, class Upd, int TPS, bool NT>
+// TRACK: also accumulate the site transformation into the gauge-transformation
+// field Gx (layout [p][c][h], 6 complex = rows 0, 1), g(x) <- Gtot g(x); lane 0
+// of the site does it.
+template <typename T, int NC, int GAUGE, class Upd, int TPS, bool NT, bool TRACK = false>
 __global__ __launch_bounds__(kBlock) void k_update_half(v2<T>* __restrict__ U, const Lat L,
-                                                        const int parity, const Upd upd) {
+                                                        const int parity, const Upd upd,
+                                                        v2<T>* __restrict__ Gx = nullptr) {
   static_assert(TPS == 1 || TPS == 2 || TPS == 4, "lanes per site");
   constexpr int DPL = 4 / TPS;  // directions per lane
   const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
@@ -265,6 +269,20 @@ __global__ __launch_bounds__(kBlock) void k_update_half(v2<T>* __restrict__ U, c
   subgroup_step<T, Upd, 0, 1, 0>(K, G, site, upd);
   subgroup_step<T, Upd, 0, 2, 1>(K, G, site, upd);
   subgroup_step<T, Upd, 1, 2, 2>(K, G, site, upd);
+  if (TRACK && r == 0) {
+    v2<T>* gp = Gx + (size_t)parity * 6 * L.vh;
+    Su3<T> gx, A;
+    load_link<T, 6, NT>(gp, L.vh, h, gx);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        Cx<T> f = cmul(G.e[a][0], gx.e[0][b]);
+        f = cmac(f, G.e[a][1], gx.e[1][b]);
+        A.e[a][b] = cmac(f, G.e[a][2], gx.e[2][b]);
+      }
+    store_link<T, 6, NT>(gp, L.vh, h, A);
+  }
   constexpr int R = NC / 3;  // stored rows
 #pragma unroll
   for (int d = 0; d < DPL; ++d) {
@@ -552,7 +570,9 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const v2<T>* __restrict__ src
   }
 }
 
-// the unit field in the device layout (scratch fields of the autotuner)
+// the unit field in the device layout (scratch fields of the autotuner, the
+// gauge-transformation field of the mixed-precision driver); grid.y blocks of
+// NC components each
 template <typename T, int NC>
 __global__ __launch_bounds__(kBlock) void k_fill_unit(v2<T>* __restrict__ U, const uint32_t vh) {
   const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
@@ -568,6 +588,49 @@ __global__ __launch_bounds__(kBlock) void k_fill_unit(v2<T>* __restrict__ U, con
 }
 
 // bandwidth probes: 16-byte elements, one per thread
+// U_mu(x) <- g(x) U_mu(x) g(x+mu)^dag in FP64, with g (Tg, rows 0 and 1 in
+// the [p][c][h] layout) projected onto SU(3) by Gram-Schmidt first. Each
+// thread owns the four forward links of one site and only reads g, so the
+// update is in place. grid (ceil(vh/kBlock), 2): blockIdx.y = parity.
+template <typename T, int NC, typename Tg>
+__global__ __launch_bounds__(kBlock) void k_apply_gauge(v2<T>* __restrict__ U,
+                                                        const v2<Tg>* __restrict__ Gx, const Lat L) {
+  const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+  if (h >= L.vh) return;
+  const int p = blockIdx.y;
+  const Site S = site_of(L, h, p);
+  const size_t blk = (size_t)NC * L.vh;
+  Su3<double> g;
+  load_link_f64<Tg, 6>(Gx + (size_t)p * 6 * L.vh, L.vh, h, g);
+  gram_schmidt(g);
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    Su3<double> gn, A, B;
+    load_link_f64<Tg, 6>(Gx + (size_t)(1 - p) * 6 * L.vh, L.vh, fwd_h(L, h, S, mu), gn);
+    gram_schmidt(gn);
+    v2<T>* q = U + ((size_t)p * 4 + mu) * blk;
+    load_link_f64<T, NC>(q, L.vh, h, A);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        Cx<double> f = cmul(g.e[a][0], A.e[0][b]);
+        f = cmac(f, g.e[a][1], A.e[1][b]);
+        B.e[a][b] = cmac(f, g.e[a][2], A.e[2][b]);
+      }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        Cx<double> f = cx<double>(0, 0);
+        f = cmac_cb(f, B.e[a][0], gn.e[b][0]);
+        f = cmac_cb(f, B.e[a][1], gn.e[b][1]);
+        A.e[a][b] = cmac_cb(f, B.e[a][2], gn.e[b][2]);
+      }
+    store_link_from_f64<T, NC>(q, L.vh, h, A);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_probe_copy(const double2* __restrict__ a,
                                                        double2* __restrict__ b, const size_t n) {
   const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;

@@ -1,0 +1,140 @@
+"""GPU checks of the simulated-annealing driver and of the Coulomb workload
+at its full size (32^3 x 64, 64 timeslices in one launch)."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle as O
+import paper_1209_4008_amd as gf
+from gpu_helpers import TOL, download, host_canon, oracle_input, say, site_parity, sites_links, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = gf.Context()
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def test_anneal_driver_is_its_schedule(ctx):
+    """gf_fix with sa_steps = the linear schedule of gf_anneal_sweep calls with
+    reunitarisation every sa_reunit_every steps, then overrelaxation; bit for bit."""
+    dims = (4, 4, 6, 4)
+    U = inputs.config0(dims, 0.5, 31)
+    steps, T0, T1, micro, every, seed = 7, 1.2, 0.05, 2, 3, 99
+    p = gf.fix_params(omega=1.7, theta_target=1e-10, max_sweeps=500, check_every=10,
+                      sa_steps=steps, sa_micro=micro, sa_reunit_every=every, sa_T0=T0,
+                      sa_T1=T1, seed=seed, flags=gf.FLAG_TIMING)
+    a, g = upload(ctx, U, gf.FP64, gf.R12)
+    r = ctx.fix(a, g, gf.COULOMB, p)
+    assert r.sa_steps == steps and r.status == gf.OK
+    assert r.kernel_launches[4] == steps * (2 + 2 * micro)
+    b, _ = upload(ctx, U, gf.FP64, gf.R12)
+    for k in range(steps):
+        ctx.anneal_sweep(b, g, gf.COULOMB, T0 + (T1 - T0) * k / (steps - 1), seed, k, micro)
+        if (k + 1) % every == 0:
+            ctx.reunitarize(b, g)
+    r2 = ctx.fix(b, g, gf.COULOMB, gf.fix_params(omega=1.7, theta_target=1e-10, max_sweeps=500,
+                                                  check_every=10))
+    assert r.sweeps == r2.sweeps and r.F == r2.F
+    assert np.array_equal(download(ctx, a, g), download(ctx, b, g))
+
+
+def test_mixed_with_annealing_stays_on_the_orbit(ctx):
+    """FP32 annealing and FP32 overrelaxation with g tracked, then FP64: the
+    final field is a gauge transform of the input (plaquette to 1e-13) and
+    every timeslice is fixed to theta < 1e-14."""
+    dims = (8, 6, 6, 6)
+    U = inputs.config0(dims, 0.4, 32)
+    glo = gf.Geom.make(dims, gf.FP32, gf.R12)
+    ghi = gf.Geom.make(dims, gf.FP64, gf.R12)
+    fhi, _ = upload(ctx, U, gf.FP64, gf.R12)
+    flo = ctx.empty_field(glo)
+    P0, P1 = ctx.empty_out(1), ctx.empty_out(1)
+    ctx.plaquette(fhi, ghi, P0)
+    p = gf.fix_params(omega=1.7, theta_target=1e-14, theta_switch=1e-6, max_sweeps=5000,
+                      check_every=50, sa_steps=200, sa_micro=3, sa_T0=1.45, sa_T1=0.01, seed=4)
+    r = ctx.fix_mixed(flo, glo, fhi, ghi, gf.COULOMB, p)
+    assert r.status == gf.OK and r.sa_steps == 200
+    ctx.plaquette(fhi, ghi, P1)
+    assert P1.item() == pytest.approx(P0.item(), abs=1e-13)
+    F, th = ctx.empty_out(dims[0]), ctx.empty_out(dims[0])
+    ctx.measure(fhi, ghi, gf.COULOMB, F, th)
+    assert np.all(th.cpu().numpy() < 1e-14)
+
+
+def test_annealing_preconditioning_raises_best_functional(ctx):
+    """The paper's claim for annealing (Sec. 1): it raises the chance of
+    reaching the global maximum of F. Over 12 random gauge copies of one
+    configuration, the best and the mean F after annealing + overrelaxation
+    are at least those of overrelaxation alone (fixed seeds)."""
+    dims = (8, 8, 8, 8)
+    base = inputs.heatbath(dims, 5.8, 40, seed=5)
+    res = {0: [], 1: []}
+    for copy in range(12):
+        U = base.copy()
+        inputs.haar_copy(U, 1000, copy)
+        for sa in (0, 1):
+            f, g = upload(ctx, U, gf.FP64, gf.R12)
+            p = gf.fix_params(omega=1.7, theta_target=1e-12, max_sweeps=20000, check_every=50,
+                              sa_steps=400 if sa else 0, sa_micro=3, sa_T0=1.2, sa_T1=0.01,
+                              seed=7 + copy)
+            r = ctx.fix(f, g, gf.LANDAU, p)
+            assert r.status == gf.OK
+            res[sa].append(r.F)
+    say("best F without / with annealing", max(res[0]), max(res[1]),
+        "means", np.mean(res[0]), np.mean(res[1]))
+    assert max(res[1]) >= max(res[0]) - 1e-12
+    assert np.mean(res[1]) >= np.mean(res[0]) - 1e-12
+
+
+@pytest.mark.parametrize("prec", [gf.FP64, gf.FP32])
+def test_coulomb_full_size_sampled(ctx, prec):
+    """32^3 x 64 (64 timeslices in one launch): one heatbath half-sweep and one
+    overrelaxation half-sweep, 256 sampled sites recomputed by the oracle."""
+    import torch
+    dims = (64, 32, 32, 32)
+    say("generating", dims)
+    d = inputs.gpu_heatbath(dims, 6.0, 10, 4)
+    torch.cuda.synchronize()
+    U = host_canon(d, dims)
+    del d
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(4)
+    cand = rng.choice(V, size=1024, replace=False)
+    for kind in ("hb", "or"):
+        f, g = upload(ctx, U, prec, gf.R12)
+        if kind == "hb":
+            ctx.heatbath_half(f, g, gf.COULOMB, 0, 1.45, 4, 0)
+        else:
+            ctx.sweep(f, g, gf.COULOMB, 0, 1.7)
+        got = download(ctx, f, g).reshape(V, 4, 3, 3)
+        ref = oracle_input(U, prec, gf.R12)
+        sites = [int(s) for s in cand if site_parity(dims, s) == 0][:256]
+        if kind == "hb":
+            O.heatbath_sites(ref, gf.COULOMB, 1.45, 4, 0, sites)
+        else:
+            O.update_sites(ref, gf.COULOMB, 1.7, sites)
+        r4 = ref.reshape(V, 4, 3, 3)
+        errs = [np.abs(got[s, mu] - r4[s, mu]).max() for s, mu in sites_links(dims, sites)]
+        tol = TOL[prec] if kind == "or" else (1e-12 if prec == gf.FP64 else 1e-3)
+        if kind == "hb" and prec == gf.FP32:
+            # FP32 draws may take a different accept/reject decision than the
+            # FP64 oracle at a few sites; the rest agree to FP32 rounding
+            assert np.mean(np.array(errs) <= 1e-4) > 0.95
+        else:
+            assert max(errs) <= tol, (kind, max(errs))
+        del ref, got
+    if prec == gf.FP64:
+        # per-timeslice F and theta of the input against the oracle on the whole field
+        f, g = upload(ctx, U, prec, gf.R12)
+        F, th = ctx.empty_out(dims[0]), ctx.empty_out(dims[0])
+        ctx.measure(f, g, gf.COULOMB, F, th)
+        ref = oracle_input(U, prec, gf.R12)
+        assert np.allclose(F.cpu().numpy(), O.functional(ref, gf.COULOMB)[1], rtol=1e-12)
+        assert np.allclose(th.cpu().numpy(), O.theta_K(ref, gf.COULOMB)[1], rtol=1e-11)
