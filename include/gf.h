@@ -243,6 +243,28 @@ gf_status gf_fix_mixed(gf_ctx* ctx, void* U_lo, const gf_geom* geom_lo, void* U_
                        const gf_geom* geom_hi, int32_t gauge, const gf_fix_params* params,
                        gf_fix_result* result);
 
+/* ---- batches (Gribov copies, lattices of uneven extents) ------------------- */
+/* n independent Landau problems fixed together: every annealing step,
+ * half-sweep, reunitarisation and measurement is one launch over all lattices
+ * that are still active (each lattice leaves a phase at its own check), and
+ * the sweeps between checks are replayed from a hipGraph.
+ * geoms: n FP64 geometries (extents may differ; all of one storage);
+ * U: n caller-owned FP64 device fields, borrowed until gf_batch_destroy;
+ * they hold the inputs and receive the results. The batch allocates its FP32
+ * working fields and gauge-transformation fields (V x 96 bytes per lattice)
+ * at creation. Coulomb batches are GF_ERR_UNSUPPORTED. */
+typedef struct gf_batch gf_batch;
+gf_status gf_batch_create(gf_ctx* ctx, int32_t n, const gf_geom* geoms, void* const* U,
+                          int32_t gauge, gf_batch** out);
+/* The gf_fix_mixed pipeline per lattice (annealing in FP32 with g tracked if
+ * sa_steps > 0, FP32 overrelaxation to theta_switch, FP64 transformation of
+ * the input by g, FP64 overrelaxation to theta_target). The annealing draws of
+ * lattice l use the key seed + l, so lattice l ends exactly where gf_fix_mixed
+ * on it alone with seed + l ends. results: n host structs (kernel timings
+ * are reported in results[0]). Synchronises the context stream. */
+gf_status gf_batch_run(gf_batch* batch, const gf_fix_params* params, gf_fix_result* results);
+gf_status gf_batch_destroy(gf_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -102,6 +102,10 @@ SIGNATURES = {
                            C.POINTER(FixResult)]),
     "gf_fix_mixed": (C.c_int32, [_vp, _dp, _gp, _dp, _gp, C.c_int32, C.POINTER(FixParams),
                                  C.POINTER(FixResult)]),
+    "gf_batch_create": (C.c_int32, [_vp, C.c_int32, C.POINTER(Geom), C.POINTER(C.c_void_p),
+                                    C.c_int32, C.POINTER(C.c_void_p)]),
+    "gf_batch_run": (C.c_int32, [_vp, C.POINTER(FixParams), C.POINTER(FixResult)]),
+    "gf_batch_destroy": (C.c_int32, [_vp]),
 }
 
 _lib = None
@@ -263,6 +267,38 @@ class Context:
                                        C.byref(geom_hi), int(gauge), C.byref(params),
                                        C.byref(r)), allow=(OK, NOT_CONVERGED))
         return r
+
+
+class Batch:
+    """n independent Landau problems (FP64 fields, uneven extents allowed) fixed
+    together by gf_batch_run; the fields are borrowed until close()."""
+
+    def __init__(self, ctx, geoms, fields, gauge=LANDAU):
+        self.ctx = ctx
+        self.n = len(geoms)
+        self.fields = list(fields)  # keep the tensors alive
+        ga = (Geom * self.n)(*geoms)
+        ua = (C.c_void_p * self.n)(*[f.data_ptr() for f in fields])
+        h = C.c_void_p()
+        ctx._check(lib().gf_batch_create(ctx.h, self.n, ga, ua, int(gauge), C.byref(h)))
+        self.h = h
+
+    def run(self, params):
+        res = (FixResult * self.n)()
+        self.ctx._check(lib().gf_batch_run(self.h, C.byref(params), res),
+                        allow=(OK, NOT_CONVERGED))
+        return list(res)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fix_params(omega=1.7, theta_target=1e-14, theta_switch=1e-6, max_sweeps=20000,

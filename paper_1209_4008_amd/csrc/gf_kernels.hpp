@@ -220,14 +220,13 @@ __device__ __forceinline__ void lane_sum(Su3<T>& K) {
 // ---------------------------------------------------------------------------
 // TRACK: also accumulate the site transformation into the gauge-transformation
 // field Gx (layout [p][c][h], 6 complex = rows 0, 1), g(x) <- Gtot g(x); lane 0
-// of the site does it.
-template <typename T, int NC, int GAUGE, class Upd, int TPS, bool NT, bool TRACK = false>
-__global__ __launch_bounds__(kBlock) void k_update_half(v2<T>* __restrict__ U, const Lat L,
-                                                        const int parity, const Upd upd,
-                                                        v2<T>* __restrict__ Gx = nullptr) {
+// of the site does it. gid = TPS * h + lane.
+template <typename T, int NC, int GAUGE, class Upd, int TPS, bool NT, bool TRACK>
+__device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const Lat& L,
+                                                 const int parity, const Upd& upd,
+                                                 v2<T>* __restrict__ Gx, const uint32_t gid) {
   static_assert(TPS == 1 || TPS == 2 || TPS == 4, "lanes per site");
   constexpr int DPL = 4 / TPS;  // directions per lane
-  const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t h = gid / TPS;
   const int r = (int)(gid % TPS);
   if (h >= L.vh) return;  // a site's lanes are all in range or all out
@@ -308,6 +307,72 @@ __global__ __launch_bounds__(kBlock) void k_update_half(v2<T>* __restrict__ U, c
       }
     store_link<T, NC, NT>(Pb + mu * blk, L.vh, hb[d], A);
   }
+}
+
+template <typename T, int NC, int GAUGE, class Upd, int TPS, bool NT, bool TRACK = false>
+__global__ __launch_bounds__(kBlock) void k_update_half(v2<T>* __restrict__ U, const Lat L,
+                                                        const int parity, const Upd upd,
+                                                        v2<T>* __restrict__ Gx = nullptr) {
+  site_half_update<T, NC, GAUGE, Upd, TPS, NT, TRACK>(U, L, parity, upd, Gx,
+                                                      blockIdx.x * kBlock + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// batches of independent lattices (Gribov copies, uneven extents): one launch
+// covers every active lattice; lattice l owns the blocks
+// [first_block[l], first_block[l+1]).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct BatchEntry {
+  Lat L;
+  v2<T>* U;   // the lattice's device field
+  v2<T>* Gx;  // its gauge-transformation field (tracked runs) or null
+  uint32_t first_block;
+  uint32_t index;  // lattice number (keys the annealing draws)
+};
+
+// lattice owning block b: the last l with first_block[l] <= b (n >= 1)
+template <typename T>
+__device__ __forceinline__ int batch_lattice(const BatchEntry<T>* __restrict__ tab, int n,
+                                             uint32_t b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].first_block <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// per-lattice update policy: the annealing draws of lattice l use the key
+// seed + l, so that a batched lattice draws what a run of it alone with that
+// seed draws
+template <class Upd>
+__device__ __forceinline__ Upd for_lattice(const Upd& u, uint32_t) {
+  return u;
+}
+template <typename T>
+__device__ __forceinline__ UpdHB<T> for_lattice(const UpdHB<T>& u, uint32_t l) {
+  UpdHB<T> v = u;
+  const uint64_t seed = (((uint64_t)u.k1 << 32) | u.k0) + l;
+  v.k0 = (uint32_t)seed;
+  v.k1 = (uint32_t)(seed >> 32);
+  return v;
+}
+
+template <typename T, int NC, class Upd, int TPS, bool NT, bool TRACK>
+__global__ __launch_bounds__(kBlock) void k_update_half_batch(const BatchEntry<T>* __restrict__ tab,
+                                                              const int n,
+                                                              const int* __restrict__ active,
+                                                              const int parity, const Upd upd) {
+  const int l = batch_lattice(tab, n, blockIdx.x);
+  if (!active[l]) return;
+  const BatchEntry<T> e = tab[l];
+  site_half_update<T, NC, kLandau, Upd, TPS, NT, TRACK>(
+      e.U, e.L, parity, for_lattice(upd, e.index), e.Gx,
+      (blockIdx.x - e.first_block) * kBlock + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -396,6 +461,92 @@ __global__ __launch_bounds__(kBlock) void k_measure(const v2<T>* __restrict__ U,
     const size_t o = ((size_t)t * gridDim.x + blockIdx.x) * 2;
     partial[o] = f;
     partial[o + 1] = th;
+  }
+}
+
+// batched Landau measurement: thread = half index of one lattice, both
+// parities; lattice l owns blocks [first_block[l], first_block[l+1]);
+// partial[2*block + {0: F, 1: theta}]
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_measure_batch(const BatchEntry<T>* __restrict__ tab,
+                                                          const int n,
+                                                          const int* __restrict__ active,
+                                                          double* __restrict__ partial) {
+  __shared__ double lds[kBlock / 64];
+  const int l = batch_lattice(tab, n, blockIdx.x);
+  if (!active[l]) return;  // uniform per block
+  const BatchEntry<T> e = tab[l];
+  const Lat& L = e.L;
+  const uint32_t h = (blockIdx.x - e.first_block) * kBlock + threadIdx.x;
+  const size_t blk = (size_t)NC * L.vh;
+  double f = 0, th = 0;
+  if (h < L.vh) {
+#pragma unroll 1
+    for (int p = 0; p < 2; ++p) {
+      const Site S = site_of(L, h, p);
+      const v2<T>* Pf = e.U + (size_t)p * 4 * blk;
+      const v2<T>* Pb = e.U + (size_t)(1 - p) * 4 * blk;
+      Su3<double> K;
+      set_zero(K);
+#pragma unroll 1
+      for (int mu = 0; mu < 4; ++mu) {
+        Su3<double> A, B;
+        load_link_f64<T, NC>(Pf + mu * blk, L.vh, h, A);
+        load_link_f64<T, NC>(Pb + mu * blk, L.vh, back_h(L, h, S, mu), B);
+        f += A.e[0][0].re + A.e[1][1].re + A.e[2][2].re;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+            K.e[a][b] = cadd(K.e[a][b], cadd(A.e[a][b], cconj(B.e[b][a])));
+      }
+      const double d0 = K.e[0][0].im, d1 = K.e[1][1].im, d2 = K.e[2][2].im;
+      const double tr3 = (d0 + d1 + d2) / 3.0;
+      double acc = (d0 - tr3) * (d0 - tr3) + (d1 - tr3) * (d1 - tr3) + (d2 - tr3) * (d2 - tr3);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          if (a == b) continue;
+          const Cx<double> z = csub(K.e[a][b], cconj(K.e[b][a]));
+          acc += 0.25 * (z.re * z.re + z.im * z.im);
+        }
+      th += acc;
+    }
+  }
+  f = block_sum(f, lds);
+  th = block_sum(th, lds);
+  if (threadIdx.x == 0) {
+    partial[2 * (size_t)blockIdx.x] = f;
+    partial[2 * (size_t)blockIdx.x + 1] = th;
+  }
+}
+
+// one block per lattice: F[l] = sum / (12 V_l), theta[l] = sum / (3 V_l) over
+// the lattice's blocks (active lattices only)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_finish_batch(const BatchEntry<T>* __restrict__ tab,
+                                                         const int n, const uint32_t total_blocks,
+                                                         const int* __restrict__ active,
+                                                         const double* __restrict__ partial,
+                                                         double* __restrict__ F,
+                                                         double* __restrict__ th) {
+  __shared__ double lds[kBlock / 64];
+  const int l = blockIdx.x;
+  if (!active[l]) return;
+  const uint32_t b0 = tab[l].first_block;
+  const uint32_t b1 = (l + 1 < n) ? tab[l + 1].first_block : total_blocks;
+  double a = 0, b = 0;
+  for (uint32_t k = b0 + threadIdx.x; k < b1; k += kBlock) {
+    a += partial[2 * (size_t)k];
+    b += partial[2 * (size_t)k + 1];
+  }
+  a = block_sum(a, lds);
+  b = block_sum(b, lds);
+  if (threadIdx.x == 0) {
+    const double V = 2.0 * tab[l].L.vh;
+    F[l] = a / (12.0 * V);
+    th[l] = b / (3.0 * V);
   }
 }
 
@@ -588,6 +739,26 @@ __global__ __launch_bounds__(kBlock) void k_fill_unit(v2<T>* __restrict__ U, con
 }
 
 // bandwidth probes: 16-byte elements, one per thread
+// batched in-place reunitarisation of the active lattices (8 link blocks each)
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_reunitarize_batch(const BatchEntry<T>* __restrict__ tab,
+                                                              const int n,
+                                                              const int* __restrict__ active) {
+  const int l = batch_lattice(tab, n, blockIdx.x);
+  if (!active[l]) return;
+  const BatchEntry<T> e = tab[l];
+  const uint32_t h = (blockIdx.x - e.first_block) * kBlock + threadIdx.x;
+  if (h >= e.L.vh) return;
+#pragma unroll 1
+  for (int pm = 0; pm < 8; ++pm) {
+    Su3<double> A;
+    v2<T>* q = e.U + (size_t)pm * NC * e.L.vh;
+    load_link_f64<T, NC>(q, e.L.vh, h, A);
+    gram_schmidt(A);
+    store_link_from_f64<T, NC>(q, e.L.vh, h, A);
+  }
+}
+
 // U_mu(x) <- g(x) U_mu(x) g(x+mu)^dag in FP64, with g (Tg, rows 0 and 1 in
 // the [p][c][h] layout) projected onto SU(3) by Gram-Schmidt first. Each
 // thread owns the four forward links of one site and only reads g, so the
