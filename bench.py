@@ -55,6 +55,12 @@ def parse():
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the sweeps between checks one by one instead of replaying a "
                          "captured hipGraph")
+    ap.add_argument("--workload", default="landau32",
+                    choices=("landau32", "mixed48", "coulomb", "batch"),
+                    help="landau32 (default, the benchmark line): 32^4 beta 6.0 mixed fix; "
+                         "mixed48: 48^4 beta 6.2 mixed vs FP64; coulomb: 32^3x64 beta 6.0 with "
+                         "3000 annealing steps then the mixed Coulomb fix; batch: 64 Haar copies "
+                         "each of 16^4, 24^4, 12^3x24 with 2000 annealing steps then the mixed fix")
     ap.add_argument("--probe", action="store_true",
                     help="kernel probe for profilers: bandwidth probes of known size, then "
                          "20 sweeps of each storage variant on a generated input")
@@ -126,6 +132,127 @@ def hbm_traffic(kname, dims):
     return round(k["traffic_bytes"]) if k else None
 
 
+def coulomb_main(args):
+    """32^3 x 64 Coulomb gauge: annealing (T 1.45 -> 0.01 over 3000 steps, 3
+    microcanonical sweeps each) then FP32 -> FP64 overrelaxation to theta < 1e-14,
+    all 64 timeslices in every launch."""
+    import torch
+
+    import inputs
+    import paper_1209_4008_amd as gf
+
+    dims = (64, 32, 32, 32)
+    V = 64 * 32 ** 3
+    ctx = gf.Context(0)
+    canon = inputs.gpu_heatbath(dims, 6.0, args.therm, 4, progress=100)
+    glo = gf.Geom.make(dims, gf.FP32, gf.R12)
+    ghi = gf.Geom.make(dims, gf.FP64, gf.R12)
+    U_lo, U_hi = ctx.empty_field(glo), ctx.empty_field(ghi)
+    for g, f in ((glo, U_lo), (ghi, U_hi)):
+        ctx.pack(g, canon, f)
+        ctx.autotune(g, gf.COULOMB, U_like=f)
+    ctx.pack(ghi, canon, U_hi)
+    P0 = ctx.empty_out(1)
+    ctx.plaquette(U_hi, ghi, P0)
+    p = gf.fix_params(omega=args.omega, theta_target=1e-14, theta_switch=1e-6,
+                      max_sweeps=args.max_sweeps, check_every=args.check_every,
+                      flags=gf.FLAG_TIMING | gf.FLAG_GRAPH, sa_steps=3000, sa_micro=3,
+                      sa_T0=1.45, sa_T1=0.01, sa_reunit_every=10, seed=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.fix_mixed(U_lo, glo, U_hi, ghi, gf.COULOMB, p)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    F, th, P1 = ctx.empty_out(64), ctx.empty_out(64), ctx.empty_out(1)
+    ctx.measure(U_hi, ghi, gf.COULOMB, F, th)
+    ctx.plaquette(U_hi, ghi, P1)
+    sa_ms, sa_n = r.kernel_ms[4], r.kernel_launches[4]
+    or_ms = r.kernel_ms[0] + r.kernel_ms[1]
+    out = {"metric": "Coulomb gauge fixing with annealing: time to max_t theta_t < 1e-14",
+           "workload": "coulomb 32^3x64 beta=6.0, 3000 annealing steps (T 1.45->0.01, 3 micro), "
+                       "mixed fp32-r12 -> fp64-r12 omega=%g" % args.omega,
+           "total_ms": round(1e3 * dt, 1), "status": r.status,
+           "annealing": {"steps": r.sa_steps, "ms": round(sa_ms, 1),
+                         "half_sweeps_per_s": round(sa_n / (sa_ms * 1e-3), 1),
+                         "site_updates_per_s": round(V / 2 * sa_n / (sa_ms * 1e-3), 0)},
+           "overrelaxation": {"sweeps": r.sweeps, "sweeps_fp32": r.sweeps_lo,
+                              "ms": round(or_ms, 1),
+                              "site_updates_per_s": round(V * r.sweeps / (or_ms * 1e-3), 0)},
+           "theta_t_max": float(th.max().item()), "F_t_mean": float(F.mean().item()),
+           "plaquette_change": abs(P1.item() - P0.item())}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def batch_main(args):
+    """Gribov-copy batch: 64 Haar copies each of 16^4 (beta 5.8), 24^4 (6.0) and
+    12^3 x 24 (5.9) heatbath configurations, annealing 2000 steps (T 1.2 -> 0.01,
+    3 micro) then the mixed fix to theta < 1e-13, all in one batch; then the same
+    copies with overrelaxation only, for the best-F comparison."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1209_4008_amd as gf
+
+    bases = [((16, 16, 16, 16), 5.8, 5), ((24, 24, 24, 24), 6.0, 6), ((24, 12, 12, 12), 5.9, 7)]
+    copies = 64
+    ctx = gf.Context(0)
+    canon = []
+    for dims, beta, seed in bases:
+        canon.append(inputs.gpu_heatbath(dims, beta, args.therm, seed))
+    torch.cuda.synchronize()
+    geoms, fields, owner = [], [], []
+    for k, (dims, beta, seed) in enumerate(bases):
+        g = gf.Geom.make(dims, gf.FP64, gf.R12)
+        for cp in range(copies):
+            c = canon[k].clone()
+            inputs.gpu_haar_copy(c, dims, 1000 + seed, cp)
+            f = ctx.empty_field(g)
+            ctx.pack(g, c, f)
+            geoms.append(g)
+            fields.append(f)
+            owner.append(k)
+    sites = sum(g.volume for g in geoms)
+    pristine = [f.clone() for f in fields]
+    ctx.autotune(gf.Geom.make((24,) * 4, gf.FP32, gf.R12), gf.LANDAU)
+    ctx.autotune(gf.Geom.make((24,) * 4, gf.FP64, gf.R12), gf.LANDAU)
+    out = {"metric": "Gribov-copy batch: copies/s and best F per base configuration",
+           "workload": "64 Haar copies each of 16^4 b5.8, 24^4 b6.0, 12^3x24 b5.9; annealing "
+                       "2000 steps (T 1.2->0.01, 3 micro) + mixed fix theta<1e-13, one batch",
+           "lattices": len(geoms), "sites": sites}
+    for label, sa in (("annealed", 2000), ("overrelaxation_only", 0)):
+        for f, p0 in zip(fields, pristine):
+            f.copy_(p0)
+        b = gf.Batch(ctx, geoms, fields)
+        p = gf.fix_params(omega=args.omega, theta_target=1e-13, theta_switch=1e-6,
+                          max_sweeps=args.max_sweeps, check_every=args.check_every,
+                          flags=gf.FLAG_TIMING | gf.FLAG_GRAPH, sa_steps=sa, sa_micro=3,
+                          sa_T0=1.2, sa_T1=0.01, sa_reunit_every=10, seed=11)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = b.run(p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.close()
+        Fs = np.array([r.F for r in res])
+        per_base = {}
+        for k, (dims, beta, seed) in enumerate(bases):
+            sel = Fs[np.array(owner) == k]
+            per_base["x".join(map(str, dims))] = {
+                "best_F": float(sel.max()), "mean_F": float(sel.mean()),
+                "min_F": float(sel.min()),
+                "copies_within_1e-8_of_best": int((sel > sel.max() - 1e-8).sum())}
+        out[label] = {"total_ms": round(1e3 * dt, 1), "copies_per_s": round(len(geoms) / dt, 2),
+                      "converged": int(sum(r.status == gf.OK for r in res)),
+                      "mean_sweeps": float(np.mean([r.sweeps for r in res])),
+                      "annealing_ms": round(res[0].kernel_ms[4], 1),
+                      "per_base": per_base}
+        log(label, json.dumps(out[label]))
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def probe_main(args):
     """Short fixed workload for rocprofv3 runs (kernel trace or counters)."""
     import torch
@@ -160,6 +287,15 @@ def main():
     if args.probe:
         probe_main(args)
         return
+    if args.workload == "coulomb":
+        coulomb_main(args)
+        return
+    if args.workload == "batch":
+        batch_main(args)
+        return
+    if args.workload == "mixed48":
+        args.dims, args.beta, args.seed, args.therm = "48,48,48,48", 6.2, 3, 400
+        args.max_sweeps = max(args.max_sweeps, 60000)
     import numpy as np
     import torch
 
