@@ -465,11 +465,14 @@ void gen_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4
 
 // ---- device entry points (device memory, enqueued on `stream`) ---------------------
 static int launch_status() { return hipGetLastError() == hipSuccess ? 0 : -4; }
+// clears a stale per-thread error left by an earlier, unrelated runtime call
+static void clear_stale_error() { (void)hipGetLastError(); }
 
 int gen_gpu_unit_field(double* U, const int32_t dims[4], void* stream) {
   if (!U || !dims_ok(dims)) return -1;
   const Lat L = make_lat(dims);
   const int64_t n = 4 * L.V;
+  clear_stale_error();
   hipLaunchKernelGGL(k_unit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                      U, n);
   return launch_status();
@@ -479,6 +482,7 @@ int gen_gpu_config0(double* U, const int32_t dims[4], double eps, uint64_t seed,
   if (!U || !dims_ok(dims)) return -1;
   const Lat L = make_lat(dims);
   const int64_t n = 4 * L.V;
+  clear_stale_error();
   hipLaunchKernelGGL(k_config0, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      (hipStream_t)stream, U, L, eps, seed);
   return launch_status();
@@ -488,6 +492,7 @@ int gen_gpu_haar_copy(double* U, const int32_t dims[4], uint64_t seed, uint32_t 
                       void* stream) {
   if (!U || !dims_ok(dims)) return -1;
   const Lat L = make_lat(dims);
+  clear_stale_error();
   hipLaunchKernelGGL(k_haar_copy, dim3((unsigned)((L.V + 255) / 256)), dim3(256), 0,
                      (hipStream_t)stream, U, L, seed, copy);
   return launch_status();
@@ -498,6 +503,7 @@ int gen_gpu_heatbath_sweep(double* U, const int32_t dims[4], double beta, uint64
   if (!U || !dims_ok(dims) || !(beta > 0.0)) return -1;
   const Lat L = make_lat(dims);
   const int64_t nh = L.V / 2;
+  clear_stale_error();
   for (int mu = 0; mu < 4; ++mu)
     for (int par = 0; par < 2; ++par)
       hipLaunchKernelGGL(k_heatbath, dim3((unsigned)((nh + 127) / 128)), dim3(128), 0,

@@ -255,9 +255,13 @@ gf_status gf_destroy(gf_ctx* c) {
   return GF_OK;
 }
 
+// every entry point starts by clearing a stale per-thread HIP error (left by
+// some earlier, unrelated runtime call), so that launch_check reports the
+// entry point's own launches
 #define CHECK_CTX(c)                                                    \
   do {                                                                  \
     if (!(c)) return GF_ERR_ARG;                                        \
+    (void)hipGetLastError();                                            \
     if (hipSetDevice((c)->device) != hipSuccess)                        \
       return fail((c), GF_ERR_DEVICE, "hipSetDevice(%d) failed", (c)->device); \
   } while (0)

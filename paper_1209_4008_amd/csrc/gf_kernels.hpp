@@ -157,6 +157,37 @@ struct UpdHB {
   }
 };
 
+// Gram-Schmidt on rows 0 and 1 in the field's precision. A 12-real link
+// rebuilds row 2 = conj(row0 x row1), so a norm error of the stored rows
+// reappears, doubled, in row 2; a forward update G U mixes row 2 back into
+// rows 0 and 1, and under strongly mixing updates (hot annealing) the error
+// grows geometrically. Projecting the two stored rows of every forward-updated
+// link keeps it at the rounding level (each link is a forward link once per
+// sweep).
+template <typename T>
+__device__ __forceinline__ void orthonormalize_rows01(Su3<T>& A) {
+  T n0 = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) n0 = fma(A.e[0][b].re, A.e[0][b].re, fma(A.e[0][b].im, A.e[0][b].im, n0));
+  n0 = rsqrt_t(n0);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) A.e[0][b] = cx(A.e[0][b].re * n0, A.e[0][b].im * n0);
+  Cx<T> ip = cx<T>(0, 0);  // sum conj(row0) row1
+#pragma unroll
+  for (int b = 0; b < 3; ++b) ip = cmac_cb(ip, A.e[1][b], A.e[0][b]);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const Cx<T> t = cmul(ip, A.e[0][b]);
+    A.e[1][b] = csub(A.e[1][b], t);
+  }
+  T n1 = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) n1 = fma(A.e[1][b].re, A.e[1][b].re, fma(A.e[1][b].im, A.e[1][b].im, n1));
+  n1 = rsqrt_t(n1);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) A.e[1][b] = cx(A.e[1][b].re * n1, A.e[1][b].im * n1);
+}
+
 template <typename T, class Upd, int I, int J, int SG>
 __device__ __forceinline__ void subgroup_step(Su3<T>& K, Su3<T>& G, uint32_t site, const Upd& upd) {
   T w[4], s[4];
@@ -295,6 +326,7 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
         f = cmac(f, G.e[a][1], Uf[d].e[1][b]);
         A.e[a][b] = cmac(f, G.e[a][2], Uf[d].e[2][b]);
       }
+    if (NC == 6) orthonormalize_rows01(A);
     store_link<T, NC, NT>(Pf + mu * blk, L.vh, h, A);
 #pragma unroll
     for (int a = 0; a < R; ++a)
@@ -309,8 +341,15 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
   }
 }
 
+// occupancy request (minimum waves per SIMD) of the sweep kernels: FP64 with
+// 4 lanes per site fits 3 waves (<= 168 registers)
+template <typename T, int TPS>
+struct SweepWaves {
+  static constexpr int value = 1;
+};
+
 template <typename T, int NC, int GAUGE, class Upd, int TPS, bool NT, bool TRACK = false>
-__global__ __launch_bounds__(kBlock) void k_update_half(v2<T>* __restrict__ U, const Lat L,
+__global__ __launch_bounds__(kBlock, (SweepWaves<T, TPS>::value)) void k_update_half(v2<T>* __restrict__ U, const Lat L,
                                                         const int parity, const Upd upd,
                                                         v2<T>* __restrict__ Gx = nullptr) {
   site_half_update<T, NC, GAUGE, Upd, TPS, NT, TRACK>(U, L, parity, upd, Gx,
