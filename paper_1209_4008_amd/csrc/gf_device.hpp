@@ -26,8 +26,18 @@ struct V2T<double> {
 template <typename T>
 using v2 = typename V2T<T>::type;
 
-__device__ __forceinline__ float rsqrt_t(float x) { return __frsqrt_rn(x); }
-__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+// 1/sqrt(x) for positive normal x. FP32: the hardware estimate (1 ulp).
+// FP64: the hardware estimate refined by two Newton steps for y = x^(-1/2),
+// y <- y (3/2 - x y^2 / 2), each of which squares the relative error.
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  double e = fma(-hx * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-hx * y, y, 0.5);
+  return fma(y, e, y);
+}
 __device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
 

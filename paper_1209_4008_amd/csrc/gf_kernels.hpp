@@ -77,7 +77,8 @@ struct UpdOR {
     const T avsq = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
     const T n = a0sq + avsq;
     if (!(n > Tiny<T>::value)) return false;
-    const T b = (omega * a0sq + avsq) / n;
+    const T rn = rsqrt_t(n);
+    const T b = (omega * a0sq + avsq) * (rn * rn);
     const T c = rsqrt_t(a0sq + b * b * avsq);
     const T bc = b * c;
     s[0] = c * w[0];
@@ -197,6 +198,39 @@ __device__ __forceinline__ void subgroup_step(Su3<T>& K, Su3<T>& G, uint32_t sit
   left_su2<T, I, J>(G, s);
 }
 
+// The three subgroup steps with Gtot = G3 G2 G1 built directly: G1 is an
+// embedding in rows/cols (0,1), G2 G1 only mixes rows 0 and 2 of it, and
+// only the last step is a general row operation. (IEEE arithmetic cannot
+// drop the products with the zeros of a unit matrix, so the general form
+// would do that work.) A declined step (degenerate subgroup) uses s = 1,
+// whose row operation is exact.
+template <typename T, class Upd>
+__device__ __forceinline__ void build_G(Su3<T>& K, Su3<T>& G, uint32_t site, const Upd& upd) {
+  T w[4], s[4], t[4];
+  subgroup_w<T, 0, 1>(K, w);
+  if (!upd(w, site, 0, s)) s[0] = 1, s[1] = s[2] = s[3] = 0;
+  left_su2<T, 0, 1>(K, s);
+  subgroup_w<T, 0, 2>(K, w);
+  if (!upd(w, site, 1, t)) t[0] = 1, t[1] = t[2] = t[3] = 0;
+  left_su2<T, 0, 2>(K, t);
+  // G2 G1: rows of G1 = (g00, g01, 0), (g10, g11, 0), (0, 0, 1)
+  const Cx<T> g00 = cx(s[0], s[3]), g01 = cx(s[2], s[1]);
+  const Cx<T> g10 = cx(-s[2], s[1]), g11 = cx(s[0], -s[3]);
+  const Cx<T> t00 = cx(t[0], t[3]), t02 = cx(t[2], t[1]);
+  const Cx<T> t20 = cx(-t[2], t[1]), t22 = cx(t[0], -t[3]);
+  G.e[0][0] = cmul(t00, g00);
+  G.e[0][1] = cmul(t00, g01);
+  G.e[0][2] = t02;
+  G.e[1][0] = g10;
+  G.e[1][1] = g11;
+  G.e[1][2] = cx<T>(0, 0);
+  G.e[2][0] = cmul(t20, g00);
+  G.e[2][1] = cmul(t20, g01);
+  G.e[2][2] = t22;
+  subgroup_w<T, 1, 2>(K, w);
+  if (upd(w, site, 2, s)) left_su2<T, 1, 2>(G, s);
+}
+
 // ---------------------------------------------------------------------------
 // lane exchange inside a quad (DPP quad_perm): value of lane (l ^ MASK)
 // ---------------------------------------------------------------------------
@@ -293,12 +327,9 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
       }
   }
   lane_sum<T, TPS>(K);
-  Su3<T> G;
-  set_unit(G);
   const uint32_t site = 2 * h + S.xodd;
-  subgroup_step<T, Upd, 0, 1, 0>(K, G, site, upd);
-  subgroup_step<T, Upd, 0, 2, 1>(K, G, site, upd);
-  subgroup_step<T, Upd, 1, 2, 2>(K, G, site, upd);
+  Su3<T> G;
+  build_G<T, Upd>(K, G, site, upd);
   if (TRACK && r == 0) {
     v2<T>* gp = Gx + (size_t)parity * 6 * L.vh;
     Su3<T> gx, A;
