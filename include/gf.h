@@ -113,6 +113,13 @@ gf_status gf_convert(gf_ctx* ctx, const gf_geom* src, const void* U_src, const g
  * omega in [1, 2) (1 = plain relaxation); otherwise GF_ERR_ARG. */
 gf_status gf_sweep(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gauge, int32_t parity,
                    double omega);
+/* Stochastic relaxation half-sweep (Sec. 1): as gf_sweep, but for each site
+ * and subgroup, with probability prob in [0, 1] the microcanonical step
+ * g = ghat^2 replaces the overrelaxation step. Draw: Philox4x32-10, key (seed
+ * low, seed high), counter (site, sweep, 0x1200 | subgroup, 0), first
+ * uniform (u + 1/2) 2^-32 < prob. prob = 0 is gf_sweep. */
+gf_status gf_sweep_sr(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gauge, int32_t parity,
+                      double omega, double prob, uint64_t seed, uint64_t sweep);
 /* Gauge functional eq. (3), normalised so that the unit field gives 1:
  * F = Re sum_{x, mu in D} tr U_mu(x) / (3 |D| V) (Landau, F_dev[0]) or per
  * timeslice / (9 V_s) (Coulomb, F_dev[0..nt-1]). Accumulated in FP64. */
@@ -204,6 +211,10 @@ typedef struct {
   int32_t sa_reserved;     /* must be 0                                                */
   double sa_T0, sa_T1;     /* linear schedule T_k = T0 + (T1 - T0) k / (sa_steps - 1)  */
   uint64_t seed;           /* Philox key of the heatbath draws (sweep index = k)       */
+  /* stochastic relaxation instead of plain overrelaxation (Sec. 1): > 0 uses
+   * gf_sweep_sr with this probability, sweep index = sweeps of the phase, key
+   * = seed; the sweeps are then launched one by one (no graph replay) */
+  double sr_prob;
 } gf_fix_params;
 
 typedef struct {

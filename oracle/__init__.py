@@ -58,6 +58,8 @@ def lib():
             "or_heatbath_half": (C.c_int, [d, i32p, C.c_int, C.c_int, C.c_double,
                                            C.c_uint64, C.c_uint64, i64p]),
             "or_micro_half": (C.c_int, [d, i32p, C.c_int, C.c_int]),
+            "or_sweep_sr": (C.c_int, [d, i32p, C.c_int, C.c_int, C.c_double, C.c_double,
+                                      C.c_uint64, C.c_uint64]),
             "or_anneal_sweep": (C.c_int, [d, i32p, C.c_int, C.c_double, C.c_uint64,
                                           C.c_uint64, C.c_int, i64p]),
         }
@@ -225,6 +227,13 @@ def heatbath_half(U, gauge, parity, T, seed, sweep):
     if rc != 0:
         raise ValueError("or_heatbath_half: bad arguments")
     return capped.value
+
+
+def sweep_sr(U, gauge, parity, omega, prob, seed, sweep):
+    rc = lib().or_sweep_sr(_field(U), _dims(dims_of(U)), int(gauge), int(parity), float(omega),
+                           float(prob), int(seed), int(sweep))
+    if rc != 0:
+        raise ValueError("or_sweep_sr: bad arguments")
 
 
 def micro_half(U, gauge, parity):

@@ -103,6 +103,12 @@ int  or_kp_draw(double alpha, uint64_t seed, uint64_t site, uint64_t sweep,
 /* Full SU(2) draw X (X0 as above, direction uniform) for the same streams. */
 int  or_heatbath_su2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep,
                      int subgroup, double X[4]);
+/* Stochastic relaxation half-sweep (Sec. 1): for each site and subgroup,
+ * with probability prob (Philox draw keyed by seed, counter (site, sweep,
+ * 0x1200 | subgroup, 0), first uniform) the microcanonical step g = ghat^2,
+ * otherwise the overrelaxation step with omega (omega = 1: relaxation). */
+int  or_sweep_sr(double* U, const int32_t dims[4], int gauge, int parity, double omega,
+                 double prob, uint64_t seed, uint64_t sweep);
 /* Heatbath half-sweep of the annealing step at temperature T: the local
  * transformation is drawn with weight exp(Re tr[g K] / T). n_capped (may be
  * NULL) accumulates the number of subgroup updates that hit the attempt cap. */

@@ -265,6 +265,7 @@ static double u01(uint32_t u) { return ((double)u + 0.5) * (1.0 / 4294967296.0);
  *   tag = 0x1000 | kind << 8 | subgroup; kind 0 = KP trial, 1 = direction. */
 #define OR_TAG_KP(sg) (0x1000u | (0u << 8) | (uint32_t)(sg))
 #define OR_TAG_DIR(sg) (0x1000u | (1u << 8) | (uint32_t)(sg))
+#define OR_TAG_SR(sg) (0x1000u | (2u << 8) | (uint32_t)(sg))
 #define OR_KP_MAX_ATTEMPTS 1024
 
 static void draw_block(uint64_t seed, uint64_t site, uint64_t sweep, uint32_t tag,
@@ -332,11 +333,11 @@ int or_heatbath_su2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, 
 /* ------------------------------------------------------------------------- */
 /* site update (Alg. 1 body) for overrelaxation, heatbath and microcanonical  */
 /* ------------------------------------------------------------------------- */
-enum { UPD_OR = 0, UPD_HB = 1, UPD_MICRO = 2 };
+enum { UPD_OR = 0, UPD_HB = 1, UPD_MICRO = 2, UPD_SR = 3 };
 typedef struct {
   int kind;
   double omega;
-  double T;
+  double T;     /* heatbath temperature; stochastic relaxation: probability p */
   uint64_t seed, sweep;
 } upd_t;
 
@@ -383,11 +384,19 @@ static int site_update(double* U, const lat_t* L, int gauge, int64_t s, const up
     double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
     if (qn2 < OR_DEGENERATE) continue;
     mat3 G;
-    if (u->kind == UPD_OR) {
+    int kind = u->kind;
+    if (kind == UPD_SR) {
+      /* stochastic relaxation (Sec. 1): with probability p the
+       * microcanonical step, otherwise the (over)relaxation step */
+      double d[4];
+      draw_block(u->seed, (uint64_t)s, u->sweep, OR_TAG_SR(sg), 0u, d);
+      kind = d[0] < u->T ? UPD_MICRO : UPD_OR;
+    }
+    if (kind == UPD_OR) {
       /* Alg. 1: g -> g^omega, project to SU(2) (19 flop) */
       if (or_overrelax(q, u->omega, g) < 0) continue;
       G = embed_su2(g, i, j);
-    } else if (u->kind == UPD_MICRO) {
+    } else if (kind == UPD_MICRO) {
       /* microcanonical step: g = ghat^2, the reflection through the local
        * maximum; it leaves Re tr[g K] unchanged */
       double n = sqrt(qn2);
@@ -477,6 +486,13 @@ int or_heatbath_sites(double* U, const int32_t dims[4], int gauge, double T, uin
 int or_sweep(double* U, const int32_t dims[4], int gauge, int parity, double omega) {
   if (!(omega >= 1.0 && omega < 2.0)) return -1; /* Sec. 2: omega in [1, 2) */
   upd_t u = {UPD_OR, omega, 0.0, 0, 0};
+  return half_sweep(U, dims, gauge, parity, &u, NULL);
+}
+
+int or_sweep_sr(double* U, const int32_t dims[4], int gauge, int parity, double omega,
+                double prob, uint64_t seed, uint64_t sweep) {
+  if (!(omega >= 1.0 && omega < 2.0) || !(prob >= 0.0 && prob <= 1.0)) return -1;
+  upd_t u = {UPD_SR, omega, prob, seed, sweep};
   return half_sweep(U, dims, gauge, parity, &u, NULL);
 }
 

@@ -432,6 +432,28 @@ gf_status gf_sweep(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32_t 
       "gf_sweep");
 }
 
+gf_status gf_sweep_sr(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32_t parity,
+                      double omega, double prob, uint64_t seed, uint64_t sweep) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_sweep_sr");
+  CHECK_GAUGE_PARITY(c, gauge, parity, "gf_sweep_sr");
+  if (!U) return fail(c, GF_ERR_ARG, "gf_sweep_sr: NULL field");
+  if (!(omega >= 1.0 && omega < 2.0)) return fail(c, GF_ERR_ARG, "gf_sweep_sr: omega must be in [1, 2)");
+  if (!(prob >= 0.0 && prob <= 1.0)) return fail(c, GF_ERR_ARG, "gf_sweep_sr: prob must be in [0, 1]");
+  return launch_update(
+      c, U, g, gauge, parity,
+      [&]<typename T>() {
+        UpdSR<T> u;
+        u.omega = (T)omega;
+        u.prob = prob;
+        u.k0 = (uint32_t)seed;
+        u.k1 = (uint32_t)(seed >> 32);
+        u.sweep = (uint32_t)sweep;
+        return u;
+      },
+      "gf_sweep_sr");
+}
+
 // FP32 half-sweep with g tracking (mixed-precision driver)
 template <class Upd>
 static gf_status update_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32_t gauge,
@@ -459,6 +481,18 @@ static gf_status sweep_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, i
   UpdOR<float> upd;
   upd.omega = (float)omega;
   return update_tracked(c, U, Gx, g, gauge, parity, upd, "tracked overrelaxation");
+}
+
+static gf_status sweep_sr_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32_t gauge,
+                                  int32_t parity, double omega, double prob, uint64_t seed,
+                                  uint64_t sweep) {
+  UpdSR<float> upd;
+  upd.omega = (float)omega;
+  upd.prob = prob;
+  upd.k0 = (uint32_t)seed;
+  upd.k1 = (uint32_t)(seed >> 32);
+  upd.sweep = (uint32_t)sweep;
+  return update_tracked(c, U, Gx, g, gauge, parity, upd, "tracked stochastic relaxation");
 }
 
 // one annealing step on an FP32 field with g tracking
@@ -774,6 +808,8 @@ gf_status check_params(gf_ctx* c, const gf_fix_params* p) {
   if (!(p->theta_target >= 0.0)) return fail(c, GF_ERR_ARG, "gf_fix: bad theta_target");
   if (p->sa_steps < 0 || p->sa_micro < 0 || p->sa_reunit_every < 0 || p->sa_reserved != 0)
     return fail(c, GF_ERR_ARG, "gf_fix: bad annealing parameters");
+  if (!(p->sr_prob >= 0.0 && p->sr_prob <= 1.0))
+    return fail(c, GF_ERR_ARG, "gf_fix: sr_prob must be in [0, 1]");
   if (p->sa_steps > 0 && (!(p->sa_T0 > 0.0) || !(p->sa_T1 > 0.0) || !std::isfinite(p->sa_T0) ||
                           !std::isfinite(p->sa_T1)))
     return fail(c, GF_ERR_ARG, "gf_fix: annealing temperatures must be > 0");
@@ -833,13 +869,22 @@ gf_status do_check(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, bool reu
   return GF_OK;
 }
 
-// enqueue n sweeps (RED then BLACK each) on the context stream
-gf_status enqueue_sweeps(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, double omega,
-                         int32_t n, void* Gx) {
+// enqueue n sweeps (RED then BLACK each) on the context stream; with
+// stochastic relaxation (p->sr_prob > 0) the draws of sweep first + k use
+// sweep index first + k
+gf_status enqueue_sweeps(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge,
+                         const gf_fix_params* p, int32_t n, void* Gx, int32_t first) {
   gf_status st;
+  const bool sr = p->sr_prob > 0.0;
   for (int32_t k = 0; k < n; ++k)
     for (int par = 0; par < 2; ++par) {
-      st = Gx ? sweep_tracked(c, U, Gx, g, gauge, par, omega) : gf_sweep(c, U, g, gauge, par, omega);
+      const uint64_t sw = (uint64_t)(first + k);
+      if (sr)
+        st = Gx ? sweep_sr_tracked(c, U, Gx, g, gauge, par, p->omega, p->sr_prob, p->seed, sw)
+                : gf_sweep_sr(c, U, g, gauge, par, p->omega, p->sr_prob, p->seed, sw);
+      else
+        st = Gx ? sweep_tracked(c, U, Gx, g, gauge, par, p->omega)
+                : gf_sweep(c, U, g, gauge, par, p->omega);
       if (st != GF_OK) return st;
     }
   return GF_OK;
@@ -856,8 +901,8 @@ struct SweepGraph {
   }
 };
 
-gf_status capture_sweeps(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, double omega,
-                         int32_t n, void* Gx, SweepGraph& sg) {
+gf_status capture_sweeps(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge,
+                         const gf_fix_params* p, int32_t n, void* Gx, SweepGraph& sg) {
   if (!c->capture) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
   hipStream_t saved = c->stream;
   c->stream = c->capture;
@@ -867,7 +912,7 @@ gf_status capture_sweeps(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, do
     c->stream = saved;
     return fail(c, GF_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
   }
-  st = enqueue_sweeps(c, U, g, gauge, omega, n, Gx);
+  st = enqueue_sweeps(c, U, g, gauge, p, n, Gx, 0);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(c->capture, &graph);
   c->stream = saved;
@@ -888,7 +933,8 @@ gf_status run_phase(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const g
                     void* Gx = nullptr) {
   gf_status st;
   const int cat = g->prec == GF_FP32 ? 0 : 1;
-  const bool use_graph = (p->flags & GF_FLAG_GRAPH) != 0;
+  // stochastic relaxation changes its kernel arguments every sweep: no replay
+  const bool use_graph = (p->flags & GF_FLAG_GRAPH) != 0 && !(p->sr_prob > 0.0);
   SweepGraph sg;
   for (;;) {
     const bool reunit = p->reunit_at_check && (ph.sweeps > 0 || first_check_reunit);
@@ -900,11 +946,11 @@ gf_status run_phase(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const g
     if (ph.sweeps >= p->max_sweeps) return GF_OK;
     const int32_t n = std::min(p->check_every, p->max_sweeps - ph.sweeps);
     if (use_graph && n == p->check_every && !sg.exec)
-      if ((st = capture_sweeps(c, U, g, gauge, p->omega, n, Gx, sg)) != GF_OK) return st;
+      if ((st = capture_sweeps(c, U, g, gauge, p, n, Gx, sg)) != GF_OK) return st;
     if ((st = tm.begin()) != GF_OK) return st;
     if (use_graph && sg.exec && n == sg.n)
       HIP_OR_FAIL(c, hipGraphLaunch(sg.exec, c->stream));
-    else if ((st = enqueue_sweeps(c, U, g, gauge, p->omega, n, Gx)) != GF_OK)
+    else if ((st = enqueue_sweeps(c, U, g, gauge, p, n, Gx, ph.sweeps)) != GF_OK)
       return st;
     if ((st = tm.end(cat, 2 * (int64_t)n)) != GF_OK) return st;
     ph.sweeps += n;
@@ -1209,19 +1255,32 @@ gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double targe
   HIP_OR_FAIL(c, hipMemcpyAsync(b->d_active, b->h_active, n * sizeof(int), hipMemcpyHostToDevice, c->stream));
   UpdOR<T> upd;
   upd.omega = (T)p->omega;
-  const bool use_graph = (p->flags & GF_FLAG_GRAPH) != 0;
+  const bool sr = p->sr_prob > 0.0;
+  const bool use_graph = (p->flags & GF_FLAG_GRAPH) != 0 && !sr;
   SweepGraph sg;
+  int32_t done = 0;  // sweeps done by the lattices still active
   auto enqueue = [&](int32_t nsw) {
     for (int32_t k = 0; k < nsw; ++k)
       for (int par = 0; par < 2; ++par) {
-        if (lo)
+        if (sr) {
+          UpdSR<T> us;
+          us.omega = (T)p->omega;
+          us.prob = p->sr_prob;
+          us.k0 = (uint32_t)p->seed;
+          us.k1 = (uint32_t)(p->seed >> 32);
+          us.sweep = (uint32_t)(done + k);
+          if (lo)
+            launch_batch_update<T, NC, UpdSR<T>, true>(c, tps, nt, d_sweep, n, ts.blocks, b->d_active, par, us);
+          else
+            launch_batch_update<T, NC, UpdSR<T>, false>(c, tps, nt, d_sweep, n, ts.blocks, b->d_active, par, us);
+        } else if (lo) {
           launch_batch_update<T, NC, UpdOR<T>, true>(c, tps, nt, d_sweep, n, ts.blocks, b->d_active, par, upd);
-        else
+        } else {
           launch_batch_update<T, NC, UpdOR<T>, false>(c, tps, nt, d_sweep, n, ts.blocks, b->d_active, par, upd);
+        }
       }
     return launch_check(c, "gf_batch_run: sweeps");
   };
-  int32_t done = 0;  // sweeps done by the lattices still active
   for (;;) {
     // check: reunitarise (after the first), measure, copy back
     if (p->reunit_at_check && done > 0) {

@@ -189,6 +189,30 @@ __device__ __forceinline__ void orthonormalize_rows01(Su3<T>& A) {
   for (int b = 0; b < 3; ++b) A.e[1][b] = cx(A.e[1][b].re * n1, A.e[1][b].im * n1);
 }
 
+// Stochastic relaxation (Sec. 1): per site and subgroup, with probability
+// prob the microcanonical step, otherwise overrelaxation with omega (omega = 1:
+// relaxation). Draw: Philox key (seed lo, hi), counter (site, sweep,
+// 0x1200 | subgroup, 0), first uniform formed in FP64 in every precision, so
+// the choice is the same in FP32 and FP64.
+constexpr uint32_t kTagSR = 0x1200u;
+
+template <typename T>
+struct UpdSR {
+  T omega;
+  double prob;
+  uint32_t k0, k1, sweep;
+  __device__ __forceinline__ bool operator()(const T w[4], uint32_t site, int sg, T s[4]) const {
+    const U4 d = philox4x32_10(site, sweep, kTagSR | (uint32_t)sg, 0u, k0, k1);
+    if (unit_open<double>(d.v[0]) < prob) {
+      UpdMicro<T> m;
+      return m(w, site, sg, s);
+    }
+    UpdOR<T> o;
+    o.omega = omega;
+    return o(w, site, sg, s);
+  }
+};
+
 template <typename T, class Upd, int I, int J, int SG>
 __device__ __forceinline__ void subgroup_step(Su3<T>& K, Su3<T>& G, uint32_t site, const Upd& upd) {
   T w[4], s[4];
@@ -426,6 +450,14 @@ __device__ __forceinline__ Upd for_lattice(const Upd& u, uint32_t) {
 template <typename T>
 __device__ __forceinline__ UpdHB<T> for_lattice(const UpdHB<T>& u, uint32_t l) {
   UpdHB<T> v = u;
+  const uint64_t seed = (((uint64_t)u.k1 << 32) | u.k0) + l;
+  v.k0 = (uint32_t)seed;
+  v.k1 = (uint32_t)(seed >> 32);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ UpdSR<T> for_lattice(const UpdSR<T>& u, uint32_t l) {
+  UpdSR<T> v = u;
   const uint64_t seed = (((uint64_t)u.k1 << 32) | u.k0) + l;
   v.k0 = (uint32_t)seed;
   v.k1 = (uint32_t)(seed >> 32);

@@ -150,3 +150,43 @@ def test_anneal_resume_is_exact_and_seeded():
     for k in range(4):
         O.anneal_sweep(C, CLB, 1.0 - 0.2 * k, seed=6, sweep=k, n_micro=3)
     assert not np.array_equal(A, C)
+
+
+# ---------------------------------------------------------------------------
+# stochastic relaxation (Sec. 1; tuned against overrelaxation in Fig. 2)
+# ---------------------------------------------------------------------------
+
+def test_stochastic_relaxation_limits():
+    """p = 0 is (over)relaxation and p = 1 the microcanonical step, bit for bit."""
+    dims = (4, 4, 6, 4)
+    U = inputs.config0(dims, 0.6, 51)
+    for gauge in (L, CLB):
+        A, B = U.copy(), U.copy()
+        O.sweep_sr(A, gauge, 0, 1.7, 0.0, 9, 3)
+        O.sweep(B, gauge, 0, 1.7)
+        assert np.array_equal(A, B)
+        A, B = U.copy(), U.copy()
+        O.sweep_sr(A, gauge, 1, 1.3, 1.0, 9, 3)
+        O.micro_half(B, gauge, 1)
+        assert np.array_equal(A, B)
+
+
+def test_stochastic_relaxation_monotone_and_mixed():
+    """Neither branch lowers the local functional, so F never decreases; an
+    intermediate p gives a field different from both limits."""
+    dims = (4, 4, 4, 4)
+    U = inputs.config0(dims, 0.6, 52)
+    F = O.functional(U, L)[0]
+    W = U.copy()
+    for k in range(10):
+        O.sweep_sr(W, L, k % 2, 1.0, 0.3, 5, k // 2)
+        F2 = O.functional(W, L)[0]
+        assert F2 >= F - 1e-14
+        F = F2
+    A, B, C = U.copy(), U.copy(), U.copy()
+    O.sweep_sr(A, L, 0, 1.0, 0.3, 5, 0)
+    O.sweep(B, L, 0, 1.0)
+    O.micro_half(C, L, 0)
+    assert not np.array_equal(A, B) and not np.array_equal(A, C)
+    with pytest.raises(ValueError):
+        O.sweep_sr(U.copy(), L, 0, 1.0, 1.5, 5, 0)
