@@ -366,6 +366,7 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
         f = cmac(f, G.e[a][1], gx.e[1][b]);
         A.e[a][b] = cmac(f, G.e[a][2], gx.e[2][b]);
       }
+    orthonormalize_rows01(A);  // g is stored as 12 reals and left-multiplied too
     store_link<T, 6, NT>(gp, L.vh, h, A);
   }
   constexpr int R = NC / 3;  // stored rows
