@@ -16,10 +16,16 @@
  * Device field (the layout every sweep works on, Sec. 4.1: the gauge field
  *   is split into a RED and a BLACK block and the site index runs fastest):
  *   complex elements of the precision `prec` (float2 or double2),
- *     elem(p, mu, c, h) at offset ((p*4 + mu)*NC + c)*(V/2) + h,
+ *     elem(p, mu, c, h) at offset
+ *       (p*4 + mu)*NC*Vp + (h/128)*128*NC + c*128 + h%128,
  *   p = parity, h = s >> 1 (the half index), c = 3a + b < NC,
  *   NC = storage/2: 9 complex (18 reals) or 6 complex (12 reals: rows 0 and 1;
- *   row 2 is rebuilt as conj(row0 x row1), Sec. 4.1). Size: gf_field_bytes().
+ *   row 2 is rebuilt as conj(row0 x row1), Sec. 4.1), Vp = V/2 rounded up to
+ *   a multiple of 128. That is, each (parity, direction) block is cut into
+ *   tiles of 128 consecutive sites that hold their NC components one after
+ *   another; the site index runs fastest within a tile. Elements of the
+ *   padding sites h >= V/2 are never read. Size: gf_field_bytes() =
+ *   8 Vp storage prec bytes.
  * Gauge: GF_LANDAU uses mu = 0..3 in K(x), F and theta (eq. (3), (5), (7));
  *   GF_COULOMB uses the spatial mu = 1..3 and reports F and theta per
  *   timeslice (arrays of nt doubles). In both gauges each site
@@ -82,7 +88,8 @@ gf_status gf_destroy(gf_ctx* ctx);
 const char* gf_last_error(const gf_ctx* ctx);
 /* Host-only: GF_OK if geom is valid, GF_ERR_ARG otherwise. */
 gf_status gf_check_geom(const gf_geom* geom);
-/* Host-only: bytes of a device field, 4 V storage prec; 0 if geom invalid. */
+/* Host-only: bytes of a device field, 8 Vp storage prec (Vp = V/2 rounded up
+ * to a multiple of 128); 0 if geom invalid. */
 size_t gf_field_bytes(const gf_geom* geom);
 /* Host-only: runs the library's host-side self checks (index arithmetic);
  * GF_OK when they pass. */
@@ -262,8 +269,8 @@ gf_status gf_fix_mixed(gf_ctx* ctx, void* U_lo, const gf_geom* geom_lo, void* U_
  * geoms: n FP64 geometries (extents may differ; all of one storage);
  * U: n caller-owned FP64 device fields, borrowed until gf_batch_destroy;
  * they hold the inputs and receive the results. The batch allocates its FP32
- * working fields and gauge-transformation fields (V x 96 bytes per lattice)
- * at creation. Coulomb batches are GF_ERR_UNSUPPORTED. */
+ * 12-real working fields and FP32 gauge-transformation fields (192 + 48 bytes
+ * per site, padded sites included) at creation. Coulomb batches are GF_ERR_UNSUPPORTED. */
 typedef struct gf_batch gf_batch;
 gf_status gf_batch_create(gf_ctx* ctx, int32_t n, const gf_geom* geoms, void* const* U,
                           int32_t gauge, gf_batch** out);

@@ -97,6 +97,7 @@ static Lat make_lat(const gf_geom* g) {
   L.nx = g->nx;
   L.hx = g->nx / 2;
   L.vh = (uint32_t)((uint64_t)g->nt * g->nz * g->ny * g->nx / 2);
+  L.vp = (uint32_t)padded_half(L.vh);
   L.sy = L.hx;
   L.sz = L.ny * L.hx;
   L.st = L.nz * L.ny * L.hx;
@@ -164,7 +165,7 @@ gf_status gf_check_geom(const gf_geom* geom) { return geom_ok(geom) ? GF_OK : GF
 size_t gf_field_bytes(const gf_geom* geom) {
   if (!geom_ok(geom)) return 0;
   const uint64_t V = (uint64_t)geom->nt * geom->nz * geom->ny * geom->nx;
-  return (size_t)(4 * V * (uint64_t)geom->storage * (uint64_t)geom->prec);
+  return (size_t)(8 * padded_half(V / 2) * (uint64_t)geom->storage * (uint64_t)geom->prec);
 }
 
 // The device index arithmetic (site_of, back_h, fwd_h) run on the host for
@@ -195,6 +196,21 @@ static int selftest_lattice(int nt, int nz, int ny, int nx) {
         if ((uint64_t)(canon(f[0], f[3], f[2], f[1]) >> 1) != hf) return 0;
       }
     }
+  // the tiled element offsets of every (block, component, site) are distinct
+  // and lie inside the 8 blocks of NC * vp elements
+  if (L.vp % kTile != 0 || L.vp < L.vh || L.vp - L.vh >= kTile) return 0;
+  for (int NC : {6, 9}) {
+    std::vector<unsigned char> seen((size_t)8 * NC * L.vp, 0);
+    for (uint32_t pm = 0; pm < 8; ++pm)
+      for (uint32_t h = 0; h < L.vh; ++h) {
+        const size_t base = (size_t)pm * NC * L.vp + (NC == 6 ? tile_offset<6>(h) : tile_offset<9>(h));
+        for (int cc = 0; cc < NC; ++cc) {
+          const size_t e = base + (size_t)cc * kTile;
+          if (e >= seen.size() || seen[e]) return 0;
+          seen[e] = 1;
+        }
+      }
+  }
   return 1;
 }
 
@@ -295,10 +311,10 @@ gf_status gf_unpack(gf_ctx* c, const gf_geom* g, const void* src, double* dst) {
 
 template <typename Ts, int NCs>
 static void launch_convert_to(gf_ctx* c, const gf_geom* d, const void* src, void* dst,
-                              uint32_t vh, int reunit) {
+                              const Lat& L, int reunit) {
   with_type(d, [&]<typename Td, int NCd>() {
-    hipLaunchKernelGGL((k_convert<Ts, NCs, Td, NCd>), dim3(blocks_for(vh), 8), dim3(kBlock), 0,
-                       c->stream, (const v2<Ts>*)src, (v2<Td>*)dst, vh, reunit);
+    hipLaunchKernelGGL((k_convert<Ts, NCs, Td, NCd>), dim3(blocks_for(L.vh), 8), dim3(kBlock), 0,
+                       c->stream, (const v2<Ts>*)src, (v2<Td>*)dst, L.vh, L.vp, reunit);
   });
 }
 
@@ -312,9 +328,9 @@ gf_status gf_convert(gf_ctx* c, const gf_geom* s, const void* src, const gf_geom
   const size_t bs = gf_field_bytes(s), bd = gf_field_bytes(d);
   const char *ps = (const char*)src, *pd = (const char*)dst;
   if (ps < pd + bd && pd < ps + bs) return fail(c, GF_ERR_ARG, "gf_convert: buffers overlap");
-  const uint32_t vh = make_lat(s).vh;
+  const Lat L = make_lat(s);
   with_type(s, [&]<typename Ts, int NCs>() {
-    launch_convert_to<Ts, NCs>(c, d, src, dst, vh, reunitarize ? 1 : 0);
+    launch_convert_to<Ts, NCs>(c, d, src, dst, L, reunitarize ? 1 : 0);
   });
   return launch_check(c, "gf_convert");
 }
@@ -323,10 +339,10 @@ gf_status gf_reunitarize(gf_ctx* c, void* U, const gf_geom* g) {
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_reunitarize");
   if (!U) return fail(c, GF_ERR_ARG, "gf_reunitarize: NULL pointer");
-  const uint32_t vh = make_lat(g).vh;
+  const Lat L = make_lat(g);
   with_type(g, [&]<typename T, int NC>() {
-    hipLaunchKernelGGL((k_reunitarize<T, NC>), dim3(blocks_for(vh), 8), dim3(kBlock), 0,
-                       c->stream, (v2<T>*)U, vh);
+    hipLaunchKernelGGL((k_reunitarize<T, NC>), dim3(blocks_for(L.vh), 8), dim3(kBlock), 0,
+                       c->stream, (v2<T>*)U, L.vh, L.vp);
   });
   return launch_check(c, "gf_reunitarize");
 }
@@ -674,8 +690,8 @@ gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, const void* U_
     }
   } else {
     with_type(g, [&]<typename T, int NC>() {
-      hipLaunchKernelGGL((k_fill_unit<T, NC>), dim3(blocks_for(L.vh), 8), dim3(kBlock), 0,
-                         c->stream, (v2<T>*)scratch, L.vh);
+      hipLaunchKernelGGL((k_fill_unit<T, NC>), dim3(blocks_for(L.vp), 8), dim3(kBlock), 0,
+                         c->stream, (v2<T>*)scratch, L.vp);
     });
   }
   const int reps = 20;
@@ -1013,7 +1029,7 @@ gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
   const bool track = (p->flags & GF_FLAG_NO_TRACK) == 0;
   const Lat L = make_lat(g_lo);
   if (track) {
-    const size_t gbytes = (size_t)2 * L.vh * 6 * sizeof(float) * 2;
+    const size_t gbytes = (size_t)2 * L.vp * 6 * sizeof(float) * 2;
     if (gbytes > c->gbuf_cap) {
       if (c->gbuf) HIP_OR_FAIL(c, hipFree(c->gbuf));
       c->gbuf = nullptr;
@@ -1029,8 +1045,8 @@ gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
   // FP64 input -> FP32 working copy; g = 1
   if ((st = tm.begin()) == GF_OK && (st = gf_convert(c, g_hi, U_hi, g_lo, U_lo, 0)) == GF_OK) {
     if (track)
-      hipLaunchKernelGGL((k_fill_unit<float, 6>), dim3(blocks_for(L.vh), 2), dim3(kBlock), 0,
-                         c->stream, (v2<float>*)c->gbuf, L.vh);
+      hipLaunchKernelGGL((k_fill_unit<float, 6>), dim3(blocks_for(L.vp), 2), dim3(kBlock), 0,
+                         c->stream, (v2<float>*)c->gbuf, L.vp);
     st = launch_check(c, "gf_fix_mixed: init");
     if (st == GF_OK) st = tm.end(3, track ? 2 : 1);
   }
@@ -1154,7 +1170,7 @@ gf_status gf_batch_create(gf_ctx* c, int32_t n, const gf_geom* geoms, void* cons
     b->off32.push_back(s32);
     b->offG.push_back(sG);
     s32 += (gf_field_bytes(&g) + 255) / 256 * 256;
-    sG += ((size_t)b->lat[l].vh * 2 * 6 * 2 * sizeof(float) + 255) / 256 * 256;
+    sG += ((size_t)b->lat[l].vp * 2 * 6 * 2 * sizeof(float) + 255) / 256 * 256;
   }
   auto cleanup = [&](gf_status st, const char* what) {
     gf_batch_destroy(b);
@@ -1411,8 +1427,8 @@ gf_status gf_batch_run(gf_batch* b, const gf_fix_params* p, gf_fix_result* res) 
   for (int l = 0; l < n && st == GF_OK; ++l) {
     st = gf_convert(c, &b->g64[l], b->U64[l], &b->g32[l], (char*)b->arena32 + b->off32[l], 0);
     if (st == GF_OK) {
-      hipLaunchKernelGGL((k_fill_unit<float, 6>), dim3(blocks_for(b->lat[l].vh), 2), dim3(kBlock), 0,
-                         c->stream, (v2<float>*)((char*)b->arenaG + b->offG[l]), b->lat[l].vh);
+      hipLaunchKernelGGL((k_fill_unit<float, 6>), dim3(blocks_for(b->lat[l].vp), 2), dim3(kBlock), 0,
+                         c->stream, (v2<float>*)((char*)b->arenaG + b->offG[l]), b->lat[l].vp);
       st = launch_check(c, "gf_batch_run: init");
     }
   }

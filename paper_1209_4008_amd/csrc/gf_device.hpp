@@ -134,16 +134,37 @@ __device__ __forceinline__ void rebuild_row2(Su3<T>& A) {
 }
 
 // ---------------------------------------------------------------------------
-// device layout: elem(p, mu, c, h) at ((p*4 + mu)*NC + c)*vh + h
+// device layout. The links of one parity p and direction mu form a block; the
+// sites of a parity (half index h) are cut into tiles of kTile, and a block
+// holds, tile after tile, the NC components of its tile's links, kTile
+// elements per component:
+//   elem(p, mu, c, h) = (p*4 + mu)*NC*vp + (h/kTile)*kTile*NC + c*kTile + h%kTile
+// vp = V/2 rounded up to a multiple of kTile; the padding sites of the last
+// tile belong to no lattice site. A wave reading one component of 16..64
+// consecutive sites reads one contiguous run, and the runs of the NC
+// components of a tile lie together (kTile*NC*sizeof elements), which keeps
+// the many concurrent streams of a half-sweep on few DRAM pages.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kTile = 128;
+
+__host__ __device__ constexpr uint64_t padded_half(uint64_t vh) {
+  return (vh + kTile - 1) / kTile * kTile;
+}
+
+// offset of component 0 of half index h inside a block of NC components
+template <int NC>
+__host__ __device__ __forceinline__ size_t tile_offset(uint32_t h) {
+  return (size_t)(h & ~(kTile - 1)) * NC + (h & (kTile - 1));
+}
+
 // NT = true marks the accesses nontemporal (streaming: each link is read and
 // written once per half-sweep, with no reuse to keep in the caches)
 template <typename T, int NC, bool NT = false>
-__device__ __forceinline__ void load_link(const v2<T>* __restrict__ blk, uint32_t vh, uint32_t h,
-                                          Su3<T>& A) {
+__device__ __forceinline__ void load_link(const v2<T>* __restrict__ blk, uint32_t h, Su3<T>& A) {
+  const v2<T>* q = blk + tile_offset<NC>(h);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const v2<T>* p = blk + (size_t)c * vh + h;
+    const v2<T>* p = q + c * kTile;
     const v2<T> v = NT ? __builtin_nontemporal_load(p) : *p;
     A.e[c / 3][c % 3] = cx<T>(v.x, v.y);
   }
@@ -151,14 +172,14 @@ __device__ __forceinline__ void load_link(const v2<T>* __restrict__ blk, uint32_
 }
 
 template <typename T, int NC, bool NT = false>
-__device__ __forceinline__ void store_link(v2<T>* __restrict__ blk, uint32_t vh, uint32_t h,
-                                           const Su3<T>& A) {
+__device__ __forceinline__ void store_link(v2<T>* __restrict__ blk, uint32_t h, const Su3<T>& A) {
+  v2<T>* q = blk + tile_offset<NC>(h);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     v2<T> v;
     v.x = A.e[c / 3][c % 3].re;
     v.y = A.e[c / 3][c % 3].im;
-    v2<T>* p = blk + (size_t)c * vh + h;
+    v2<T>* p = q + c * kTile;
     if (NT)
       __builtin_nontemporal_store(v, p);
     else
@@ -188,6 +209,7 @@ struct Lat {
   uint32_t nt, nz, ny, nx;
   uint32_t hx;           // nx / 2
   uint32_t vh;           // V / 2
+  uint32_t vp;           // V / 2 rounded up to a multiple of kTile (block stride unit)
   uint32_t sy, sz, st;   // half-index strides of y, z, t: hx, ny*hx, nz*ny*hx
   FastDiv div_hx, div_ny, div_nz;
 };

@@ -308,7 +308,8 @@ __device__ __forceinline__ void lane_sum(Su3<T>& K) {
 // same subgroup transformations, and each updates and stores its own links.
 // ---------------------------------------------------------------------------
 // TRACK: also accumulate the site transformation into the gauge-transformation
-// field Gx (layout [p][c][h], 6 complex = rows 0, 1), g(x) <- Gtot g(x); lane 0
+// field Gx (one block per parity, 6 complex = rows 0, 1, tiled like the
+// links), g(x) <- Gtot g(x); lane 0
 // of the site does it. gid = TPS * h + lane.
 template <typename T, int NC, int GAUGE, class Upd, int TPS, bool NT, bool TRACK>
 __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const Lat& L,
@@ -320,7 +321,7 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
   const int r = (int)(gid % TPS);
   if (h >= L.vh) return;  // a site's lanes are all in range or all out
   const Site S = site_of(L, h, parity);
-  const size_t blk = (size_t)NC * L.vh;
+  const size_t blk = (size_t)NC * L.vp;
   v2<T>* __restrict__ Pf = U + (size_t)parity * 4 * blk;
   v2<T>* __restrict__ Pb = U + (size_t)(1 - parity) * 4 * blk;
   uint32_t hb[DPL];
@@ -329,8 +330,8 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
   for (int d = 0; d < DPL; ++d) {
     const int mu = r * DPL + d;
     hb[d] = back_h(L, h, S, mu);
-    load_link<T, NC, NT>(Pf + mu * blk, L.vh, h, Uf[d]);
-    load_link<T, NC, NT>(Pb + mu * blk, L.vh, hb[d], Ub[d]);
+    load_link<T, NC, NT>(Pf + mu * blk, h, Uf[d]);
+    load_link<T, NC, NT>(Pb + mu * blk, hb[d], Ub[d]);
   }
   Su3<T> K;
   set_zero(K);
@@ -355,9 +356,9 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
   Su3<T> G;
   build_G<T, Upd>(K, G, site, upd);
   if (TRACK && r == 0) {
-    v2<T>* gp = Gx + (size_t)parity * 6 * L.vh;
+    v2<T>* gp = Gx + (size_t)parity * 6 * L.vp;
     Su3<T> gx, A;
-    load_link<T, 6, NT>(gp, L.vh, h, gx);
+    load_link<T, 6, NT>(gp, h, gx);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -367,7 +368,7 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
         A.e[a][b] = cmac(f, G.e[a][2], gx.e[2][b]);
       }
     orthonormalize_rows01(A);  // g is stored as 12 reals and left-multiplied too
-    store_link<T, 6, NT>(gp, L.vh, h, A);
+    store_link<T, 6, NT>(gp, h, A);
   }
   constexpr int R = NC / 3;  // stored rows
 #pragma unroll
@@ -383,7 +384,7 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
         A.e[a][b] = cmac(f, G.e[a][2], Uf[d].e[2][b]);
       }
     if (NC == 6) orthonormalize_rows01(A);
-    store_link<T, NC, NT>(Pf + mu * blk, L.vh, h, A);
+    store_link<T, NC, NT>(Pf + mu * blk, h, A);
 #pragma unroll
     for (int a = 0; a < R; ++a)
 #pragma unroll
@@ -393,7 +394,7 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
         f = cmac_cb(f, Ub[d].e[a][1], G.e[b][1]);
         A.e[a][b] = cmac_cb(f, Ub[d].e[a][2], G.e[b][2]);
       }
-    store_link<T, NC, NT>(Pb + mu * blk, L.vh, hb[d], A);
+    store_link<T, NC, NT>(Pb + mu * blk, hb[d], A);
   }
 }
 
@@ -502,11 +503,12 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 }
 
 template <typename T, int NC>
-__device__ __forceinline__ void load_link_f64(const v2<T>* __restrict__ blk, uint32_t vh,
-                                              uint32_t h, Su3<double>& A) {
+__device__ __forceinline__ void load_link_f64(const v2<T>* __restrict__ blk, uint32_t h,
+                                              Su3<double>& A) {
+  const v2<T>* q = blk + tile_offset<NC>(h);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const v2<T> v = blk[(size_t)c * vh + h];
+    const v2<T> v = q[c * kTile];
     A.e[c / 3][c % 3] = cx<double>((double)v.x, (double)v.y);
   }
   if (NC == 6) rebuild_row2(A);
@@ -520,7 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_measure(const v2<T>* __restrict__ U,
   __shared__ double lds[kBlock / 64];
   const uint32_t t = blockIdx.y;
   const uint32_t ht = blockIdx.x * kBlock + threadIdx.x;
-  const size_t blk = (size_t)NC * L.vh;
+  const size_t blk = (size_t)NC * L.vp;
   double f = 0, th = 0;
   if (ht < L.st) {
     const uint32_t h = t * L.st + ht;
@@ -534,8 +536,8 @@ __global__ __launch_bounds__(kBlock) void k_measure(const v2<T>* __restrict__ U,
 #pragma unroll 1
       for (int mu = FirstDir<GAUGE>::value; mu < 4; ++mu) {
         Su3<double> A, B;
-        load_link_f64<T, NC>(Pf + mu * blk, L.vh, h, A);
-        load_link_f64<T, NC>(Pb + mu * blk, L.vh, back_h(L, h, S, mu), B);
+        load_link_f64<T, NC>(Pf + mu * blk, h, A);
+        load_link_f64<T, NC>(Pb + mu * blk, back_h(L, h, S, mu), B);
         f += A.e[0][0].re + A.e[1][1].re + A.e[2][2].re;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -581,7 +583,7 @@ __global__ __launch_bounds__(kBlock) void k_measure_batch(const BatchEntry<T>* _
   const BatchEntry<T> e = tab[l];
   const Lat& L = e.L;
   const uint32_t h = (blockIdx.x - e.first_block) * kBlock + threadIdx.x;
-  const size_t blk = (size_t)NC * L.vh;
+  const size_t blk = (size_t)NC * L.vp;
   double f = 0, th = 0;
   if (h < L.vh) {
 #pragma unroll 1
@@ -594,8 +596,8 @@ __global__ __launch_bounds__(kBlock) void k_measure_batch(const BatchEntry<T>* _
 #pragma unroll 1
       for (int mu = 0; mu < 4; ++mu) {
         Su3<double> A, B;
-        load_link_f64<T, NC>(Pf + mu * blk, L.vh, h, A);
-        load_link_f64<T, NC>(Pb + mu * blk, L.vh, back_h(L, h, S, mu), B);
+        load_link_f64<T, NC>(Pf + mu * blk, h, A);
+        load_link_f64<T, NC>(Pb + mu * blk, back_h(L, h, S, mu), B);
         f += A.e[0][0].re + A.e[1][1].re + A.e[2][2].re;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -679,7 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_plaquette(const v2<T>* __restrict__ 
                                                       double* __restrict__ partial) {
   __shared__ double lds[kBlock / 64];
   const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
-  const size_t blk = (size_t)NC * L.vh;
+  const size_t blk = (size_t)NC * L.vp;
   double acc = 0;
   if (h < L.vh) {
 #pragma unroll 1
@@ -692,10 +694,10 @@ __global__ __launch_bounds__(kBlock) void k_plaquette(const v2<T>* __restrict__ 
 #pragma unroll 1
         for (int nu = mu + 1; nu < 4; ++nu) {
           Su3<double> A, B, C, D;
-          load_link_f64<T, NC>(Pp + mu * blk, L.vh, h, A);
-          load_link_f64<T, NC>(Po + nu * blk, L.vh, fwd_h(L, h, S, mu), B);
-          load_link_f64<T, NC>(Po + mu * blk, L.vh, fwd_h(L, h, S, nu), C);
-          load_link_f64<T, NC>(Pp + nu * blk, L.vh, h, D);
+          load_link_f64<T, NC>(Pp + mu * blk, h, A);
+          load_link_f64<T, NC>(Po + nu * blk, fwd_h(L, h, S, mu), B);
+          load_link_f64<T, NC>(Po + mu * blk, fwd_h(L, h, S, nu), C);
+          load_link_f64<T, NC>(Pp + nu * blk, h, D);
           // Re tr[A B C^dag D^dag] = Re sum_{a,b} (A B)_{ab} (D C)^*_{ab}
           double tr = 0;
 #pragma unroll
@@ -747,41 +749,43 @@ __device__ __forceinline__ void gram_schmidt(Su3<double>& A) {
 }
 
 template <typename Td, int NCd>
-__device__ __forceinline__ void store_link_from_f64(v2<Td>* __restrict__ blk, uint32_t vh,
-                                                    uint32_t h, const Su3<double>& A) {
+__device__ __forceinline__ void store_link_from_f64(v2<Td>* __restrict__ blk, uint32_t h,
+                                                    const Su3<double>& A) {
+  v2<Td>* q = blk + tile_offset<NCd>(h);
 #pragma unroll
   for (int c = 0; c < NCd; ++c) {
     v2<Td> v;
     v.x = (Td)A.e[c / 3][c % 3].re;
     v.y = (Td)A.e[c / 3][c % 3].im;
-    blk[(size_t)c * vh + h] = v;
+    q[c * kTile] = v;
   }
 }
 
-// grid (ceil(vh/kBlock), 8): blockIdx.y = p*4 + mu
+// grid (ceil(vh/kBlock), 8): blockIdx.y = p*4 + mu; vp = padded block stride
 template <typename Ts, int NCs, typename Td, int NCd>
 __global__ __launch_bounds__(kBlock) void k_convert(const v2<Ts>* __restrict__ src,
                                                     v2<Td>* __restrict__ dst, const uint32_t vh,
-                                                    const int reunit) {
+                                                    const uint32_t vp, const int reunit) {
   const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
   if (h >= vh) return;
   const size_t pm = blockIdx.y;
   Su3<double> A;
-  load_link_f64<Ts, NCs>(src + pm * NCs * vh, vh, h, A);
+  load_link_f64<Ts, NCs>(src + pm * NCs * vp, h, A);
   if (reunit) gram_schmidt(A);
-  store_link_from_f64<Td, NCd>(dst + pm * NCd * vh, vh, h, A);
+  store_link_from_f64<Td, NCd>(dst + pm * NCd * vp, h, A);
 }
 
 // in place: same buffer, each thread reads and then writes its own link
 template <typename T, int NC>
-__global__ __launch_bounds__(kBlock) void k_reunitarize(v2<T>* U, const uint32_t vh) {
+__global__ __launch_bounds__(kBlock) void k_reunitarize(v2<T>* U, const uint32_t vh,
+                                                       const uint32_t vp) {
   const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
   if (h >= vh) return;
   const size_t pm = blockIdx.y;
   Su3<double> A;
-  load_link_f64<T, NC>(U + pm * NC * vh, vh, h, A);
+  load_link_f64<T, NC>(U + pm * NC * vp, h, A);
   gram_schmidt(A);
-  store_link_from_f64<T, NC>(U + pm * NC * vh, vh, h, A);
+  store_link_from_f64<T, NC>(U + pm * NC * vp, h, A);
 }
 
 // canonical complex128 U[s][mu][3][3] -> device layout; grid (ceil(V/kBlock), 4)
@@ -795,13 +799,13 @@ __global__ __launch_bounds__(kBlock) void k_pack(const double* __restrict__ src,
   const Site S = site_of(L, h, 0);
   const int p = (int)((S.t + S.z + S.y + (s & 1u)) & 1u);
   const double* q = src + ((size_t)s * 4 + mu) * 18;
-  v2<T>* d = dst + ((size_t)p * 4 + mu) * NC * L.vh;
+  v2<T>* d = dst + ((size_t)p * 4 + mu) * NC * L.vp + tile_offset<NC>(h);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     v2<T> v;
     v.x = (T)q[2 * c];
     v.y = (T)q[2 * c + 1];
-    d[(size_t)c * L.vh + h] = v;
+    d[c * kTile] = v;
   }
 }
 
@@ -815,7 +819,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const v2<T>* __restrict__ src
   const Site S = site_of(L, h, 0);
   const int p = (int)((S.t + S.z + S.y + (s & 1u)) & 1u);
   Su3<double> A;
-  load_link_f64<T, NC>(src + ((size_t)p * 4 + mu) * NC * L.vh, L.vh, h, A);
+  load_link_f64<T, NC>(src + ((size_t)p * 4 + mu) * NC * L.vp, h, A);
   double* q = dst + ((size_t)s * 4 + mu) * 18;
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
@@ -826,18 +830,19 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const v2<T>* __restrict__ src
 
 // the unit field in the device layout (scratch fields of the autotuner, the
 // gauge-transformation field of the mixed-precision driver); grid.y blocks of
-// NC components each
+// NC components each, padding sites included (grid.x covers vp)
 template <typename T, int NC>
-__global__ __launch_bounds__(kBlock) void k_fill_unit(v2<T>* __restrict__ U, const uint32_t vh) {
+__global__ __launch_bounds__(kBlock) void k_fill_unit(v2<T>* __restrict__ U, const uint32_t vp) {
   const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
-  if (h >= vh) return;
+  if (h >= vp) return;
   const size_t pm = blockIdx.y;
+  v2<T>* q = U + pm * NC * vp + tile_offset<NC>(h);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     v2<T> v;
     v.x = (c % 4 == 0) ? T(1) : T(0);  // c = 0, 4, 8 are the diagonal
     v.y = 0;
-    U[(pm * NC + c) * vh + h] = v;
+    q[c * kTile] = v;
   }
 }
 
@@ -855,15 +860,15 @@ __global__ __launch_bounds__(kBlock) void k_reunitarize_batch(const BatchEntry<T
 #pragma unroll 1
   for (int pm = 0; pm < 8; ++pm) {
     Su3<double> A;
-    v2<T>* q = e.U + (size_t)pm * NC * e.L.vh;
-    load_link_f64<T, NC>(q, e.L.vh, h, A);
+    v2<T>* q = e.U + (size_t)pm * NC * e.L.vp;
+    load_link_f64<T, NC>(q, h, A);
     gram_schmidt(A);
-    store_link_from_f64<T, NC>(q, e.L.vh, h, A);
+    store_link_from_f64<T, NC>(q, h, A);
   }
 }
 
-// U_mu(x) <- g(x) U_mu(x) g(x+mu)^dag in FP64, with g (Tg, rows 0 and 1 in
-// the [p][c][h] layout) projected onto SU(3) by Gram-Schmidt first. Each
+// U_mu(x) <- g(x) U_mu(x) g(x+mu)^dag in FP64, with g (Tg, rows 0 and 1, one
+// tiled block per parity) projected onto SU(3) by Gram-Schmidt first. Each
 // thread owns the four forward links of one site and only reads g, so the
 // update is in place. grid (ceil(vh/kBlock), 2): blockIdx.y = parity.
 template <typename T, int NC, typename Tg>
@@ -873,17 +878,17 @@ __global__ __launch_bounds__(kBlock) void k_apply_gauge(v2<T>* __restrict__ U,
   if (h >= L.vh) return;
   const int p = blockIdx.y;
   const Site S = site_of(L, h, p);
-  const size_t blk = (size_t)NC * L.vh;
+  const size_t blk = (size_t)NC * L.vp;
   Su3<double> g;
-  load_link_f64<Tg, 6>(Gx + (size_t)p * 6 * L.vh, L.vh, h, g);
+  load_link_f64<Tg, 6>(Gx + (size_t)p * 6 * L.vp, h, g);
   gram_schmidt(g);
 #pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
     Su3<double> gn, A, B;
-    load_link_f64<Tg, 6>(Gx + (size_t)(1 - p) * 6 * L.vh, L.vh, fwd_h(L, h, S, mu), gn);
+    load_link_f64<Tg, 6>(Gx + (size_t)(1 - p) * 6 * L.vp, fwd_h(L, h, S, mu), gn);
     gram_schmidt(gn);
     v2<T>* q = U + ((size_t)p * 4 + mu) * blk;
-    load_link_f64<T, NC>(q, L.vh, h, A);
+    load_link_f64<T, NC>(q, h, A);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -901,7 +906,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_gauge(v2<T>* __restrict__ U,
         f = cmac_cb(f, B.e[a][1], gn.e[b][1]);
         A.e[a][b] = cmac_cb(f, B.e[a][2], gn.e[b][2]);
       }
-    store_link_from_f64<T, NC>(q, L.vh, h, A);
+    store_link_from_f64<T, NC>(q, h, A);
   }
 }
 

@@ -39,6 +39,9 @@ def test_geometry_validation_and_sizes():
     assert gf.field_bytes(g) == 4 * 8 ** 4 * 18 * 8
     assert gf.field_bytes(gf.Geom.make((32, 32, 32, 32), gf.FP32, gf.R12)) == 4 * 32 ** 4 * 12 * 4
     assert gf.field_bytes(gf.Geom.make((48,) * 4, gf.FP64, gf.R12)) == 4 * 48 ** 4 * 12 * 8
+    # V/2 is padded to whole tiles of 128 sites: 6x4x2x10 has 240 sites per parity
+    assert gf.field_bytes(gf.Geom.make((6, 4, 2, 10), gf.FP32, gf.R18)) == 8 * 256 * 18 * 4
+    assert gf.field_bytes(gf.Geom.make((2, 2, 2, 2), gf.FP64, gf.R12)) == 8 * 128 * 12 * 8
     for bad in [gf.Geom.make((7, 8, 8, 8)), gf.Geom.make((8, 8, 8, 0)),
                 gf.Geom.make((8, 8, 8, 8), 5, gf.R18), gf.Geom.make((8, 8, 8, 8), gf.FP32, 10),
                 gf.Geom.make((2048, 2048, 2048, 2))]:
