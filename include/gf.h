@@ -17,15 +17,15 @@
  *   is split into a RED and a BLACK block and the site index runs fastest):
  *   complex elements of the precision `prec` (float2 or double2),
  *     elem(p, mu, c, h) at offset
- *       (p*4 + mu)*NC*Vp + (h/128)*128*NC + c*128 + h%128,
+ *       p*4*NC*Vp + (h/128)*128*4*NC + (mu*NC + c)*128 + h%128,
  *   p = parity, h = s >> 1 (the half index), c = 3a + b < NC,
  *   NC = storage/2: 9 complex (18 reals) or 6 complex (12 reals: rows 0 and 1;
  *   row 2 is rebuilt as conj(row0 x row1), Sec. 4.1), Vp = V/2 rounded up to
- *   a multiple of 128. That is, each (parity, direction) block is cut into
- *   tiles of 128 consecutive sites that hold their NC components one after
- *   another; the site index runs fastest within a tile. Elements of the
- *   padding sites h >= V/2 are never read. Size: gf_field_bytes() =
- *   8 Vp storage prec bytes.
+ *   a multiple of 128. That is, the sites of each parity are cut into tiles
+ *   of 128 consecutive half indices; a tile holds its links direction after
+ *   direction and component after component, the site index running fastest.
+ *   Elements of the padding sites h >= V/2 are never read. Size:
+ *   gf_field_bytes() = 8 Vp storage prec bytes.
  * Gauge: GF_LANDAU uses mu = 0..3 in K(x), F and theta (eq. (3), (5), (7));
  *   GF_COULOMB uses the spatial mu = 1..3 and reports F and theta per
  *   timeslice (arrays of nt doubles). In both gauges each site

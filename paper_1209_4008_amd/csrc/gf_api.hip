@@ -196,14 +196,26 @@ static int selftest_lattice(int nt, int nz, int ny, int nx) {
         if ((uint64_t)(canon(f[0], f[3], f[2], f[1]) >> 1) != hf) return 0;
       }
     }
-  // the tiled element offsets of every (block, component, site) are distinct
-  // and lie inside the 8 blocks of NC * vp elements
+  // the tiled element offsets of every (parity, direction, component, site)
+  // are distinct and lie inside the field of 8 * NC * vp elements; the same
+  // for the one-matrix-per-site fields (2 * 6 * vp elements)
   if (L.vp % kTile != 0 || L.vp < L.vh || L.vp - L.vh >= kTile) return 0;
+  {
+    std::vector<unsigned char> seen((size_t)2 * 6 * L.vp, 0);
+    for (int pp = 0; pp < 2; ++pp)
+      for (uint32_t h = 0; h < L.vh; ++h)
+        for (int cc = 0; cc < 6; ++cc) {
+          const size_t e = link_offset<6, 1>(L.vp, pp, 0, h) + (size_t)cc * kTile;
+          if (e >= seen.size() || seen[e]) return 0;
+          seen[e] = 1;
+        }
+  }
   for (int NC : {6, 9}) {
     std::vector<unsigned char> seen((size_t)8 * NC * L.vp, 0);
     for (uint32_t pm = 0; pm < 8; ++pm)
       for (uint32_t h = 0; h < L.vh; ++h) {
-        const size_t base = (size_t)pm * NC * L.vp + (NC == 6 ? tile_offset<6>(h) : tile_offset<9>(h));
+        const int pp = (int)(pm >> 2), mu = (int)(pm & 3);
+        const size_t base = NC == 6 ? link_offset<6>(L.vp, pp, mu, h) : link_offset<9>(L.vp, pp, mu, h);
         for (int cc = 0; cc < NC; ++cc) {
           const size_t e = base + (size_t)cc * kTile;
           if (e >= seen.size() || seen[e]) return 0;
@@ -690,7 +702,7 @@ gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, const void* U_
     }
   } else {
     with_type(g, [&]<typename T, int NC>() {
-      hipLaunchKernelGGL((k_fill_unit<T, NC>), dim3(blocks_for(L.vp), 8), dim3(kBlock), 0,
+      hipLaunchKernelGGL((k_fill_unit<T, NC, 4>), dim3(blocks_for(L.vp), 8), dim3(kBlock), 0,
                          c->stream, (v2<T>*)scratch, L.vp);
     });
   }
@@ -1045,7 +1057,7 @@ gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
   // FP64 input -> FP32 working copy; g = 1
   if ((st = tm.begin()) == GF_OK && (st = gf_convert(c, g_hi, U_hi, g_lo, U_lo, 0)) == GF_OK) {
     if (track)
-      hipLaunchKernelGGL((k_fill_unit<float, 6>), dim3(blocks_for(L.vp), 2), dim3(kBlock), 0,
+      hipLaunchKernelGGL((k_fill_unit<float, 6, 1>), dim3(blocks_for(L.vp), 2), dim3(kBlock), 0,
                          c->stream, (v2<float>*)c->gbuf, L.vp);
     st = launch_check(c, "gf_fix_mixed: init");
     if (st == GF_OK) st = tm.end(3, track ? 2 : 1);
@@ -1427,7 +1439,7 @@ gf_status gf_batch_run(gf_batch* b, const gf_fix_params* p, gf_fix_result* res) 
   for (int l = 0; l < n && st == GF_OK; ++l) {
     st = gf_convert(c, &b->g64[l], b->U64[l], &b->g32[l], (char*)b->arena32 + b->off32[l], 0);
     if (st == GF_OK) {
-      hipLaunchKernelGGL((k_fill_unit<float, 6>), dim3(blocks_for(b->lat[l].vp), 2), dim3(kBlock), 0,
+      hipLaunchKernelGGL((k_fill_unit<float, 6, 1>), dim3(blocks_for(b->lat[l].vp), 2), dim3(kBlock), 0,
                          c->stream, (v2<float>*)((char*)b->arenaG + b->offG[l]), b->lat[l].vp);
       st = launch_check(c, "gf_batch_run: init");
     }

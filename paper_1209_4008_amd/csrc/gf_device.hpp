@@ -134,16 +134,18 @@ __device__ __forceinline__ void rebuild_row2(Su3<T>& A) {
 }
 
 // ---------------------------------------------------------------------------
-// device layout. The links of one parity p and direction mu form a block; the
-// sites of a parity (half index h) are cut into tiles of kTile, and a block
-// holds, tile after tile, the NC components of its tile's links, kTile
-// elements per component:
-//   elem(p, mu, c, h) = (p*4 + mu)*NC*vp + (h/kTile)*kTile*NC + c*kTile + h%kTile
+// device layout. The sites of one parity p (half index h) are cut into tiles
+// of kTile; a tile holds the links of its sites direction after direction,
+// and each link's NC components one after another, kTile elements each:
+//   elem(p, mu, c, h) = p*4*NC*vp + (h/kTile)*kTile*4*NC + (mu*NC + c)*kTile
+//                       + h%kTile
 // vp = V/2 rounded up to a multiple of kTile; the padding sites of the last
-// tile belong to no lattice site. A wave reading one component of 16..64
-// consecutive sites reads one contiguous run, and the runs of the NC
-// components of a tile lie together (kTile*NC*sizeof elements), which keeps
-// the many concurrent streams of a half-sweep on few DRAM pages.
+// tile belong to no lattice site and are never read by a site update. A wave
+// reading one component of 16..64 consecutive sites reads one contiguous run,
+// and the forward links of a tile (4*NC runs) lie in one contiguous region,
+// so the many concurrent streams of a half-sweep touch few DRAM pages.
+// Fields with one matrix per site (the gauge transformation, ND = 1) use the
+// same scheme with the direction dropped.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kTile = 128;
 
@@ -151,17 +153,19 @@ __host__ __device__ constexpr uint64_t padded_half(uint64_t vh) {
   return (vh + kTile - 1) / kTile * kTile;
 }
 
-// offset of component 0 of half index h inside a block of NC components
-template <int NC>
-__host__ __device__ __forceinline__ size_t tile_offset(uint32_t h) {
-  return (size_t)(h & ~(kTile - 1)) * NC + (h & (kTile - 1));
+// offset of component 0 of link (p, mu) at half index h; the components
+// follow at strides of kTile
+template <int NC, int ND = 4>
+__host__ __device__ __forceinline__ size_t link_offset(uint32_t vp, int p, int mu, uint32_t h) {
+  return (size_t)p * ND * NC * vp + (size_t)(h & ~(kTile - 1)) * ND * NC +
+         (size_t)(mu * NC) * kTile + (h & (kTile - 1));
 }
 
 // NT = true marks the accesses nontemporal (streaming: each link is read and
-// written once per half-sweep, with no reuse to keep in the caches)
+// written once per half-sweep, with no reuse to keep in the caches).
+// q points at component 0 of the link.
 template <typename T, int NC, bool NT = false>
-__device__ __forceinline__ void load_link(const v2<T>* __restrict__ blk, uint32_t h, Su3<T>& A) {
-  const v2<T>* q = blk + tile_offset<NC>(h);
+__device__ __forceinline__ void load_link(const v2<T>* __restrict__ q, Su3<T>& A) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const v2<T>* p = q + c * kTile;
@@ -172,8 +176,7 @@ __device__ __forceinline__ void load_link(const v2<T>* __restrict__ blk, uint32_
 }
 
 template <typename T, int NC, bool NT = false>
-__device__ __forceinline__ void store_link(v2<T>* __restrict__ blk, uint32_t h, const Su3<T>& A) {
-  v2<T>* q = blk + tile_offset<NC>(h);
+__device__ __forceinline__ void store_link(v2<T>* __restrict__ q, const Su3<T>& A) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     v2<T> v;

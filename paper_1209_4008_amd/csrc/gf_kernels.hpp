@@ -308,8 +308,8 @@ __device__ __forceinline__ void lane_sum(Su3<T>& K) {
 // same subgroup transformations, and each updates and stores its own links.
 // ---------------------------------------------------------------------------
 // TRACK: also accumulate the site transformation into the gauge-transformation
-// field Gx (one block per parity, 6 complex = rows 0, 1, tiled like the
-// links), g(x) <- Gtot g(x); lane 0
+// field Gx (6 complex = rows 0, 1 per site, tiled like the links with one
+// direction), g(x) <- Gtot g(x); lane 0
 // of the site does it. gid = TPS * h + lane.
 template <typename T, int NC, int GAUGE, class Upd, int TPS, bool NT, bool TRACK>
 __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const Lat& L,
@@ -321,17 +321,14 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
   const int r = (int)(gid % TPS);
   if (h >= L.vh) return;  // a site's lanes are all in range or all out
   const Site S = site_of(L, h, parity);
-  const size_t blk = (size_t)NC * L.vp;
-  v2<T>* __restrict__ Pf = U + (size_t)parity * 4 * blk;
-  v2<T>* __restrict__ Pb = U + (size_t)(1 - parity) * 4 * blk;
   uint32_t hb[DPL];
   Su3<T> Uf[DPL], Ub[DPL];
 #pragma unroll
   for (int d = 0; d < DPL; ++d) {
     const int mu = r * DPL + d;
     hb[d] = back_h(L, h, S, mu);
-    load_link<T, NC, NT>(Pf + mu * blk, h, Uf[d]);
-    load_link<T, NC, NT>(Pb + mu * blk, hb[d], Ub[d]);
+    load_link<T, NC, NT>(U + link_offset<NC>(L.vp, parity, mu, h), Uf[d]);
+    load_link<T, NC, NT>(U + link_offset<NC>(L.vp, 1 - parity, mu, hb[d]), Ub[d]);
   }
   Su3<T> K;
   set_zero(K);
@@ -356,9 +353,9 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
   Su3<T> G;
   build_G<T, Upd>(K, G, site, upd);
   if (TRACK && r == 0) {
-    v2<T>* gp = Gx + (size_t)parity * 6 * L.vp;
+    v2<T>* gp = Gx + link_offset<6, 1>(L.vp, parity, 0, h);
     Su3<T> gx, A;
-    load_link<T, 6, NT>(gp, h, gx);
+    load_link<T, 6, NT>(gp, gx);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -368,7 +365,7 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
         A.e[a][b] = cmac(f, G.e[a][2], gx.e[2][b]);
       }
     orthonormalize_rows01(A);  // g is stored as 12 reals and left-multiplied too
-    store_link<T, 6, NT>(gp, h, A);
+    store_link<T, 6, NT>(gp, A);
   }
   constexpr int R = NC / 3;  // stored rows
 #pragma unroll
@@ -384,7 +381,7 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
         A.e[a][b] = cmac(f, G.e[a][2], Uf[d].e[2][b]);
       }
     if (NC == 6) orthonormalize_rows01(A);
-    store_link<T, NC, NT>(Pf + mu * blk, h, A);
+    store_link<T, NC, NT>(U + link_offset<NC>(L.vp, parity, mu, h), A);
 #pragma unroll
     for (int a = 0; a < R; ++a)
 #pragma unroll
@@ -394,7 +391,7 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
         f = cmac_cb(f, Ub[d].e[a][1], G.e[b][1]);
         A.e[a][b] = cmac_cb(f, Ub[d].e[a][2], G.e[b][2]);
       }
-    store_link<T, NC, NT>(Pb + mu * blk, hb[d], A);
+    store_link<T, NC, NT>(U + link_offset<NC>(L.vp, 1 - parity, mu, hb[d]), A);
   }
 }
 
@@ -503,9 +500,7 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 }
 
 template <typename T, int NC>
-__device__ __forceinline__ void load_link_f64(const v2<T>* __restrict__ blk, uint32_t h,
-                                              Su3<double>& A) {
-  const v2<T>* q = blk + tile_offset<NC>(h);
+__device__ __forceinline__ void load_link_f64(const v2<T>* __restrict__ q, Su3<double>& A) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const v2<T> v = q[c * kTile];
@@ -522,22 +517,19 @@ __global__ __launch_bounds__(kBlock) void k_measure(const v2<T>* __restrict__ U,
   __shared__ double lds[kBlock / 64];
   const uint32_t t = blockIdx.y;
   const uint32_t ht = blockIdx.x * kBlock + threadIdx.x;
-  const size_t blk = (size_t)NC * L.vp;
   double f = 0, th = 0;
   if (ht < L.st) {
     const uint32_t h = t * L.st + ht;
 #pragma unroll 1
     for (int p = 0; p < 2; ++p) {
       const Site S = site_of(L, h, p);
-      const v2<T>* Pf = U + (size_t)p * 4 * blk;
-      const v2<T>* Pb = U + (size_t)(1 - p) * 4 * blk;
       Su3<double> K;
       set_zero(K);
 #pragma unroll 1
       for (int mu = FirstDir<GAUGE>::value; mu < 4; ++mu) {
         Su3<double> A, B;
-        load_link_f64<T, NC>(Pf + mu * blk, h, A);
-        load_link_f64<T, NC>(Pb + mu * blk, back_h(L, h, S, mu), B);
+        load_link_f64<T, NC>(U + link_offset<NC>(L.vp, p, mu, h), A);
+        load_link_f64<T, NC>(U + link_offset<NC>(L.vp, 1 - p, mu, back_h(L, h, S, mu)), B);
         f += A.e[0][0].re + A.e[1][1].re + A.e[2][2].re;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -583,21 +575,18 @@ __global__ __launch_bounds__(kBlock) void k_measure_batch(const BatchEntry<T>* _
   const BatchEntry<T> e = tab[l];
   const Lat& L = e.L;
   const uint32_t h = (blockIdx.x - e.first_block) * kBlock + threadIdx.x;
-  const size_t blk = (size_t)NC * L.vp;
   double f = 0, th = 0;
   if (h < L.vh) {
 #pragma unroll 1
     for (int p = 0; p < 2; ++p) {
       const Site S = site_of(L, h, p);
-      const v2<T>* Pf = e.U + (size_t)p * 4 * blk;
-      const v2<T>* Pb = e.U + (size_t)(1 - p) * 4 * blk;
       Su3<double> K;
       set_zero(K);
 #pragma unroll 1
       for (int mu = 0; mu < 4; ++mu) {
         Su3<double> A, B;
-        load_link_f64<T, NC>(Pf + mu * blk, h, A);
-        load_link_f64<T, NC>(Pb + mu * blk, back_h(L, h, S, mu), B);
+        load_link_f64<T, NC>(e.U + link_offset<NC>(L.vp, p, mu, h), A);
+        load_link_f64<T, NC>(e.U + link_offset<NC>(L.vp, 1 - p, mu, back_h(L, h, S, mu)), B);
         f += A.e[0][0].re + A.e[1][1].re + A.e[2][2].re;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -681,23 +670,20 @@ __global__ __launch_bounds__(kBlock) void k_plaquette(const v2<T>* __restrict__ 
                                                       double* __restrict__ partial) {
   __shared__ double lds[kBlock / 64];
   const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
-  const size_t blk = (size_t)NC * L.vp;
   double acc = 0;
   if (h < L.vh) {
 #pragma unroll 1
     for (int p = 0; p < 2; ++p) {
       const Site S = site_of(L, h, p);
-      const v2<T>* Pp = U + (size_t)p * 4 * blk;
-      const v2<T>* Po = U + (size_t)(1 - p) * 4 * blk;
 #pragma unroll 1
       for (int mu = 0; mu < 4; ++mu)
 #pragma unroll 1
         for (int nu = mu + 1; nu < 4; ++nu) {
           Su3<double> A, B, C, D;
-          load_link_f64<T, NC>(Pp + mu * blk, h, A);
-          load_link_f64<T, NC>(Po + nu * blk, fwd_h(L, h, S, mu), B);
-          load_link_f64<T, NC>(Po + mu * blk, fwd_h(L, h, S, nu), C);
-          load_link_f64<T, NC>(Pp + nu * blk, h, D);
+          load_link_f64<T, NC>(U + link_offset<NC>(L.vp, p, mu, h), A);
+          load_link_f64<T, NC>(U + link_offset<NC>(L.vp, 1 - p, nu, fwd_h(L, h, S, mu)), B);
+          load_link_f64<T, NC>(U + link_offset<NC>(L.vp, 1 - p, mu, fwd_h(L, h, S, nu)), C);
+          load_link_f64<T, NC>(U + link_offset<NC>(L.vp, p, nu, h), D);
           // Re tr[A B C^dag D^dag] = Re sum_{a,b} (A B)_{ab} (D C)^*_{ab}
           double tr = 0;
 #pragma unroll
@@ -749,9 +735,8 @@ __device__ __forceinline__ void gram_schmidt(Su3<double>& A) {
 }
 
 template <typename Td, int NCd>
-__device__ __forceinline__ void store_link_from_f64(v2<Td>* __restrict__ blk, uint32_t h,
+__device__ __forceinline__ void store_link_from_f64(v2<Td>* __restrict__ q,
                                                     const Su3<double>& A) {
-  v2<Td>* q = blk + tile_offset<NCd>(h);
 #pragma unroll
   for (int c = 0; c < NCd; ++c) {
     v2<Td> v;
@@ -768,11 +753,11 @@ __global__ __launch_bounds__(kBlock) void k_convert(const v2<Ts>* __restrict__ s
                                                     const uint32_t vp, const int reunit) {
   const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
   if (h >= vh) return;
-  const size_t pm = blockIdx.y;
+  const int p = blockIdx.y >> 2, mu = blockIdx.y & 3;
   Su3<double> A;
-  load_link_f64<Ts, NCs>(src + pm * NCs * vp, h, A);
+  load_link_f64<Ts, NCs>(src + link_offset<NCs>(vp, p, mu, h), A);
   if (reunit) gram_schmidt(A);
-  store_link_from_f64<Td, NCd>(dst + pm * NCd * vp, h, A);
+  store_link_from_f64<Td, NCd>(dst + link_offset<NCd>(vp, p, mu, h), A);
 }
 
 // in place: same buffer, each thread reads and then writes its own link
@@ -781,11 +766,11 @@ __global__ __launch_bounds__(kBlock) void k_reunitarize(v2<T>* U, const uint32_t
                                                        const uint32_t vp) {
   const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
   if (h >= vh) return;
-  const size_t pm = blockIdx.y;
+  v2<T>* q = U + link_offset<NC>(vp, blockIdx.y >> 2, blockIdx.y & 3, h);
   Su3<double> A;
-  load_link_f64<T, NC>(U + pm * NC * vp, h, A);
+  load_link_f64<T, NC>(q, A);
   gram_schmidt(A);
-  store_link_from_f64<T, NC>(U + pm * NC * vp, h, A);
+  store_link_from_f64<T, NC>(q, A);
 }
 
 // canonical complex128 U[s][mu][3][3] -> device layout; grid (ceil(V/kBlock), 4)
@@ -799,7 +784,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(const double* __restrict__ src,
   const Site S = site_of(L, h, 0);
   const int p = (int)((S.t + S.z + S.y + (s & 1u)) & 1u);
   const double* q = src + ((size_t)s * 4 + mu) * 18;
-  v2<T>* d = dst + ((size_t)p * 4 + mu) * NC * L.vp + tile_offset<NC>(h);
+  v2<T>* d = dst + link_offset<NC>(L.vp, p, mu, h);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     v2<T> v;
@@ -819,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const v2<T>* __restrict__ src
   const Site S = site_of(L, h, 0);
   const int p = (int)((S.t + S.z + S.y + (s & 1u)) & 1u);
   Su3<double> A;
-  load_link_f64<T, NC>(src + ((size_t)p * 4 + mu) * NC * L.vp, h, A);
+  load_link_f64<T, NC>(src + link_offset<NC>(L.vp, p, mu, h), A);
   double* q = dst + ((size_t)s * 4 + mu) * 18;
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
@@ -829,14 +814,13 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const v2<T>* __restrict__ src
 }
 
 // the unit field in the device layout (scratch fields of the autotuner, the
-// gauge-transformation field of the mixed-precision driver); grid.y blocks of
-// NC components each, padding sites included (grid.x covers vp)
-template <typename T, int NC>
+// gauge-transformation field of the mixed-precision driver, ND = 1); grid.y =
+// 2 * ND (parity, direction), padding sites included (grid.x covers vp)
+template <typename T, int NC, int ND>
 __global__ __launch_bounds__(kBlock) void k_fill_unit(v2<T>* __restrict__ U, const uint32_t vp) {
   const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
   if (h >= vp) return;
-  const size_t pm = blockIdx.y;
-  v2<T>* q = U + pm * NC * vp + tile_offset<NC>(h);
+  v2<T>* q = U + link_offset<NC, ND>(vp, blockIdx.y / ND, blockIdx.y % ND, h);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     v2<T> v;
@@ -860,10 +844,10 @@ __global__ __launch_bounds__(kBlock) void k_reunitarize_batch(const BatchEntry<T
 #pragma unroll 1
   for (int pm = 0; pm < 8; ++pm) {
     Su3<double> A;
-    v2<T>* q = e.U + (size_t)pm * NC * e.L.vp;
-    load_link_f64<T, NC>(q, h, A);
+    v2<T>* q = e.U + link_offset<NC>(e.L.vp, pm >> 2, pm & 3, h);
+    load_link_f64<T, NC>(q, A);
     gram_schmidt(A);
-    store_link_from_f64<T, NC>(q, h, A);
+    store_link_from_f64<T, NC>(q, A);
   }
 }
 
@@ -878,17 +862,16 @@ __global__ __launch_bounds__(kBlock) void k_apply_gauge(v2<T>* __restrict__ U,
   if (h >= L.vh) return;
   const int p = blockIdx.y;
   const Site S = site_of(L, h, p);
-  const size_t blk = (size_t)NC * L.vp;
   Su3<double> g;
-  load_link_f64<Tg, 6>(Gx + (size_t)p * 6 * L.vp, h, g);
+  load_link_f64<Tg, 6>(Gx + link_offset<6, 1>(L.vp, p, 0, h), g);
   gram_schmidt(g);
 #pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
     Su3<double> gn, A, B;
-    load_link_f64<Tg, 6>(Gx + (size_t)(1 - p) * 6 * L.vp, fwd_h(L, h, S, mu), gn);
+    load_link_f64<Tg, 6>(Gx + link_offset<6, 1>(L.vp, 1 - p, 0, fwd_h(L, h, S, mu)), gn);
     gram_schmidt(gn);
-    v2<T>* q = U + ((size_t)p * 4 + mu) * blk;
-    load_link_f64<T, NC>(q, h, A);
+    v2<T>* q = U + link_offset<NC>(L.vp, p, mu, h);
+    load_link_f64<T, NC>(q, A);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -906,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_gauge(v2<T>* __restrict__ U,
         f = cmac_cb(f, B.e[a][1], gn.e[b][1]);
         A.e[a][b] = cmac_cb(f, B.e[a][2], gn.e[b][2]);
       }
-    store_link_from_f64<T, NC>(q, h, A);
+    store_link_from_f64<T, NC>(q, A);
   }
 }
 
