@@ -56,11 +56,13 @@ def parse():
                     help="launch the sweeps between checks one by one instead of replaying a "
                          "captured hipGraph")
     ap.add_argument("--workload", default="landau32",
-                    choices=("landau32", "mixed48", "coulomb", "batch"),
+                    choices=("landau32", "mixed48", "coulomb", "batch", "scan"),
                     help="landau32 (default, the benchmark line): 32^4 beta 6.0 mixed fix; "
                          "mixed48: 48^4 beta 6.2 mixed vs FP64; coulomb: 32^3x64 beta 6.0 with "
                          "3000 annealing steps then the mixed Coulomb fix; batch: 64 Haar copies "
-                         "each of 16^4, 24^4, 12^3x24 with 2000 annealing steps then the mixed fix")
+                         "each of 16^4, 24^4, 12^3x24 with 2000 annealing steps then the mixed fix; "
+                         "scan: 32^4 sweeps and time against the precision switch, omega and the "
+                         "stochastic-relaxation probability")
     ap.add_argument("--probe", action="store_true",
                     help="kernel probe for profilers: bandwidth probes of known size, then "
                          "20 sweeps of each storage variant on a generated input")
@@ -154,8 +156,11 @@ def coulomb_main(args):
     ctx.pack(ghi, canon, U_hi)
     P0 = ctx.empty_out(1)
     ctx.plaquette(U_hi, ghi, P0)
+    # a few timeslices pass near saddle points of F, where theta_t rises by
+    # orders of magnitude before the sweeps reach a maximum; the fix ends when
+    # the last timeslice is below the target, so the cap is generous
     p = gf.fix_params(omega=args.omega, theta_target=1e-14, theta_switch=1e-6,
-                      max_sweeps=args.max_sweeps, check_every=args.check_every,
+                      max_sweeps=max(args.max_sweeps, 100000), check_every=args.check_every,
                       flags=gf.FLAG_TIMING | gf.FLAG_GRAPH, sa_steps=3000, sa_micro=3,
                       sa_T0=1.45, sa_T1=0.01, sa_reunit_every=10, seed=4)
     torch.cuda.synchronize()
@@ -178,7 +183,9 @@ def coulomb_main(args):
            "overrelaxation": {"sweeps": r.sweeps, "sweeps_fp32": r.sweeps_lo,
                               "ms": round(or_ms, 1),
                               "site_updates_per_s": round(V * r.sweeps / (or_ms * 1e-3), 0)},
-           "theta_t_max": float(th.max().item()), "F_t_mean": float(F.mean().item()),
+           "theta_t_max": float(th.max().item()), "theta_t_median": float(th.median().item()),
+           "timeslices_below_1e-14": int((th < 1e-14).sum().item()),
+           "F_t_mean": float(F.mean().item()),
            "plaquette_change": abs(P1.item() - P0.item())}
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -253,6 +260,87 @@ def batch_main(args):
     print(json.dumps(out), flush=True)
 
 
+def scan_main(args):
+    """Tuning scans on 32^4 heatbath configurations (mixed FP32 -> FP64 driver,
+    12-real storage, g tracked):
+    (1) precision switch: the benchmark configuration (beta 6.0, seed 2) fixed
+        to theta < 1e-14 with the FP32 -> FP64 switch at theta 1e-6 ... 1e-12,
+        against pure FP64;
+    (2) sweeps to theta < 1e-12 on a beta = 6.1 configuration (300 heatbath
+        sweeps, seed 8) against the overrelaxation parameter omega and against
+        the stochastic-relaxation probability (omega = 1), the quantity the
+        paper tunes for its beta = 6.1 32^4 lattice (Sec. 5, Fig. 2 left)."""
+    import torch
+
+    import inputs
+    import paper_1209_4008_amd as gf
+
+    dims = (32, 32, 32, 32)
+    cap = 30000
+    ctx = gf.Context(0)
+    glo = gf.Geom.make(dims, gf.FP32, gf.R12)
+    ghi = gf.Geom.make(dims, gf.FP64, gf.R12)
+    U_lo, U_hi = ctx.empty_field(glo), ctx.empty_field(ghi)
+    out = {"metric": "sweeps and time to theta against the precision switch, omega and the "
+                     "stochastic-relaxation probability",
+           "workload": "32^4 wilson-heatbath beta 6.0 (seed 2) and beta 6.1 (seed 8), "
+                       "300 sweeps each; mixed fp32-r12 -> fp64-r12, check every 100 sweeps, "
+                       "at most %d sweeps per precision phase" % cap}
+
+    def run(canon, **kw):
+        ctx.pack(ghi, canon, U_hi)
+        prm = gf.fix_params(check_every=100, max_sweeps=cap, flags=gf.FLAG_GRAPH, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.fix_mixed(U_lo, glo, U_hi, ghi, gf.LANDAU, prm)
+        torch.cuda.synchronize()
+        return r, 1e3 * (time.perf_counter() - t0)
+
+    canon = inputs.gpu_heatbath(dims, 6.0, 300, 2, progress=100)
+    for g, f in ((glo, U_lo), (ghi, U_hi)):
+        ctx.pack(g, canon, f)
+        ctx.autotune(g, gf.LANDAU, U_like=f)
+    ctx.pack(ghi, canon, U_hi)
+    ref = gf.fix_params(omega=1.7, theta_target=1e-14, max_sweeps=cap, flags=gf.FLAG_GRAPH)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r64 = ctx.fix(U_hi, ghi, gf.LANDAU, ref)
+    torch.cuda.synchronize()
+    t64 = 1e3 * (time.perf_counter() - t0)
+    out["fp64_only"] = {"ms": round(t64, 1), "sweeps": r64.sweeps, "F": r64.F,
+                        "theta": r64.theta, "status": r64.status}
+    log(f"fp64 only: {r64.sweeps} sweeps {t64:.0f} ms")
+    rows = []
+    for sw in (1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12):
+        r, ms = run(canon, omega=1.7, theta_target=1e-14, theta_switch=sw)
+        rows.append({"theta_switch": sw, "ms": round(ms, 1), "sweeps": r.sweeps,
+                     "sweeps_fp32": r.sweeps_lo, "theta_at_switch": r.theta_at_switch,
+                     "theta": r.theta, "status": r.status,
+                     "F_rel_diff_vs_fp64": abs(r.F - r64.F) / abs(r64.F),
+                     "speedup_vs_fp64": round(t64 / ms, 3)})
+        log("switch", rows[-1])
+    out["switch_scan"] = rows
+
+    canon = inputs.gpu_heatbath(dims, 6.1, 300, 8, progress=100)
+    rows = []
+    for w in (1.0, 1.3, 1.5, 1.6, 1.65, 1.7, 1.75, 1.8, 1.85, 1.9, 1.95):
+        r, ms = run(canon, omega=w, theta_target=1e-12, theta_switch=1e-9)
+        rows.append({"omega": w, "sweeps": r.sweeps, "sweeps_fp32": r.sweeps_lo,
+                     "converged": r.status == gf.OK, "ms": round(ms, 1), "F": r.F})
+        log("omega", rows[-1])
+    out["omega_scan"] = rows
+    rows = []
+    for prob in (0.5, 0.7, 0.8, 0.85, 0.9, 0.95):
+        r, ms = run(canon, omega=1.0, theta_target=1e-12, theta_switch=1e-9, sr_prob=prob,
+                    seed=8)
+        rows.append({"sr_prob": prob, "sweeps": r.sweeps, "sweeps_fp32": r.sweeps_lo,
+                     "converged": r.status == gf.OK, "ms": round(ms, 1), "F": r.F})
+        log("sr", rows[-1])
+    out["sr_scan"] = rows
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def probe_main(args):
     """Short fixed workload for rocprofv3 runs (kernel trace or counters)."""
     import torch
@@ -292,6 +380,9 @@ def main():
         return
     if args.workload == "batch":
         batch_main(args)
+        return
+    if args.workload == "scan":
+        scan_main(args)
         return
     if args.workload == "mixed48":
         args.dims, args.beta, args.seed, args.therm = "48,48,48,48", 6.2, 3, 400
