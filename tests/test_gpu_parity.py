@@ -228,3 +228,29 @@ def test_argument_errors_on_gpu(ctx):
         ctx.sweep(None, g, gf.LANDAU, 0, 1.5)
     # the field is untouched by rejected calls
     assert np.array_equal(download(ctx, f, g), U)
+
+
+@pytest.mark.parametrize("prec,storage", [(gf.FP64, gf.R12), (gf.FP32, gf.R12)])
+def test_autotune_choice_and_parity_after(ctx, prec, storage):
+    """The autotuner times six variants on a copy of the caller's field, leaves
+    that field untouched, keeps a variant within 1.5% of the fastest (the
+    built-in one when it qualifies), and the tuned sweep still matches the
+    oracle."""
+    dims = (6, 4, 8, 10)
+    U = inputs.config0(dims, 0.6, 18)
+    f, g = upload(ctx, U, prec, storage)
+    before = download(ctx, f, g)
+    say("autotune", prec, storage)
+    try:
+        (tps, nt), table = ctx.autotune(g, gf.LANDAU, U_like=f)
+        assert set(table) == {(t, n) for t in (1, 2, 4) for n in (0, 1)}
+        assert all(v > 0 for v in table.values())
+        assert table[(tps, nt)] <= 1.015 * min(table.values())
+        default = (4, 1) if prec == gf.FP64 else (2, 0)
+        if table[default] <= 1.015 * min(table.values()):
+            assert (tps, nt) == default
+        assert ctx.get_sweep_variant(prec, storage) == (tps, nt)
+        assert np.array_equal(download(ctx, f, g), before)
+        _half_sweep_check(ctx, U, prec, storage, gf.LANDAU)
+    finally:
+        ctx.set_sweep_variant(prec, storage, 0, -1)
