@@ -36,6 +36,8 @@ def lib():
             "or_set_num_threads": (None, [C.c_int]),
             "or_su2_part": (None, [d, C.c_int, C.c_int, d]),
             "or_overrelax": (C.c_int, [d, C.c_double, d]),
+            "or_overrelax_form": (C.c_int, [d, C.c_double, C.c_int, d]),
+            "or_sweep_form": (C.c_int, [d, i32p, C.c_int, C.c_int, C.c_double, C.c_int]),
             "or_local_K": (None, [d, i32p, C.c_int, C.c_int64, d]),
             "or_sweep": (C.c_int, [d, i32p, C.c_int, C.c_int, C.c_double]),
             "or_update_sites": (C.c_int, [d, i32p, C.c_int, C.c_double, i64p, C.c_int64]),
@@ -48,7 +50,7 @@ def lib():
             "or_reunitarize": (None, [d, C.c_int64]),
             "or_plaquette": (C.c_double, [d, i32p]),
             "or_gauge_transform": (C.c_int, [d, i32p, d]),
-            "or_fix": (C.c_int, [d, i32p, C.c_int, C.c_double, C.c_double, C.c_int32,
+            "or_fix": (C.c_int, [d, i32p, C.c_int, C.c_double, C.c_int, C.c_double, C.c_int32,
                                  C.c_int32, C.c_int32, i32p, d, d]),
             "or_philox4x32": (None, [u32p, u32p, u32p]),
             "or_kp_draw": (C.c_int, [C.c_double, C.c_uint64, C.c_uint64, C.c_uint64,
@@ -114,6 +116,20 @@ def overrelax(q, omega):
     s = np.zeros(4)
     rc = lib().or_overrelax(_dptr(q), float(omega), _dptr(s))
     return None if rc != 0 else s
+
+
+def overrelax_form(q, omega, form):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    s = np.zeros(4)
+    rc = lib().or_overrelax_form(_dptr(q), float(omega), int(form), _dptr(s))
+    return None if rc != 0 else s
+
+
+def sweep_form(U, gauge, parity, omega, form):
+    rc = lib().or_sweep_form(_field(U), _dims(dims_of(U)), int(gauge), int(parity), float(omega),
+                             int(form))
+    if rc != 0:
+        raise ValueError("or_sweep_form: bad arguments")
 
 
 def local_K(U, gauge, s):
@@ -186,11 +202,11 @@ def gauge_transform(U, g):
         raise ValueError("or_gauge_transform: bad arguments")
 
 
-def fix(U, gauge, omega, theta_target, max_sweeps, check_every=100, reunit_at_check=1):
+def fix(U, gauge, omega, theta_target, max_sweeps, check_every=100, reunit_at_check=1, form=0):
     sw = C.c_int32(0)
     F = C.c_double(0.0)
     th = C.c_double(0.0)
-    rc = lib().or_fix(_field(U), _dims(dims_of(U)), int(gauge), float(omega),
+    rc = lib().or_fix(_field(U), _dims(dims_of(U)), int(gauge), float(omega), int(form),
                       float(theta_target), int(max_sweeps), int(check_every),
                       int(reunit_at_check), C.byref(sw), C.byref(F), C.byref(th))
     if rc < 0:

@@ -52,6 +52,13 @@ void or_su2_part(const double M[18], int i, int j, double q[4]);
  * quaternion q of K^dagger (Sec. 2, overrelaxation paragraph; flop-count
  * reading of Alg. 1): unit norm on output. Returns -1 if |q| is degenerate. */
 int  or_overrelax(const double q[4], double omega, double s[4]);
+/* The other forms of g^omega (Sec. 2, overrelaxation paragraph: the power is
+ * taken to first or second order): with g = q/|q| = 1 + a, form 1 is
+ * 1 + omega a, form 2 is 1 + omega a + omega (omega-1)/2 a^2 (both projected
+ * onto SU(2) by normalising), form 3 the exact power (cos(omega phi),
+ * n sin(omega phi)) of g = (cos phi, n sin phi); form 0 is or_overrelax.
+ * Unit norm on output. Returns -1 for a degenerate q or an invalid form. */
+int  or_overrelax_form(const double q[4], double omega, int form, double s[4]);
 /* K(x) of eq. (5) (sum over mu of U_mu(x) + U_mu(x-mu)^dagger) at site s. */
 void or_local_K(const double* U, const int32_t dims[4], int gauge, int64_t s, double K[18]);
 
@@ -59,6 +66,10 @@ void or_local_K(const double* U, const int32_t dims[4], int gauge, int64_t s, do
 /* One checkerboard half-sweep of overrelaxation over the sites of one parity
  * (Alg. 1; omega = 1 is plain relaxation). */
 int  or_sweep(double* U, const int32_t dims[4], int gauge, int parity, double omega);
+/* The same half-sweep with the power g^omega taken in the given form
+ * (or_overrelax_form; form 0 is or_sweep). */
+int  or_sweep_form(double* U, const int32_t dims[4], int gauge, int parity, double omega,
+                   int form);
 /* The same update on a list of sites of one parity only (sampled checks). */
 int  or_update_sites(double* U, const int32_t dims[4], int gauge, double omega,
                      const int64_t* sites, int64_t n);
@@ -82,12 +93,13 @@ double or_plaquette(const double* U, const int32_t dims[4]);
 /* U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger, g[s][3][3] complex128 (eq. (4)). */
 int    or_gauge_transform(double* U, const int32_t dims[4], const double* g);
 
-/* Driver: sweeps (RED then BLACK) with a check every check_every sweeps,
- * starting before the first sweep; at each check after the first, the field
- * is first reunitarised if reunit_at_check != 0. Stops when theta < target
- * (Coulomb: max over timeslices) or when max_sweeps is reached.
- * Returns 0 if converged, 1 if not, <0 on bad arguments. */
-int or_fix(double* U, const int32_t dims[4], int gauge, double omega,
+/* Driver: sweeps (RED then BLACK, g^omega in the given form) with a check
+ * every check_every sweeps, starting before the first sweep; at each check
+ * after the first, the field is first reunitarised if reunit_at_check != 0.
+ * Stops when theta < target (Coulomb: max over timeslices) or when
+ * max_sweeps is reached. Returns 0 if converged, 1 if not, <0 on bad
+ * arguments. */
+int or_fix(double* U, const int32_t dims[4], int gauge, double omega, int form,
            double theta_target, int32_t max_sweeps, int32_t check_every,
            int32_t reunit_at_check, int32_t* sweeps_out, double* F_out,
            double* theta_out);

@@ -230,6 +230,57 @@ int or_overrelax(const double q[4], double omega, double s[4]) {
   return 0;
 }
 
+/* Other forms of the power g^omega of the local maximum g = q/|q| (Sec. 2:
+ * the exponentiation is carried out to first or second order). Writing
+ * g = 1 + a, the binomial series (1 + a)^omega is truncated:
+ *   form 1: 1 + omega a,
+ *   form 2: 1 + omega a + omega (omega - 1)/2 a^2,
+ * and the result is projected back onto SU(2), i.e. the quaternion is divided
+ * by its length. In quaternion components, with a = (g0 - 1, gv) and
+ * a^2 = (a0^2 - |gv|^2, 2 a0 gv), form 2 is
+ *   (1 + omega a0 + omega (omega - 1)/2 (a0^2 - |gv|^2), gv (omega + omega (omega - 1) a0)).
+ *   form 3: the exact power: g = (cos phi, n sin phi) -> (cos(omega phi),
+ *   n sin(omega phi)), phi = atan2(|gv|, g0) in [0, pi]; for gv = 0 the power
+ *   is left at g (phi = 0 or pi, no axis).
+ * form 0 is or_overrelax. Returns -1 if |q| (or the truncated series) is
+ * degenerate. */
+int or_overrelax_form(const double q[4], double omega, int form, double s[4]) {
+  if (form == 0) return or_overrelax(q, omega, s);
+  if (form < 0 || form > 3) return -1;
+  double n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+  if (n2 < OR_DEGENERATE) return -1;
+  double n = sqrt(n2);
+  double g[4] = {q[0] / n, q[1] / n, q[2] / n, q[3] / n};
+  double gv2 = g[1] * g[1] + g[2] * g[2] + g[3] * g[3];
+  double t[4];
+  if (form == 3) {
+    double nv = sqrt(gv2);
+    if (nv == 0.0) {
+      for (int k = 0; k < 4; ++k) s[k] = g[k];
+      return 0;
+    }
+    double phi = atan2(nv, g[0]);
+    double f = sin(omega * phi) / nv;
+    t[0] = cos(omega * phi);
+    t[1] = f * g[1];
+    t[2] = f * g[2];
+    t[3] = f * g[3];
+  } else {
+    double a0 = g[0] - 1.0;
+    double c2 = form == 2 ? 0.5 * omega * (omega - 1.0) : 0.0;
+    t[0] = 1.0 + omega * a0 + c2 * (a0 * a0 - gv2);
+    double fv = omega + 2.0 * c2 * a0;
+    t[1] = fv * g[1];
+    t[2] = fv * g[2];
+    t[3] = fv * g[3];
+  }
+  double m2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2] + t[3] * t[3];
+  if (m2 < OR_DEGENERATE) return -1;
+  double m = sqrt(m2);
+  for (int k = 0; k < 4; ++k) s[k] = t[k] / m;
+  return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as     */
 /* easy as 1, 2, 3", SC'11): 10 rounds of the Philox S-box on a 4x32 counter  */
@@ -339,6 +390,7 @@ typedef struct {
   double omega;
   double T;     /* heatbath temperature; stochastic relaxation: probability p */
   uint64_t seed, sweep;
+  int form;     /* overrelaxation: form of g^omega (0: or_overrelax) */
 } upd_t;
 
 /* First direction entering K, F and theta: Landau all four, Coulomb the
@@ -393,8 +445,8 @@ static int site_update(double* U, const lat_t* L, int gauge, int64_t s, const up
       kind = d[0] < u->T ? UPD_MICRO : UPD_OR;
     }
     if (kind == UPD_OR) {
-      /* Alg. 1: g -> g^omega, project to SU(2) (19 flop) */
-      if (or_overrelax(q, u->omega, g) < 0) continue;
+      /* Alg. 1: g -> g^omega, project to SU(2) (19 flop in form 0) */
+      if (or_overrelax_form(q, u->omega, u->form, g) < 0) continue;
       G = embed_su2(g, i, j);
     } else if (kind == UPD_MICRO) {
       /* microcanonical step: g = ghat^2, the reflection through the local
@@ -461,7 +513,7 @@ int or_update_sites(double* U, const int32_t dims[4], int gauge, double omega,
   int p0 = site_parity(&L, sites[0]);
   for (int64_t k = 0; k < n; ++k)
     if (sites[k] < 0 || sites[k] >= L.V || site_parity(&L, sites[k]) != p0) return -1;
-  upd_t u = {UPD_OR, omega, 0.0, 0, 0};
+  upd_t u = {UPD_OR, omega, 0.0, 0, 0, 0};
 #pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < n; ++k) site_update(U, &L, gauge, sites[k], &u);
   return 0;
@@ -477,7 +529,7 @@ int or_heatbath_sites(double* U, const int32_t dims[4], int gauge, double T, uin
   int p0 = site_parity(&L, sites[0]);
   for (int64_t k = 0; k < n; ++k)
     if (sites[k] < 0 || sites[k] >= L.V || site_parity(&L, sites[k]) != p0) return -1;
-  upd_t u = {UPD_HB, 0.0, T, seed, sweep};
+  upd_t u = {UPD_HB, 0.0, T, seed, sweep, 0};
 #pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < n; ++k) site_update(U, &L, gauge, sites[k], &u);
   return 0;
@@ -485,26 +537,33 @@ int or_heatbath_sites(double* U, const int32_t dims[4], int gauge, double T, uin
 
 int or_sweep(double* U, const int32_t dims[4], int gauge, int parity, double omega) {
   if (!(omega >= 1.0 && omega < 2.0)) return -1; /* Sec. 2: omega in [1, 2) */
-  upd_t u = {UPD_OR, omega, 0.0, 0, 0};
+  upd_t u = {UPD_OR, omega, 0.0, 0, 0, 0};
+  return half_sweep(U, dims, gauge, parity, &u, NULL);
+}
+
+int or_sweep_form(double* U, const int32_t dims[4], int gauge, int parity, double omega,
+                  int form) {
+  if (!(omega >= 1.0 && omega < 2.0) || form < 0 || form > 3) return -1;
+  upd_t u = {UPD_OR, omega, 0.0, 0, 0, form};
   return half_sweep(U, dims, gauge, parity, &u, NULL);
 }
 
 int or_sweep_sr(double* U, const int32_t dims[4], int gauge, int parity, double omega,
                 double prob, uint64_t seed, uint64_t sweep) {
   if (!(omega >= 1.0 && omega < 2.0) || !(prob >= 0.0 && prob <= 1.0)) return -1;
-  upd_t u = {UPD_SR, omega, prob, seed, sweep};
+  upd_t u = {UPD_SR, omega, prob, seed, sweep, 0};
   return half_sweep(U, dims, gauge, parity, &u, NULL);
 }
 
 int or_micro_half(double* U, const int32_t dims[4], int gauge, int parity) {
-  upd_t u = {UPD_MICRO, 0.0, 0.0, 0, 0};
+  upd_t u = {UPD_MICRO, 0.0, 0.0, 0, 0, 0};
   return half_sweep(U, dims, gauge, parity, &u, NULL);
 }
 
 int or_heatbath_half(double* U, const int32_t dims[4], int gauge, int parity, double T,
                      uint64_t seed, uint64_t sweep, int64_t* n_capped) {
   if (!(T > 0.0) || !isfinite(T)) return -1;
-  upd_t u = {UPD_HB, 0.0, T, seed, sweep};
+  upd_t u = {UPD_HB, 0.0, T, seed, sweep, 0};
   return half_sweep(U, dims, gauge, parity, &u, n_capped);
 }
 
@@ -742,11 +801,11 @@ int or_gauge_transform(double* U, const int32_t dims[4], const double* g) {
 /* driver: the while-theta loop of Alg. 1 with a check every check_every      */
 /* sweeps (Sec. 4.1 checks F_g and theta after every 100th iteration)        */
 /* ------------------------------------------------------------------------- */
-int or_fix(double* U, const int32_t dims[4], int gauge, double omega, double theta_target,
-           int32_t max_sweeps, int32_t check_every, int32_t reunit_at_check,
-           int32_t* sweeps_out, double* F_out, double* theta_out) {
+int or_fix(double* U, const int32_t dims[4], int gauge, double omega, int form,
+           double theta_target, int32_t max_sweeps, int32_t check_every,
+           int32_t reunit_at_check, int32_t* sweeps_out, double* F_out, double* theta_out) {
   if (!U || or_check_dims(dims) != 0 || check_every < 1 || max_sweeps < 0) return -1;
-  if (!(omega >= 1.0 && omega < 2.0)) return -1;
+  if (!(omega >= 1.0 && omega < 2.0) || form < 0 || form > 3) return -1;
   int64_t V = or_volume(dims);
   int32_t sweeps = 0;
   int converged = 0;
@@ -758,8 +817,8 @@ int or_fix(double* U, const int32_t dims[4], int gauge, double omega, double the
     if (th < theta_target) { converged = 1; break; }
     if (sweeps >= max_sweeps) break;
     for (int32_t k = 0; k < check_every && sweeps < max_sweeps; ++k) {
-      or_sweep(U, dims, gauge, 0, omega);
-      or_sweep(U, dims, gauge, 1, omega);
+      or_sweep_form(U, dims, gauge, 0, omega, form);
+      or_sweep_form(U, dims, gauge, 1, omega, form);
       ++sweeps;
     }
   }

@@ -158,6 +158,96 @@ def test_overrelax_angle_closed_form():
         assert math.atan2(np.linalg.norm(s[1:]), s[0]) / 1e-5 == pytest.approx(w, rel=1e-8)
 
 
+def quat_of(M):
+    """inverse of su2_matrix for one 2x2 matrix"""
+    return np.array([M[0, 0].real, M[0, 1].imag, M[0, 1].real, M[0, 0].imag])
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_overrelax_series_forms_from_matrix_algebra(form):
+    """Forms 1 and 2 (Sec. 2: the power to first or second order): the binomial
+    series of (1 + A)^omega, A = G - 1, truncated after the first or second
+    order and projected onto SU(2), evaluated here with 2x2 complex matrices."""
+    rng = np.random.default_rng(40 + form)
+    I2 = np.eye(2)
+    for _ in range(300):
+        q = rng.normal(size=4) * rng.uniform(0.1, 10)
+        w = rng.uniform(1.0, 2.0)
+        G = su2_matrix(q / np.linalg.norm(q))[0]
+        A = G - I2
+        S = I2 + w * A
+        if form == 2:
+            S = S + 0.5 * w * (w - 1) * (A @ A)
+        S = S / np.sqrt(np.linalg.det(S).real)
+        assert np.allclose(O.overrelax_form(q, w, form), quat_of(S), atol=1e-13)
+
+
+def test_overrelax_exact_power():
+    """Form 3 is the principal power G^omega of the SU(2) matrix of g = q/|q|:
+    the rotation angle times omega about the same axis."""
+    from scipy.linalg import fractional_matrix_power
+    rng = np.random.default_rng(44)
+    for _ in range(200):
+        q = rng.normal(size=4) * rng.uniform(0.1, 10)
+        if q[0] < -0.95 * np.linalg.norm(q):
+            continue  # principal branch ill-conditioned near G = -1
+        w = rng.uniform(1.0, 2.0)
+        G = su2_matrix(q / np.linalg.norm(q))[0]
+        S = fractional_matrix_power(G, w)
+        assert np.allclose(O.overrelax_form(q, w, 3), quat_of(S), atol=1e-10)
+    n = np.array([0.36, -0.48, 0.8])
+    for phi in (1e-6, 0.2, 1.1, 2.5):
+        q = 3.0 * np.concatenate([[math.cos(phi)], math.sin(phi) * n])
+        s = O.overrelax_form(q, 1.6, 3)
+        assert s[0] == pytest.approx(math.cos(1.6 * phi), abs=1e-14)
+        assert np.allclose(s[1:], math.sin(1.6 * phi) * n, atol=1e-14)
+
+
+def test_overrelax_forms_limits_and_monotone():
+    rng = np.random.default_rng(45)
+    for _ in range(200):
+        q = rng.normal(size=4) * rng.uniform(0.1, 10)
+        g = q / np.linalg.norm(q)
+        assert np.array_equal(O.overrelax_form(q, 1.7, 0), O.overrelax(q, 1.7))
+        for form in (1, 2, 3):
+            assert np.allclose(O.overrelax_form(q, 1.0, form), g, atol=1e-15)
+            for w in (1.3, 1.7, 1.99):
+                s = O.overrelax_form(q, w, form)
+                assert np.linalg.norm(s) == pytest.approx(1.0, abs=1e-14)
+                assert s @ g >= g[0] - 1e-12  # local functional not lowered
+                assert np.allclose(np.cross(s[1:], g[1:]), 0, atol=1e-12)
+    assert O.overrelax_form(np.zeros(4), 1.7, 2) is None
+    assert O.overrelax_form(np.ones(4), 1.7, 4) is None
+    assert np.array_equal(O.overrelax_form(np.array([-2.0, 0, 0, 0]), 1.7, 3), [-1.0, 0, 0, 0])
+
+
+@pytest.mark.parametrize("form", [1, 2, 3])
+def test_sweep_forms_monotone_and_pure_gauge(form):
+    dims = (4, 4, 4, 6)
+    U = inputs.config0(dims, 0.6, 21)
+    A = U.copy()
+    O.sweep_form(A, L, 0, 1.7, 0)
+    B = U.copy()
+    O.sweep(B, L, 0, 1.7)
+    assert np.array_equal(A, B)
+    P0 = O.plaquette(U)
+    for gauge in (L, CLB):
+        W = U.copy()
+        F_prev = O.functional(W, gauge)[1]
+        for k in range(10):
+            O.sweep_form(W, gauge, k % 2, 1.7, form)
+            F = O.functional(W, gauge)[1]
+            assert np.all(F >= F_prev - 1e-14), (k, F - F_prev)
+            F_prev = F
+        assert abs(O.plaquette(W) - P0) < 1e-13
+        assert unitarity_dev(W) < 1e-13
+    P = inputs.pure_gauge((4, 4, 4, 4), 5)
+    r = O.fix(P, L, 1.7, 1e-24, 3000, check_every=20, form=form)
+    assert r["converged"] and abs(r["F"] - 1.0) < 1e-12
+    with pytest.raises(ValueError):
+        O.sweep_form(U.copy(), L, 0, 1.7, 5)
+
+
 # ---------------------------------------------------------------------------
 # sweep invariants
 # ---------------------------------------------------------------------------
