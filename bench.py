@@ -269,7 +269,9 @@ def scan_main(args):
     (2) sweeps to theta < 1e-12 on a beta = 6.1 configuration (300 heatbath
         sweeps, seed 8) against the overrelaxation parameter omega and against
         the stochastic-relaxation probability (omega = 1), the quantity the
-        paper tunes for its beta = 6.1 32^4 lattice (Sec. 5, Fig. 2 left)."""
+        paper tunes for its beta = 6.1 32^4 lattice (Sec. 5, Fig. 2 left);
+    (3) the same for the four forms of g^omega at omega 1.7 and 1.85, with
+        the cost per half-sweep of each."""
     import torch
 
     import inputs
@@ -337,6 +339,27 @@ def scan_main(args):
                      "converged": r.status == gf.OK, "ms": round(ms, 1), "F": r.F})
         log("sr", rows[-1])
     out["sr_scan"] = rows
+    # forms of g^omega (0: the 19-flop form; 1, 2: first and second order of the
+    # binomial series; 3: exact power) at omega 1.7 and 1.85: sweeps and cost
+    rows = []
+    for w in (1.7, 1.85):
+        for form in (0, 1, 2, 3):
+            ctx.pack(ghi, canon, U_hi)
+            prm = gf.fix_params(omega=w, theta_target=1e-12, theta_switch=1e-9, check_every=100,
+                                max_sweeps=cap, or_form=form, flags=gf.FLAG_GRAPH | gf.FLAG_TIMING)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.fix_mixed(U_lo, glo, U_hi, ghi, gf.LANDAU, prm)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            rows.append({"omega": w, "form": form, "sweeps": r.sweeps, "sweeps_fp32": r.sweeps_lo,
+                         "converged": r.status == gf.OK, "ms": round(ms, 1), "F": r.F,
+                         "us_per_half_sweep_fp32": round(1e3 * r.kernel_ms[0]
+                                                         / max(r.kernel_launches[0], 1), 2),
+                         "us_per_half_sweep_fp64": round(1e3 * r.kernel_ms[1]
+                                                         / max(r.kernel_launches[1], 1), 2)})
+            log("form", rows[-1])
+    out["form_scan"] = rows
     ctx.close()
     print(json.dumps(out), flush=True)
 

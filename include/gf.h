@@ -120,6 +120,14 @@ gf_status gf_convert(gf_ctx* ctx, const gf_geom* src, const void* U_src, const g
  * omega in [1, 2) (1 = plain relaxation); otherwise GF_ERR_ARG. */
 gf_status gf_sweep(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gauge, int32_t parity,
                    double omega);
+/* gf_sweep with another form of the power g^omega (Sec. 2: the power is taken
+ * to first or second order). With g = q/|q| = 1 + a the local maximum:
+ * form 1: 1 + omega a; form 2: 1 + omega a + omega (omega - 1)/2 a^2; form 3:
+ * the exact power (cos(omega phi), n sin(omega phi)) of g = (cos phi, n sin phi)
+ * (left at g when g has no axis); each divided by its length. form 0 is
+ * gf_sweep. omega in [1, 2), form in 0..3; otherwise GF_ERR_ARG. */
+gf_status gf_sweep_form(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gauge, int32_t parity,
+                        double omega, int32_t form);
 /* Stochastic relaxation half-sweep (Sec. 1): as gf_sweep, but for each site
  * and subgroup, with probability prob in [0, 1] the microcanonical step
  * g = ghat^2 replaces the overrelaxation step. Draw: Philox4x32-10, key (seed
@@ -216,7 +224,10 @@ typedef struct {
   int32_t sa_steps;        /* 0: none; else steps k = 0..sa_steps-1 of gf_anneal_sweep */
   int32_t sa_micro;        /* microcanonical sweeps per step                           */
   int32_t sa_reunit_every; /* reunitarise after every this many steps (0: never)       */
-  int32_t sa_reserved;     /* must be 0                                                */
+  int32_t or_form;         /* form of g^omega in the overrelaxation sweeps (gf_sweep_form):
+                              0 = the 19-flop form of gf_sweep (default), 1 = first order,
+                              2 = second order, 3 = exact; not with sr_prob > 0 and not in
+                              batches (GF_ERR_UNSUPPORTED)                               */
   double sa_T0, sa_T1;     /* linear schedule T_k = T0 + (T1 - T0) k / (sa_steps - 1)  */
   uint64_t seed;           /* Philox key of the heatbath draws (sweep index = k)       */
   /* stochastic relaxation instead of plain overrelaxation (Sec. 1): > 0 uses

@@ -48,7 +48,7 @@ class FixParams(C.Structure):
                 ("theta_switch", C.c_double), ("max_sweeps", C.c_int32),
                 ("check_every", C.c_int32), ("reunit_at_check", C.c_int32),
                 ("flags", C.c_uint32), ("sa_steps", C.c_int32), ("sa_micro", C.c_int32),
-                ("sa_reunit_every", C.c_int32), ("sa_reserved", C.c_int32),
+                ("sa_reunit_every", C.c_int32), ("or_form", C.c_int32),
                 ("sa_T0", C.c_double), ("sa_T1", C.c_double), ("seed", C.c_uint64),
                 ("sr_prob", C.c_double)]
 
@@ -82,6 +82,7 @@ SIGNATURES = {
     "gf_unpack": (C.c_int32, [_vp, _gp, _dp, _dp]),
     "gf_convert": (C.c_int32, [_vp, _gp, _dp, _gp, _dp, C.c_int32]),
     "gf_sweep": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.c_int32, C.c_double]),
+    "gf_sweep_form": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.c_int32, C.c_double, C.c_int32]),
     "gf_sweep_sr": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                 C.c_uint64, C.c_uint64]),
     "gf_functional": (C.c_int32, [_vp, _dp, _gp, C.c_int32, _dp]),
@@ -201,6 +202,10 @@ class Context:
         return self._check(lib().gf_sweep(self.h, _ptr(U), C.byref(geom), int(gauge),
                                           int(parity), float(omega)))
 
+    def sweep_form(self, U, geom, gauge, parity, omega, form):
+        return self._check(lib().gf_sweep_form(self.h, _ptr(U), C.byref(geom), int(gauge),
+                                               int(parity), float(omega), int(form)))
+
     def sweep_sr(self, U, geom, gauge, parity, omega, prob, seed, sweep):
         return self._check(lib().gf_sweep_sr(self.h, _ptr(U), C.byref(geom), int(gauge),
                                              int(parity), float(omega), float(prob), int(seed),
@@ -311,8 +316,8 @@ class Batch:
 
 def fix_params(omega=1.7, theta_target=1e-14, theta_switch=1e-6, max_sweeps=20000,
                check_every=100, reunit_at_check=1, flags=0, sa_steps=0, sa_micro=3,
-               sa_reunit_every=10, sa_T0=1.45, sa_T1=0.01, seed=0, sr_prob=0.0):
+               sa_reunit_every=10, sa_T0=1.45, sa_T1=0.01, seed=0, sr_prob=0.0, or_form=0):
     return FixParams(float(omega), float(theta_target), float(theta_switch), int(max_sweeps),
                      int(check_every), int(reunit_at_check), int(flags), int(sa_steps),
-                     int(sa_micro), int(sa_reunit_every), 0, float(sa_T0), float(sa_T1),
-                     int(seed), float(sr_prob))
+                     int(sa_micro), int(sa_reunit_every), int(or_form), float(sa_T0),
+                     float(sa_T1), int(seed), float(sr_prob))

@@ -460,6 +460,27 @@ gf_status gf_sweep(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32_t 
       "gf_sweep");
 }
 
+gf_status gf_sweep_form(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32_t parity,
+                        double omega, int32_t form) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_sweep_form");
+  CHECK_GAUGE_PARITY(c, gauge, parity, "gf_sweep_form");
+  if (!U) return fail(c, GF_ERR_ARG, "gf_sweep_form: NULL field");
+  if (!(omega >= 1.0 && omega < 2.0))
+    return fail(c, GF_ERR_ARG, "gf_sweep_form: omega must be in [1, 2)");
+  if (form < 0 || form > 3) return fail(c, GF_ERR_ARG, "gf_sweep_form: form must be 0..3");
+  if (form == 0) return gf_sweep(c, U, g, gauge, parity, omega);
+  return launch_update(
+      c, U, g, gauge, parity,
+      [&]<typename T>() {
+        UpdORForm<T> u;
+        u.omega = (T)omega;
+        u.form = form;
+        return u;
+      },
+      "gf_sweep_form");
+}
+
 gf_status gf_sweep_sr(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32_t parity,
                       double omega, double prob, uint64_t seed, uint64_t sweep) {
   CHECK_CTX(c);
@@ -511,6 +532,14 @@ static gf_status sweep_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, i
   return update_tracked(c, U, Gx, g, gauge, parity, upd, "tracked overrelaxation");
 }
 
+static gf_status sweep_form_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g,
+                                    int32_t gauge, int32_t parity, double omega, int32_t form) {
+  if (form == 0) return sweep_tracked(c, U, Gx, g, gauge, parity, omega);
+  UpdORForm<float> upd;
+  upd.omega = (float)omega;
+  upd.form = form;
+  return update_tracked(c, U, Gx, g, gauge, parity, upd, "tracked overrelaxation (form)");
+}
 static gf_status sweep_sr_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32_t gauge,
                                   int32_t parity, double omega, double prob, uint64_t seed,
                                   uint64_t sweep) {
@@ -845,8 +874,11 @@ gf_status check_params(gf_ctx* c, const gf_fix_params* p) {
   if (!(p->omega >= 1.0 && p->omega < 2.0)) return fail(c, GF_ERR_ARG, "gf_fix: omega must be in [1, 2)");
   if (p->max_sweeps < 0 || p->check_every < 1) return fail(c, GF_ERR_ARG, "gf_fix: bad sweep counts");
   if (!(p->theta_target >= 0.0)) return fail(c, GF_ERR_ARG, "gf_fix: bad theta_target");
-  if (p->sa_steps < 0 || p->sa_micro < 0 || p->sa_reunit_every < 0 || p->sa_reserved != 0)
+  if (p->sa_steps < 0 || p->sa_micro < 0 || p->sa_reunit_every < 0)
     return fail(c, GF_ERR_ARG, "gf_fix: bad annealing parameters");
+  if (p->or_form < 0 || p->or_form > 3) return fail(c, GF_ERR_ARG, "gf_fix: or_form must be 0..3");
+  if (p->or_form != 0 && p->sr_prob > 0.0)
+    return fail(c, GF_ERR_UNSUPPORTED, "gf_fix: or_form != 0 with stochastic relaxation");
   if (!(p->sr_prob >= 0.0 && p->sr_prob <= 1.0))
     return fail(c, GF_ERR_ARG, "gf_fix: sr_prob must be in [0, 1]");
   if (p->sa_steps > 0 && (!(p->sa_T0 > 0.0) || !(p->sa_T1 > 0.0) || !std::isfinite(p->sa_T0) ||
@@ -922,8 +954,8 @@ gf_status enqueue_sweeps(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge,
         st = Gx ? sweep_sr_tracked(c, U, Gx, g, gauge, par, p->omega, p->sr_prob, p->seed, sw)
                 : gf_sweep_sr(c, U, g, gauge, par, p->omega, p->sr_prob, p->seed, sw);
       else
-        st = Gx ? sweep_tracked(c, U, Gx, g, gauge, par, p->omega)
-                : gf_sweep(c, U, g, gauge, par, p->omega);
+        st = Gx ? sweep_form_tracked(c, U, Gx, g, gauge, par, p->omega, p->or_form)
+                : gf_sweep_form(c, U, g, gauge, par, p->omega, p->or_form);
       if (st != GF_OK) return st;
     }
   return GF_OK;
@@ -1441,6 +1473,7 @@ gf_status gf_batch_run(gf_batch* b, const gf_fix_params* p, gf_fix_result* res) 
   gf_status st = check_params(c, p);
   if (st != GF_OK) return st;
   if (!(p->theta_switch > 0.0)) return fail(c, GF_ERR_ARG, "gf_batch_run: theta_switch must be > 0");
+  if (p->or_form != 0) return fail(c, GF_ERR_UNSUPPORTED, "gf_batch_run: or_form must be 0");
   const int n = b->n;
   for (int l = 0; l < n; ++l) init_result(&res[l]);
   const auto t0 = std::chrono::steady_clock::now();

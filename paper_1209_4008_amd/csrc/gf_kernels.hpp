@@ -89,6 +89,57 @@ struct UpdOR {
   }
 };
 
+__device__ __forceinline__ float atan2_t(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double atan2_t(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ void sincos_t(float a, float* sn, float* cs) { sincosf(a, sn, cs); }
+__device__ __forceinline__ void sincos_t(double a, double* sn, double* cs) { sincos(a, sn, cs); }
+
+// Other forms of g^omega (Sec. 2: the power is taken to first or second
+// order). With g = w/|w| = 1 + a: form 1 is 1 + omega a, form 2 is
+// 1 + omega a + omega (omega - 1)/2 a^2 (a^2 = (a0^2 - |gv|^2, 2 a0 gv)), form 3
+// the exact power (cos(omega phi), n sin(omega phi)) of g = (cos phi, n sin phi),
+// left at g when gv = 0; the result is divided by its length.
+template <typename T>
+struct UpdORForm {
+  T omega;
+  int form;  // 1, 2 or 3 (uniform over the launch)
+  __device__ __forceinline__ bool operator()(const T w[4], uint32_t, int, T s[4]) const {
+    const T n2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+    if (!(n2 > Tiny<T>::value)) return false;
+    const T r = rsqrt_t(n2);
+    const T g0 = w[0] * r, g1 = w[1] * r, g2 = w[2] * r, g3 = w[3] * r;
+    const T gv2 = g1 * g1 + g2 * g2 + g3 * g3;
+    T t0, f;
+    if (form == 3) {
+      const T nv = sqrt(gv2);
+      if (!(nv > T(0))) {
+        s[0] = g0;
+        s[1] = g1;
+        s[2] = g2;
+        s[3] = g3;
+        return true;
+      }
+      T sn, cs;
+      sincos_t(omega * atan2_t(nv, g0), &sn, &cs);
+      t0 = cs;
+      f = sn / nv;
+    } else {
+      const T a0 = g0 - T(1);
+      const T c2 = form == 2 ? T(0.5) * omega * (omega - T(1)) : T(0);
+      t0 = T(1) + omega * a0 + c2 * (a0 * a0 - gv2);
+      f = omega + T(2) * c2 * a0;
+    }
+    const T m2 = t0 * t0 + f * f * gv2;
+    if (!(m2 > Tiny<T>::value)) return false;
+    const T m = rsqrt_t(m2);
+    s[0] = t0 * m;
+    s[1] = f * m * g1;
+    s[2] = f * m * g2;
+    s[3] = f * m * g3;
+    return true;
+  }
+};
+
 // Microcanonical reflection: s = (w/|w|)^2, leaves Re tr[g K] unchanged.
 template <typename T>
 struct UpdMicro {
