@@ -100,6 +100,20 @@ def pure_gauge(dims, seed):
     return U
 
 
+def abelian_gauge(dims, seed, eps=0.5):
+    """Diagonal SU(3) links diag(e^{i t1}, e^{i t2}, e^{-i(t1+t2)}), t uniform in
+    [-eps pi, eps pi] (numpy Philox stream `seed`), hit by a Haar gauge
+    transformation (gen_haar_copy with `seed`, copy 0): a gauge copy of an
+    Abelian field."""
+    rng = np.random.Generator(np.random.Philox(int(seed)))
+    t = rng.uniform(-eps * np.pi, eps * np.pi, size=tuple(dims) + (4, 2))
+    U = np.zeros(tuple(dims) + (4, 3, 3), dtype=np.complex128)
+    U[..., 0, 0] = np.exp(1j * t[..., 0])
+    U[..., 1, 1] = np.exp(1j * t[..., 1])
+    U[..., 2, 2] = np.exp(-1j * (t[..., 0] + t[..., 1]))
+    return haar_copy(U, seed, 0)
+
+
 def haar_copy(U, seed, copy):
     """In place: U_mu(x) <- h(x) U_mu(x) h(x+mu)^dag with Haar h from (seed, copy)."""
     assert U.dtype == np.complex128 and U.flags["C_CONTIGUOUS"]

@@ -37,6 +37,13 @@ def lib():
             "or_su2_part": (None, [d, C.c_int, C.c_int, d]),
             "or_overrelax": (C.c_int, [d, C.c_double, d]),
             "or_overrelax_form": (C.c_int, [d, C.c_double, C.c_int, d]),
+            "or_mag_matrix": (None, [d, i32p, C.c_int64, C.c_int, d]),
+            "or_mag_local_max": (C.c_int, [d, i32p, C.c_int64, C.c_int, d]),
+            "or_mag_sweep": (C.c_int, [d, i32p, C.c_int, C.c_double, C.c_int]),
+            "or_mag_functional": (C.c_double, [d, i32p]),
+            "or_mag_theta": (C.c_double, [d, i32p]),
+            "or_fix_mag": (C.c_int, [d, i32p, C.c_double, C.c_int, C.c_double, C.c_int32,
+                                     C.c_int32, C.c_int32, i32p, d, d]),
             "or_sweep_form": (C.c_int, [d, i32p, C.c_int, C.c_int, C.c_double, C.c_int]),
             "or_local_K": (None, [d, i32p, C.c_int, C.c_int64, d]),
             "or_sweep": (C.c_int, [d, i32p, C.c_int, C.c_int, C.c_double]),
@@ -130,6 +137,44 @@ def sweep_form(U, gauge, parity, omega, form):
                              int(form))
     if rc != 0:
         raise ValueError("or_sweep_form: bad arguments")
+
+
+def mag_matrix(U, s, sg):
+    M = np.zeros(16)
+    lib().or_mag_matrix(_field(U), _dims(dims_of(U)), int(s), int(sg), _dptr(M))
+    return M.reshape(4, 4)
+
+
+def mag_local_max(U, s, sg):
+    a = np.zeros(4)
+    rc = lib().or_mag_local_max(_field(U), _dims(dims_of(U)), int(s), int(sg), _dptr(a))
+    return None if rc != 0 else a
+
+
+def mag_sweep(U, parity, omega, form=0):
+    rc = lib().or_mag_sweep(_field(U), _dims(dims_of(U)), int(parity), float(omega), int(form))
+    if rc != 0:
+        raise ValueError("or_mag_sweep: bad arguments")
+
+
+def mag_functional(U):
+    return lib().or_mag_functional(_field(U), _dims(dims_of(U)))
+
+
+def mag_theta(U):
+    return lib().or_mag_theta(_field(U), _dims(dims_of(U)))
+
+
+def fix_mag(U, omega, theta_target, max_sweeps, check_every=100, reunit_at_check=1, form=0):
+    sw = C.c_int32(0)
+    F = C.c_double(0.0)
+    th = C.c_double(0.0)
+    rc = lib().or_fix_mag(_field(U), _dims(dims_of(U)), float(omega), int(form),
+                          float(theta_target), int(max_sweeps), int(check_every),
+                          int(reunit_at_check), C.byref(sw), C.byref(F), C.byref(th))
+    if rc < 0:
+        raise ValueError("or_fix_mag: bad arguments")
+    return {"converged": rc == 0, "sweeps": sw.value, "F": F.value, "theta": th.value}
 
 
 def local_K(U, gauge, s):

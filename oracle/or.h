@@ -104,6 +104,29 @@ int or_fix(double* U, const int32_t dims[4], int gauge, double omega, int form,
            int32_t reunit_at_check, int32_t* sweeps_out, double* F_out,
            double* theta_out);
 
+/* maximally Abelian gauge (named in Sec. 1 and the summary, functional from
+ * the literature): maximise R = sum_{x,mu} sum_k |U_mu(x)_kk|^2 -------------- */
+/* M (4x4, row major) of the quadratic form R_x(a) = a^T M a + const of the 8
+ * links at site s under the local transformation embed(a) on subgroup sg
+ * ((0,1), (0,2), (1,2)), by polarisation of R evaluated with full products. */
+void   or_mag_matrix(const double* U, const int32_t dims[4], int64_t s, int sg, double M[16]);
+/* The maximiser of R_x over the subgroup: top eigenvector of M restricted to
+ * a3 = 0 (the top eigenvalue is degenerate along the diagonal-phase symmetry),
+ * unit norm, a0 >= 0. Returns -1 if M vanishes. */
+int    or_mag_local_max(const double* U, const int32_t dims[4], int64_t s, int sg, double a[4]);
+/* One checkerboard half-sweep of MAG overrelaxation (maximiser raised to
+ * omega in the given form, or_overrelax_form). */
+int    or_mag_sweep(double* U, const int32_t dims[4], int parity, double omega, int form);
+/* F_MAG = R / (3 * 4 V) (1 when all links are diagonal). */
+double or_mag_functional(const double* U, const int32_t dims[4]);
+/* theta_MAG = (1/(3V)) sum_x sum_sg (M_01^2 + M_02^2): the squared gradient of
+ * R along the six off-diagonal generators, 0 at stationary points. */
+double or_mag_theta(const double* U, const int32_t dims[4]);
+/* Driver as or_fix, with the MAG sweep, functional and theta. */
+int    or_fix_mag(double* U, const int32_t dims[4], double omega, int form, double theta_target,
+                  int32_t max_sweeps, int32_t check_every, int32_t reunit_at_check,
+                  int32_t* sweeps_out, double* F_out, double* theta_out);
+
 /* simulated annealing ----------------------------------------------------- */
 /* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11). */
 void or_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

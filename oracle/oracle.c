@@ -828,6 +828,245 @@ int or_fix(double* U, const int32_t dims[4], int gauge, double omega, int form,
   return converged ? 0 : 1;
 }
 
+/* ------------------------------------------------------------------------- */
+/* maximally Abelian gauge (named in Sec. 1 and the summary; the paper does   */
+/* not write out its functional): maximise                                    */
+/*   R[U] = sum_{x, mu} sum_k |U_mu(x)_kk|^2,                                 */
+/* the weight of the diagonal (Abelian) part of the links.                    */
+/* ------------------------------------------------------------------------- */
+
+/* R of the 8 links at site s after the local transformation G = embed(a) on
+ * the subgroup (i, j): U_mu(s) -> G U_mu(s), U_mu(s - mu) -> U_mu(s - mu) G^dag.
+ * a need not be a unit quaternion (embed is linear in a on the (i, j) block). */
+static double mag_local_R(const double* U, const lat_t* L, int64_t s, const double a[4], int i,
+                          int j) {
+  mat3 G = embed_su2(a, i, j);
+  mat3 Gd = mat_dag(&G);
+  double R = 0.0;
+  for (int mu = 0; mu < 4; ++mu) {
+    mat3 Uf = get_link(U, s, mu);
+    mat3 Ub = get_link(U, neighbour(L, s, mu, -1), mu);
+    mat3 A = mat_mul(&G, &Uf);
+    mat3 B = mat_mul(&Ub, &Gd);
+    for (int k = 0; k < 3; ++k) R += cx_abs2(A.m[k][k]) + cx_abs2(B.m[k][k]);
+  }
+  return R;
+}
+
+/* R is a quadratic form in a plus a constant (the diagonal entries outside
+ * the subgroup do not depend on a): R(a) = a^T M a + C with C = R(0). M by
+ * polarisation: M_kk = R(e_k) - C, M_kl = (R(e_k + e_l) - R(e_k) - R(e_l) + C)/2. */
+static void mag_matrix(const double* U, const lat_t* L, int64_t s, int sg, double M[4][4]) {
+  int i = SG_I[sg], j = SG_J[sg];
+  double zero[4] = {0, 0, 0, 0};
+  double C = mag_local_R(U, L, s, zero, i, j);
+  double Rk[4];
+  for (int k = 0; k < 4; ++k) {
+    double e[4] = {0, 0, 0, 0};
+    e[k] = 1.0;
+    Rk[k] = mag_local_R(U, L, s, e, i, j);
+    M[k][k] = Rk[k] - C;
+  }
+  for (int k = 0; k < 4; ++k)
+    for (int l = k + 1; l < 4; ++l) {
+      double e[4] = {0, 0, 0, 0};
+      e[k] = 1.0;
+      e[l] = 1.0;
+      M[k][l] = M[l][k] = 0.5 * (mag_local_R(U, L, s, e, i, j) - Rk[k] - Rk[l] + C);
+    }
+}
+
+void or_mag_matrix(const double* U, const int32_t dims[4], int64_t s, int sg, double M[16]) {
+  lat_t L = make_lat(dims);
+  double A[4][4];
+  mag_matrix(U, &L, s, sg, A);
+  for (int k = 0; k < 4; ++k)
+    for (int l = 0; l < 4; ++l) M[4 * k + l] = A[k][l];
+}
+
+/* Eigenvector of the largest eigenvalue of a real symmetric 3x3 matrix by
+ * cyclic Jacobi rotations (Golub & Van Loan, Matrix Computations, Sec. 8.5):
+ * each rotation zeroes one off-diagonal entry; sweeps repeat until the
+ * off-diagonal part vanishes to rounding. */
+static void sym3_top_eigvec(const double A_in[3][3], double v[3]) {
+  double A[3][3], Q[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      A[r][c] = A_in[r][c];
+      Q[r][c] = r == c ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= 1e-34 * dia || off == 0.0) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (A[p][q] == 0.0) continue;
+        /* rotation angle: tan(2 t) = 2 A_pq / (A_qq - A_pp), smaller root */
+        double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 3; ++k) { /* A <- A J (columns p, q) */
+          double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) { /* A <- J^T A (rows p, q) */
+          double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) { /* Q <- Q J */
+          double qkp = Q[k][p], qkq = Q[k][q];
+          Q[k][p] = c * qkp - sn * qkq;
+          Q[k][q] = sn * qkp + c * qkq;
+        }
+      }
+  }
+  int best = 0;
+  for (int k = 1; k < 3; ++k)
+    if (A[k][k] > A[best][best]) best = k;
+  for (int k = 0; k < 3; ++k) v[k] = Q[k][best];
+}
+
+/* The maximiser of R over the subgroup: a^T M a is invariant under left
+ * multiplication of g by the diagonal phases diag(e^{it}, e^{-it}) of the
+ * subgroup (they do not change |U_kk|), which rotate (a0, a3) and (a1, a2)
+ * together, so the largest eigenvalue of M is (at least) doubly degenerate
+ * and its eigenspace meets a3 = 0. The maximiser is taken there: the top
+ * eigenvector of the 3x3 block on (a0, a1, a2), sign fixed by a0 >= 0 (then
+ * a1 >= 0, a2 >= 0). Returns -1 if M vanishes. */
+static int mag_local_max(const double M[4][4], double a[4]) {
+  double B[3][3], v[3];
+  double nrm = 0.0;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      B[r][c] = M[r][c];
+      nrm += fabs(M[r][c]);
+    }
+  if (!(nrm > 1e-300)) return -1;
+  sym3_top_eigvec(B, v);
+  double sgn = 1.0;
+  if (v[0] < 0 || (v[0] == 0 && (v[1] < 0 || (v[1] == 0 && v[2] < 0)))) sgn = -1.0;
+  double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  a[0] = sgn * v[0] / n;
+  a[1] = sgn * v[1] / n;
+  a[2] = sgn * v[2] / n;
+  a[3] = 0.0;
+  return 0;
+}
+
+int or_mag_local_max(const double* U, const int32_t dims[4], int64_t s, int sg, double a[4]) {
+  lat_t L = make_lat(dims);
+  double M[4][4];
+  mag_matrix(U, &L, s, sg, M);
+  return mag_local_max(M, a);
+}
+
+/* Alg. 1 with the MAG local step: for each subgroup in turn, M from the
+ * current links, the maximiser a, its power a^omega (or_overrelax_form), and
+ * the 8 links transformed. */
+static void mag_site_update(double* U, const lat_t* L, int64_t s, double omega, int form) {
+  for (int sg = 0; sg < 3; ++sg) {
+    int i = SG_I[sg], j = SG_J[sg];
+    double M[4][4], a[4], g[4];
+    mag_matrix(U, L, s, sg, M);
+    if (mag_local_max(M, a) < 0) continue;
+    if (or_overrelax_form(a, omega, form, g) < 0) continue;
+    mat3 G = embed_su2(g, i, j);
+    mat3 Gd = mat_dag(&G);
+    for (int mu = 0; mu < 4; ++mu) {
+      int64_t sb = neighbour(L, s, mu, -1);
+      mat3 Uf = get_link(U, s, mu);
+      mat3 Ub = get_link(U, sb, mu);
+      mat3 Ufn = mat_mul(&G, &Uf);
+      mat3 Ubn = mat_mul(&Ub, &Gd);
+      put_link(U, s, mu, &Ufn);
+      put_link(U, sb, mu, &Ubn);
+    }
+  }
+}
+
+int or_mag_sweep(double* U, const int32_t dims[4], int parity, double omega, int form) {
+  if (!U || or_check_dims(dims) != 0 || (parity != 0 && parity != 1)) return -1;
+  if (!(omega >= 1.0 && omega < 2.0) || form < 0 || form > 3) return -1;
+  lat_t L = make_lat(dims);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < L.V; ++s)
+    if (site_parity(&L, s) == parity) mag_site_update(U, &L, s, omega, form);
+  return 0;
+}
+
+/* F_MAG = R / (N_c 4 V): 1 exactly when every link is diagonal. */
+double or_mag_functional(const double* U, const int32_t dims[4]) {
+  lat_t L = make_lat(dims);
+  double* per_site = (double*)malloc(sizeof(double) * (size_t)L.V);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < L.V; ++s) {
+    double acc = 0.0;
+    for (int mu = 0; mu < 4; ++mu) {
+      mat3 A = get_link(U, s, mu);
+      for (int k = 0; k < 3; ++k) acc += cx_abs2(A.m[k][k]);
+    }
+    per_site[s] = acc;
+  }
+  double sum = 0.0;
+  for (int64_t s = 0; s < L.V; ++s) sum += per_site[s];
+  free(per_site);
+  return sum / (3.0 * 4.0 * (double)L.V);
+}
+
+/* theta_MAG = (1 / (N_c V)) sum_x sum_subgroups (M_01^2 + M_02^2): at a = 1 the
+ * derivatives of R along the two off-diagonal generators of a subgroup are
+ * 2 M_01 and 2 M_02 (the third, diagonal generator is a symmetry, M_03 = 0),
+ * so theta_MAG vanishes exactly at stationary points of R. */
+double or_mag_theta(const double* U, const int32_t dims[4]) {
+  lat_t L = make_lat(dims);
+  double* per_site = (double*)malloc(sizeof(double) * (size_t)L.V);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < L.V; ++s) {
+    double acc = 0.0;
+    for (int sg = 0; sg < 3; ++sg) {
+      double M[4][4];
+      mag_matrix(U, &L, s, sg, M);
+      acc += M[0][1] * M[0][1] + M[0][2] * M[0][2];
+    }
+    per_site[s] = acc;
+  }
+  double sum = 0.0;
+  for (int64_t s = 0; s < L.V; ++s) sum += per_site[s];
+  free(per_site);
+  return sum / (3.0 * (double)L.V);
+}
+
+/* the while-theta loop of Alg. 1 for the MAG, checks as in or_fix */
+int or_fix_mag(double* U, const int32_t dims[4], double omega, int form, double theta_target,
+               int32_t max_sweeps, int32_t check_every, int32_t reunit_at_check,
+               int32_t* sweeps_out, double* F_out, double* theta_out) {
+  if (!U || or_check_dims(dims) != 0 || check_every < 1 || max_sweeps < 0) return -1;
+  if (!(omega >= 1.0 && omega < 2.0) || form < 0 || form > 3) return -1;
+  int64_t V = or_volume(dims);
+  int32_t sweeps = 0;
+  int converged = 0;
+  double F = 0.0, th = 0.0;
+  for (;;) {
+    if (sweeps > 0 && reunit_at_check) or_reunitarize(U, V * 4);
+    F = or_mag_functional(U, dims);
+    th = or_mag_theta(U, dims);
+    if (th < theta_target) { converged = 1; break; }
+    if (sweeps >= max_sweeps) break;
+    for (int32_t k = 0; k < check_every && sweeps < max_sweeps; ++k) {
+      or_mag_sweep(U, dims, 0, omega, form);
+      or_mag_sweep(U, dims, 1, omega, form);
+      ++sweeps;
+    }
+  }
+  if (sweeps_out) *sweeps_out = sweeps;
+  if (F_out) *F_out = F;
+  if (theta_out) *theta_out = th;
+  return converged ? 0 : 1;
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
