@@ -28,7 +28,14 @@
  *   gf_field_bytes() = 8 Vp storage prec bytes.
  * Gauge: GF_LANDAU uses mu = 0..3 in K(x), F and theta (eq. (3), (5), (7));
  *   GF_COULOMB uses the spatial mu = 1..3 and reports F and theta per
- *   timeslice (arrays of nt doubles). In both gauges each site
+ *   timeslice (arrays of nt doubles). GF_MAG, the maximally Abelian gauge
+ *   (named in Sec. 1; the paper does not write out its functional), maximises
+ *   R = sum_{x,mu} sum_k |U_mu(x)_kk|^2: in each SU(2) subgroup the site's R is
+ *   a quadratic form a^T M a in the quaternion a of the local transformation,
+ *   maximised by the top eigenvector of M restricted to a3 = 0 (the subgroup's
+ *   diagonal phases are a symmetry); F = R / (12 V) (1 iff all links are
+ *   diagonal), theta = sum_x sum_subgroups (M01^2 + M02^2) / (3 V) (the squared
+ *   gradient along the off-diagonal generators). In all gauges each site
  *   transformation is applied to all 8 links at the site, so the result is a
  *   gauge transform of the input.
  *
@@ -65,6 +72,7 @@ typedef int32_t gf_status;
 
 #define GF_LANDAU 0
 #define GF_COULOMB 1
+#define GF_MAG 2   /* overrelaxation sweeps, measurement and the drivers only */
 #define GF_FP32 4
 #define GF_FP64 8
 #define GF_R12 12

@@ -114,6 +114,19 @@ def abelian_gauge(dims, seed, eps=0.5):
     return haar_copy(U, seed, 0)
 
 
+def abelian_noise(dims, seed, eps):
+    """diag(e^{i t1}, e^{i t2}, e^{-i(t1+t2)}) exp(i eps H) per link: random
+    diagonal phases (t uniform in [-pi, pi], numpy Philox stream `seed`) times
+    the links of smooth_links(dims, eps, seed); close to the maximally Abelian
+    gauge without being in it."""
+    rng = np.random.Generator(np.random.Philox(int(seed)))
+    t = rng.uniform(-np.pi, np.pi, size=tuple(dims) + (4, 2))
+    V = smooth_links(dims, eps, seed)
+    d = np.stack([np.exp(1j * t[..., 0]), np.exp(1j * t[..., 1]),
+                  np.exp(-1j * (t[..., 0] + t[..., 1]))], axis=-1)
+    return np.ascontiguousarray(d[..., :, None] * V)
+
+
 def haar_copy(U, seed, copy):
     """In place: U_mu(x) <- h(x) U_mu(x) h(x+mu)^dag with Haar h from (seed, copy)."""
     assert U.dtype == np.complex128 and U.flags["C_CONTIGUOUS"]

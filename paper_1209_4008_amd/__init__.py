@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libgf.so")
 
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_UNSUPPORTED, ERR_DEVICE, ERR_HIP, ERR_NONFINITE, ERR_NOMEM = -1, -2, -3, -4, -5, -6
-LANDAU, COULOMB = 0, 1
+LANDAU, COULOMB, MAG = 0, 1, 2
 FP32, FP64 = 4, 8
 R12, R18 = 12, 18
 FLAG_TIMING, FLAG_GRAPH, FLAG_NO_TRACK = 1, 2, 4

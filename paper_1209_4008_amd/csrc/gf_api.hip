@@ -384,9 +384,52 @@ static void launch_update_v(gf_ctx* c, int tps, void* U, const Lat& L, int parit
   }
 }
 
+// the MAG site update takes the overrelaxation policies only
+template <class Upd>
+struct MagCapable {
+  static constexpr bool value = false;
+};
+template <typename T>
+struct MagCapable<UpdOR<T>> {
+  static constexpr bool value = true;
+};
+template <typename T>
+struct MagCapable<UpdORForm<T>> {
+  static constexpr bool value = true;
+};
+
+template <typename T, int NC, class Upd, bool NT, bool TRACK>
+static void launch_mag_v(gf_ctx* c, int tps, void* U, void* Gx, const Lat& L, int parity,
+                         const Upd& upd) {
+  const dim3 grid(blocks_for((uint64_t)L.vh * (uint64_t)tps));
+  switch (tps) {
+    case 1:
+      hipLaunchKernelGGL((k_mag_half<T, NC, Upd, 1, NT, TRACK>), grid, dim3(kBlock), 0, c->stream,
+                         (v2<T>*)U, L, parity, upd, (v2<T>*)Gx);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_mag_half<T, NC, Upd, 2, NT, TRACK>), grid, dim3(kBlock), 0, c->stream,
+                         (v2<T>*)U, L, parity, upd, (v2<T>*)Gx);
+      break;
+    default:
+      hipLaunchKernelGGL((k_mag_half<T, NC, Upd, 4, NT, TRACK>), grid, dim3(kBlock), 0, c->stream,
+                         (v2<T>*)U, L, parity, upd, (v2<T>*)Gx);
+      break;
+  }
+}
+
 template <typename T, int NC, int GAUGE, class Upd>
 static void launch_update_tps(gf_ctx* c, int tps, int nt, void* U, const Lat& L, int parity,
                               const Upd& upd) {
+  if constexpr (GAUGE == kMAG) {
+    if constexpr (MagCapable<Upd>::value) {
+      if (nt)
+        launch_mag_v<T, NC, Upd, true, false>(c, tps, U, nullptr, L, parity, upd);
+      else
+        launch_mag_v<T, NC, Upd, false, false>(c, tps, U, nullptr, L, parity, upd);
+    }
+    return;
+  }
   if (nt)
     launch_update_v<T, NC, GAUGE, Upd, true>(c, tps, U, L, parity, upd);
   else
@@ -432,16 +475,22 @@ static gf_status launch_update(gf_ctx* c, void* U, const gf_geom* g, int32_t gau
     auto upd = make_upd.template operator()<T>();
     if (gauge == GF_LANDAU)
       launch_update_tps<T, NC, kLandau>(c, tps, nt, U, L, (int)parity, upd);
-    else
+    else if (gauge == GF_COULOMB)
       launch_update_tps<T, NC, kCoulomb>(c, tps, nt, U, L, (int)parity, upd);
+    else
+      launch_update_tps<T, NC, kMAG>(c, tps, nt, U, L, (int)parity, upd);
   });
   return launch_check(c, what);
 }
 
 #define CHECK_GAUGE_PARITY(c, gauge, parity, what)                                    \
-  if ((gauge) != GF_LANDAU && (gauge) != GF_COULOMB)                                  \
-    return fail((c), GF_ERR_ARG, "%s: gauge must be GF_LANDAU or GF_COULOMB", what); \
+  if ((gauge) != GF_LANDAU && (gauge) != GF_COULOMB && (gauge) != GF_MAG)             \
+    return fail((c), GF_ERR_ARG, "%s: gauge must be GF_LANDAU, GF_COULOMB or GF_MAG", what); \
   if ((parity) != 0 && (parity) != 1) return fail((c), GF_ERR_ARG, "%s: parity must be 0 or 1", what)
+// the annealing and stochastic-relaxation updates are defined for the linear
+// functionals of Landau and Coulomb gauge only
+#define REJECT_MAG(c, gauge, what) \
+  if ((gauge) == GF_MAG) return fail((c), GF_ERR_UNSUPPORTED, "%s: not available for GF_MAG", what)
 
 gf_status gf_sweep(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32_t parity,
                    double omega) {
@@ -486,6 +535,7 @@ gf_status gf_sweep_sr(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_sweep_sr");
   CHECK_GAUGE_PARITY(c, gauge, parity, "gf_sweep_sr");
+  REJECT_MAG(c, gauge, "gf_sweep_sr");
   if (!U) return fail(c, GF_ERR_ARG, "gf_sweep_sr: NULL field");
   if (!(omega >= 1.0 && omega < 2.0)) return fail(c, GF_ERR_ARG, "gf_sweep_sr: omega must be in [1, 2)");
   if (!(prob >= 0.0 && prob <= 1.0)) return fail(c, GF_ERR_ARG, "gf_sweep_sr: prob must be in [0, 1]");
@@ -513,6 +563,11 @@ static gf_status update_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, 
     if (gauge == GF_LANDAU) {
       if (nt) launch_tracked_v<NC, kLandau, true>(c, tps, U, Gx, L, parity, upd);
       else launch_tracked_v<NC, kLandau, false>(c, tps, U, Gx, L, parity, upd);
+    } else if (gauge == GF_MAG) {
+      if constexpr (MagCapable<Upd>::value) {
+        if (nt) launch_mag_v<float, NC, Upd, true, true>(c, tps, U, Gx, L, parity, upd);
+        else launch_mag_v<float, NC, Upd, false, true>(c, tps, U, Gx, L, parity, upd);
+      }
     } else {
       if (nt) launch_tracked_v<NC, kCoulomb, true>(c, tps, U, Gx, L, parity, upd);
       else launch_tracked_v<NC, kCoulomb, false>(c, tps, U, Gx, L, parity, upd);
@@ -574,6 +629,7 @@ gf_status gf_micro_half(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_micro_half");
   CHECK_GAUGE_PARITY(c, gauge, parity, "gf_micro_half");
+  REJECT_MAG(c, gauge, "gf_micro_half");
   if (!U) return fail(c, GF_ERR_ARG, "gf_micro_half: NULL field");
   return launch_update(
       c, U, g, gauge, parity, [&]<typename T>() { return UpdMicro<T>(); }, "gf_micro_half");
@@ -584,6 +640,7 @@ gf_status gf_heatbath_half(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, 
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_heatbath_half");
   CHECK_GAUGE_PARITY(c, gauge, parity, "gf_heatbath_half");
+  REJECT_MAG(c, gauge, "gf_heatbath_half");
   if (!U) return fail(c, GF_ERR_ARG, "gf_heatbath_half: NULL field");
   if (!(T > 0.0) || !std::isfinite(T)) return fail(c, GF_ERR_ARG, "gf_heatbath_half: T must be > 0");
   return launch_update(
@@ -603,6 +660,7 @@ gf_status gf_anneal_sweep(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, d
                           uint64_t seed, uint64_t sweep, int32_t n_micro) {
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_anneal_sweep");
+  REJECT_MAG(c, gauge, "gf_anneal_sweep");
   if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_anneal_sweep: bad gauge");
   if (!U) return fail(c, GF_ERR_ARG, "gf_anneal_sweep: NULL field");
   if (!(T > 0.0) || !std::isfinite(T)) return fail(c, GF_ERR_ARG, "gf_anneal_sweep: T must be > 0");
@@ -627,12 +685,15 @@ static gf_status measure_impl(gf_ctx* c, const void* U, const gf_geom* g, int32_
     if (gauge == GF_LANDAU)
       hipLaunchKernelGGL((k_measure<T, NC, kLandau>), grid, dim3(kBlock), 0, c->stream,
                          (const v2<T>*)U, L, c->partial);
-    else
+    else if (gauge == GF_COULOMB)
       hipLaunchKernelGGL((k_measure<T, NC, kCoulomb>), grid, dim3(kBlock), 0, c->stream,
+                         (const v2<T>*)U, L, c->partial);
+    else
+      hipLaunchKernelGGL((k_measure_mag<T, NC>), grid, dim3(kBlock), 0, c->stream,
                          (const v2<T>*)U, L, c->partial);
   });
   const double V = 2.0 * L.vh, Vs = V / L.nt;
-  if (gauge == GF_LANDAU)
+  if (gauge != GF_COULOMB)
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial,
                        bpt * L.nt, 12.0 * V, 3.0 * V, F, th);
   else
@@ -645,7 +706,8 @@ gf_status gf_measure(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, 
                      double* th) {
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_measure");
-  if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_measure: bad gauge");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB && gauge != GF_MAG)
+    return fail(c, GF_ERR_ARG, "gf_measure: bad gauge");
   if (!U || (!F && !th)) return fail(c, GF_ERR_ARG, "gf_measure: NULL pointer");
   return measure_impl(c, U, g, gauge, F, th);
 }
@@ -1038,7 +1100,11 @@ gf_status gf_fix(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const gf_f
                  gf_fix_result* r) {
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_fix");
-  if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_fix: bad gauge");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB && gauge != GF_MAG)
+    return fail(c, GF_ERR_ARG, "gf_fix: bad gauge");
+  if (gauge == GF_MAG && p && (p->sa_steps > 0 || p->sr_prob > 0.0))
+    return fail(c, GF_ERR_UNSUPPORTED, "gf_fix: annealing and stochastic relaxation are not "
+                                       "available for GF_MAG");
   if (!U || !r) return fail(c, GF_ERR_ARG, "gf_fix: NULL pointer");
   gf_status st = check_params(c, p);
   if (st != GF_OK) return st;
@@ -1071,7 +1137,11 @@ gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
   if (g_lo->prec != GF_FP32 || g_hi->prec != GF_FP64)
     return fail(c, GF_ERR_ARG, "gf_fix_mixed: needs an FP32 and an FP64 field");
   if (!same_extents(g_lo, g_hi)) return fail(c, GF_ERR_ARG, "gf_fix_mixed: extents differ");
-  if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_fix_mixed: bad gauge");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB && gauge != GF_MAG)
+    return fail(c, GF_ERR_ARG, "gf_fix_mixed: bad gauge");
+  if (gauge == GF_MAG && p && (p->sa_steps > 0 || p->sr_prob > 0.0))
+    return fail(c, GF_ERR_UNSUPPORTED, "gf_fix_mixed: annealing and stochastic relaxation are "
+                                       "not available for GF_MAG");
   if (!U_lo || !U_hi || !r) return fail(c, GF_ERR_ARG, "gf_fix_mixed: NULL pointer");
   {
     const char *a = (const char*)U_lo, *b = (const char*)U_hi;

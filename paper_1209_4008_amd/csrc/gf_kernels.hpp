@@ -23,6 +23,7 @@ namespace gf {
 constexpr int kBlock = 256;
 constexpr int kLandau = 0;
 constexpr int kCoulomb = 1;
+constexpr int kMAG = 2;  // maximally Abelian gauge (its own site update, k_mag_half)
 
 template <int GAUGE>
 struct FirstDir {
@@ -462,6 +463,233 @@ __global__ __launch_bounds__(kBlock, (SweepWaves<T, TPS>::value)) void k_update_
 }
 
 // ---------------------------------------------------------------------------
+// maximally Abelian gauge: maximise R = sum_{x,mu} sum_k |U_mu(x)_kk|^2 (the
+// gauge named in Sec. 1; functional from the literature). Under G = embed(a)
+// on the subgroup (i, j) the diagonal entries of the site's links that change
+// are linear in the quaternion a = (a0, a1, a2, a3):
+//   (G U)_ii   = U_ii a0 + i U_ji a1 + U_ji a2 + i U_ii a3
+//   (G U)_jj   = U_jj a0 + i U_ij a1 - U_ij a2 - i U_jj a3
+//   (W G^+)_ii = W_ii a0 - i W_ij a1 + W_ij a2 - i W_ii a3
+//   (W G^+)_jj = W_jj a0 - i W_ji a1 - W_ji a2 + i W_jj a3
+// (U forward, W backward links), so the site's R is a^T M a + const with
+// M_kl = sum Re(c_k conj(c_l)) over these coefficient vectors c. The diagonal
+// phases of the subgroup (rotating (a0, a3) and (a1, a2) together) leave R
+// unchanged, so the maximiser is taken with a3 = 0: the top eigenvector of
+// the 3x3 block of M on (a0, a1, a2), with a0 >= 0.
+// ---------------------------------------------------------------------------
+// M block entries m = (M00, M01, M02, M11, M12, M22) += Re(c_k conj(c_l))
+template <typename T>
+__device__ __forceinline__ void mag_acc(T m[6], const Cx<T>& c0, const Cx<T>& c1,
+                                        const Cx<T>& c2) {
+  m[0] = fma(c0.re, c0.re, fma(c0.im, c0.im, m[0]));
+  m[1] = fma(c0.re, c1.re, fma(c0.im, c1.im, m[1]));
+  m[2] = fma(c0.re, c2.re, fma(c0.im, c2.im, m[2]));
+  m[3] = fma(c1.re, c1.re, fma(c1.im, c1.im, m[3]));
+  m[4] = fma(c1.re, c2.re, fma(c1.im, c2.im, m[4]));
+  m[5] = fma(c2.re, c2.re, fma(c2.im, c2.im, m[5]));
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> times_i(const Cx<T>& z) { return cx<T>(-z.im, z.re); }
+template <typename T>
+__device__ __forceinline__ Cx<T> times_mi(const Cx<T>& z) { return cx<T>(z.im, -z.re); }
+template <typename T>
+__device__ __forceinline__ Cx<T> neg(const Cx<T>& z) { return cx<T>(-z.re, -z.im); }
+
+template <typename T>
+__device__ __forceinline__ void mag_forward(T m[6], const Su3<T>& U, int i, int j) {
+  mag_acc(m, U.e[i][i], times_i(U.e[j][i]), U.e[j][i]);
+  mag_acc(m, U.e[j][j], times_i(U.e[i][j]), neg(U.e[i][j]));
+}
+template <typename T>
+__device__ __forceinline__ void mag_backward(T m[6], const Su3<T>& W, int i, int j) {
+  mag_acc(m, W.e[i][i], times_mi(W.e[i][j]), W.e[i][j]);
+  mag_acc(m, W.e[j][j], times_mi(W.e[j][i]), neg(W.e[j][i]));
+}
+
+template <typename T>
+struct JacobiTol;
+template <>
+struct JacobiTol<float> {
+  static constexpr float value = 1e-14f;  // off-diagonal^2 relative to diagonal^2
+};
+template <>
+struct JacobiTol<double> {
+  static constexpr double value = 1e-34;
+};
+
+// top eigenvector of the symmetric 3x3 m = (M00, M01, M02, M11, M12, M22) by
+// cyclic Jacobi rotations (Golub & Van Loan, Sec. 8.5), at most 6 sweeps,
+// stopping when the off-diagonal part is at rounding level; unit length,
+// a0 >= 0 (then a1, a2 >= 0). Returns false if m vanishes.
+template <typename T>
+__device__ __forceinline__ bool mag_top_eigvec(const T m[6], T v[3]) {
+  T A[3][3] = {{m[0], m[1], m[2]}, {m[1], m[3], m[4]}, {m[2], m[4], m[5]}};
+  T Q[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  const T nrm = fabs(m[0]) + fabs(m[3]) + fabs(m[5]) + 2 * (fabs(m[1]) + fabs(m[2]) + fabs(m[4]));
+  if (!(nrm > Tiny<T>::value)) return false;
+  for (int sw = 0; sw < 6; ++sw) {
+    const T off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const T dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= JacobiTol<T>::value * dia) break;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = p + 1; q < 3; ++q) {
+        if (A[p][q] == T(0)) continue;
+        const T theta = (A[q][q] - A[p][p]) / (T(2) * A[p][q]);
+        const T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
+        const T c = T(1) / sqrt(t * t + T(1)), sn = t * c;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T qkp = Q[k][p], qkq = Q[k][q];
+          Q[k][p] = c * qkp - sn * qkq;
+          Q[k][q] = sn * qkp + c * qkq;
+        }
+      }
+  }
+  int best = 0;
+  T lb = A[0][0];
+  if (A[1][1] > lb) {
+    best = 1;
+    lb = A[1][1];
+  }
+  if (A[2][2] > lb) best = 2;
+  T x = Q[0][0], y = Q[1][0], z = Q[2][0];
+  if (best == 1) {
+    x = Q[0][1];
+    y = Q[1][1];
+    z = Q[2][1];
+  } else if (best == 2) {
+    x = Q[0][2];
+    y = Q[1][2];
+    z = Q[2][2];
+  }
+  const bool flip = x < T(0) || (x == T(0) && (y < T(0) || (y == T(0) && z < T(0))));
+  const T r = (flip ? T(-1) : T(1)) / sqrt(x * x + y * y + z * z);
+  v[0] = x * r;
+  v[1] = y * r;
+  v[2] = z * r;
+  return true;
+}
+
+// MAG half-sweep (Alg. 1 with the MAG local step), TPS lanes per site as in
+// site_half_update: for each subgroup in turn the lanes add their parts of M,
+// every lane finds the same maximiser and its power (Upd: g^omega from the
+// unit quaternion), and each lane transforms its own links in registers,
+// since M of the next subgroup depends on the updated links quadratically.
+template <typename T, int NC, class Upd, int TPS, bool NT, bool TRACK>
+__device__ __forceinline__ void site_mag_update(v2<T>* __restrict__ U, const Lat& L,
+                                                const int parity, const Upd& upd,
+                                                v2<T>* __restrict__ Gx, const uint32_t gid) {
+  static_assert(TPS == 1 || TPS == 2 || TPS == 4, "lanes per site");
+  constexpr int DPL = 4 / TPS;
+  const uint32_t h = gid / TPS;
+  const int r = (int)(gid % TPS);
+  if (h >= L.vh) return;  // a site's lanes are all in range or all out
+  const Site S = site_of(L, h, parity);
+  uint32_t hb[DPL];
+  Su3<T> Uf[DPL], Ub[DPL];
+#pragma unroll
+  for (int d = 0; d < DPL; ++d) {
+    const int mu = r * DPL + d;
+    hb[d] = back_h(L, h, S, mu);
+    load_link<T, NC, NT>(U + link_offset<NC>(L.vp, parity, mu, h), Uf[d]);
+    load_link<T, NC, NT>(U + link_offset<NC>(L.vp, 1 - parity, mu, hb[d]), Ub[d]);
+  }
+  Su3<T> Gt;
+  if (TRACK) set_unit(Gt);
+  const uint32_t site = 2 * h + S.xodd;
+#pragma unroll
+  for (int sg = 0; sg < 3; ++sg) {
+    const int i = sg == 2 ? 1 : 0, j = sg == 0 ? 1 : 2;
+    T m[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DPL; ++d) {
+      mag_forward(m, Uf[d], i, j);
+      mag_backward(m, Ub[d], i, j);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      if (TPS >= 2) m[k] += quad_xor<1>(m[k]);
+      if (TPS >= 4) m[k] += quad_xor<2>(m[k]);
+    }
+    T v[3];
+    if (!mag_top_eigvec(m, v)) continue;
+    const T w[4] = {v[0], v[1], v[2], T(0)};
+    T q[4];
+    if (!upd(w, site, sg, q)) continue;
+    // SU(2) block [[q0 + i q3, q2 + i q1], [-q2 + i q1, q0 - i q3]] on (i, j)
+    const Cx<T> g00 = cx<T>(q[0], q[3]), g01 = cx<T>(q[2], q[1]);
+    const Cx<T> g10 = cx<T>(-q[2], q[1]), g11 = cx<T>(q[0], -q[3]);
+#pragma unroll
+    for (int d = 0; d < DPL; ++d) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {  // rows i, j of G U
+        const Cx<T> ui = Uf[d].e[i][b], uj = Uf[d].e[j][b];
+        Uf[d].e[i][b] = cmac(cmul(g00, ui), g01, uj);
+        Uf[d].e[j][b] = cmac(cmul(g10, ui), g11, uj);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {  // columns i, j of W G^+
+        const Cx<T> wi = Ub[d].e[a][i], wj = Ub[d].e[a][j];
+        Ub[d].e[a][i] = cmac_cb(cmac_cb(cx<T>(0, 0), wi, g00), wj, g01);
+        Ub[d].e[a][j] = cmac_cb(cmac_cb(cx<T>(0, 0), wi, g10), wj, g11);
+      }
+    }
+    if (TRACK) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const Cx<T> gi = Gt.e[i][b], gj = Gt.e[j][b];
+        Gt.e[i][b] = cmac(cmul(g00, gi), g01, gj);
+        Gt.e[j][b] = cmac(cmul(g10, gi), g11, gj);
+      }
+    }
+  }
+  if (TRACK && r == 0) {
+    v2<T>* gp = Gx + link_offset<6, 1>(L.vp, parity, 0, h);
+    Su3<T> gx, A;
+    load_link<T, 6, NT>(gp, gx);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        Cx<T> f = cmul(Gt.e[a][0], gx.e[0][b]);
+        f = cmac(f, Gt.e[a][1], gx.e[1][b]);
+        A.e[a][b] = cmac(f, Gt.e[a][2], gx.e[2][b]);
+      }
+    orthonormalize_rows01(A);
+    store_link<T, 6, NT>(gp, A);
+  }
+#pragma unroll
+  for (int d = 0; d < DPL; ++d) {
+    const int mu = r * DPL + d;
+    if (NC == 6) orthonormalize_rows01(Uf[d]);
+    store_link<T, NC, NT>(U + link_offset<NC>(L.vp, parity, mu, h), Uf[d]);
+    store_link<T, NC, NT>(U + link_offset<NC>(L.vp, 1 - parity, mu, hb[d]), Ub[d]);
+  }
+}
+
+template <typename T, int NC, class Upd, int TPS, bool NT, bool TRACK = false>
+__global__ __launch_bounds__(kBlock) void k_mag_half(v2<T>* __restrict__ U, const Lat L,
+                                                     const int parity, const Upd upd,
+                                                     v2<T>* __restrict__ Gx = nullptr) {
+  site_mag_update<T, NC, Upd, TPS, NT, TRACK>(U, L, parity, upd, Gx,
+                                              blockIdx.x * kBlock + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
 // batches of independent lattices (Gribov copies, uneven extents): one launch
 // covers every active lattice; lattice l owns the blocks
 // [first_block[l], first_block[l+1]).
@@ -601,6 +829,51 @@ __global__ __launch_bounds__(kBlock) void k_measure(const v2<T>* __restrict__ U,
           acc += 0.25 * (z.re * z.re + z.im * z.im);
         }
       th += acc;
+    }
+  }
+  f = block_sum(f, lds);
+  th = block_sum(th, lds);
+  if (threadIdx.x == 0) {
+    const size_t o = ((size_t)t * gridDim.x + blockIdx.x) * 2;
+    partial[o] = f;
+    partial[o + 1] = th;
+  }
+}
+
+// MAG measurement, same grid and partials as k_measure: F part = sum over
+// the forward links of sum_k |U_kk|^2, theta part = sum over the subgroups of
+// M01^2 + M02^2 (the derivatives of R along the off-diagonal generators are
+// 2 M01, 2 M02 at the identity), with M from the 8 links of the site.
+template <typename T, int NC>
+__global__ __launch_bounds__(kBlock) void k_measure_mag(const v2<T>* __restrict__ U, const Lat L,
+                                                        double* __restrict__ partial) {
+  __shared__ double lds[kBlock / 64];
+  const uint32_t t = blockIdx.y;
+  const uint32_t ht = blockIdx.x * kBlock + threadIdx.x;
+  double f = 0, th = 0;
+  if (ht < L.st) {
+    const uint32_t h = t * L.st + ht;
+#pragma unroll 1
+    for (int p = 0; p < 2; ++p) {
+      const Site S = site_of(L, h, p);
+      double m[3][6] = {};
+#pragma unroll 1
+      for (int mu = 0; mu < 4; ++mu) {
+        Su3<double> A, B;
+        load_link_f64<T, NC>(U + link_offset<NC>(L.vp, p, mu, h), A);
+        load_link_f64<T, NC>(U + link_offset<NC>(L.vp, 1 - p, mu, back_h(L, h, S, mu)), B);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          f += A.e[k][k].re * A.e[k][k].re + A.e[k][k].im * A.e[k][k].im;
+#pragma unroll
+        for (int sg = 0; sg < 3; ++sg) {
+          const int i = sg == 2 ? 1 : 0, j = sg == 0 ? 1 : 2;
+          mag_forward(m[sg], A, i, j);
+          mag_backward(m[sg], B, i, j);
+        }
+      }
+#pragma unroll
+      for (int sg = 0; sg < 3; ++sg) th += m[sg][1] * m[sg][1] + m[sg][2] * m[sg][2];
     }
   }
   f = block_sum(f, lds);
