@@ -56,13 +56,13 @@ def parse():
                     help="launch the sweeps between checks one by one instead of replaying a "
                          "captured hipGraph")
     ap.add_argument("--workload", default="landau32",
-                    choices=("landau32", "mixed48", "coulomb", "batch", "scan"),
+                    choices=("landau32", "mixed48", "coulomb", "batch", "scan", "mag"),
                     help="landau32 (default, the benchmark line): 32^4 beta 6.0 mixed fix; "
                          "mixed48: 48^4 beta 6.2 mixed vs FP64; coulomb: 32^3x64 beta 6.0 with "
                          "3000 annealing steps then the mixed Coulomb fix; batch: 64 Haar copies "
                          "each of 16^4, 24^4, 12^3x24 with 2000 annealing steps then the mixed fix; "
                          "scan: 32^4 sweeps and time against the precision switch, omega and the "
-                         "stochastic-relaxation probability")
+                         "stochastic-relaxation probability; mag: 32^4 maximally Abelian gauge")
     ap.add_argument("--probe", action="store_true",
                     help="kernel probe for profilers: bandwidth probes of known size, then "
                          "20 sweeps of each storage variant on a generated input")
@@ -260,6 +260,71 @@ def batch_main(args):
     print(json.dumps(out), flush=True)
 
 
+def mag_main(args):
+    """Maximally Abelian gauge on the 32^4 beta = 6.0 configuration: the mixed
+    driver (FP32 12-real with g tracked to theta_MAG < 1e-8, FP64 12-real to
+    theta_MAG < 1e-12) against pure FP64, with the per-half-sweep time of the
+    MAG kernels and their algorithmic bandwidth."""
+    import torch
+
+    import inputs
+    import paper_1209_4008_amd as gf
+
+    dims = (32, 32, 32, 32)
+    V = 32 ** 4
+    ctx = gf.Context(0)
+    canon = inputs.gpu_heatbath(dims, 6.0, 300, 2, progress=100)
+    glo = gf.Geom.make(dims, gf.FP32, gf.R12)
+    ghi = gf.Geom.make(dims, gf.FP64, gf.R12)
+    U_lo, U_hi = ctx.empty_field(glo), ctx.empty_field(ghi)
+    tuning = {}
+    for g, f in ((glo, U_lo), (ghi, U_hi)):
+        ctx.pack(g, canon, f)
+        best, ms = ctx.autotune(g, gf.MAG, U_like=f)
+        tuning["fp32" if g.prec == gf.FP32 else "fp64"] = {
+            "lanes_per_site": best[0], "nontemporal": best[1],
+            "us_per_half_sweep": {f"tps{k[0]}_nt{k[1]}": round(v * 1e3, 2) for k, v in ms.items()}}
+    log("mag autotune", tuning)
+    flags = gf.FLAG_TIMING | gf.FLAG_GRAPH
+    p = gf.fix_params(omega=1.7, theta_target=1e-12, theta_switch=1e-8, max_sweeps=20000,
+                      check_every=100, flags=flags)
+    ctx.pack(ghi, canon, U_hi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.fix_mixed(U_lo, glo, U_hi, ghi, gf.MAG, p)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    ctx.pack(ghi, canon, U_hi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r64 = ctx.fix(U_hi, ghi, gf.MAG, p)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+
+    def rate(ms, n, bytes_per_site):
+        us = 1e3 * ms / max(n, 1)
+        return {"us_per_half_sweep": round(us, 2),
+                "GBps": round((V // 2) * bytes_per_site / (us * 1e-6) / 1e9, 1)}
+
+    out = {"metric": "maximally Abelian gauge: time to theta_MAG < 1e-12, MAG sweep rates",
+           "workload": "mag 32x32x32x32 wilson-heatbath beta=6 (300 sweeps, seed 2), omega 1.7, "
+                       "mixed fp32-r12 (g tracked, to 1e-8) -> fp64-r12",
+           "mixed": {"ms": round(1e3 * t_mixed, 1), "sweeps": r.sweeps, "sweeps_fp32": r.sweeps_lo,
+                     "status": r.status, "F": r.F, "theta": r.theta,
+                     "fp32_kernel": rate(r.kernel_ms[0], r.kernel_launches[0], 16 * 12 * 4 + 96),
+                     "fp64_kernel": rate(r.kernel_ms[1], r.kernel_launches[1], 16 * 12 * 8)},
+           "fp64_only": {"ms": round(1e3 * t64, 1), "sweeps": r64.sweeps, "status": r64.status,
+                         "F": r64.F, "theta": r64.theta,
+                         "fp64_kernel": rate(r64.kernel_ms[1], r64.kernel_launches[1],
+                                             16 * 12 * 8)},
+           "mixed_speedup_vs_fp64": round(t64 / t_mixed, 3),
+           "F_rel_diff": abs(r.F - r64.F) / abs(r64.F),
+           "site_updates_per_s_mixed": round(V * r.sweeps / t_mixed, 0),
+           "autotune": tuning}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def scan_main(args):
     """Tuning scans on 32^4 heatbath configurations (mixed FP32 -> FP64 driver,
     12-real storage, g tracked):
@@ -406,6 +471,9 @@ def main():
         return
     if args.workload == "scan":
         scan_main(args)
+        return
+    if args.workload == "mag":
+        mag_main(args)
         return
     if args.workload == "mixed48":
         args.dims, args.beta, args.seed, args.therm = "48,48,48,48", 6.2, 3, 400

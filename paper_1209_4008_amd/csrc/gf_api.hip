@@ -781,7 +781,8 @@ gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, const void* U_
                       int32_t* tps_out, int32_t* nt_out, float* ms_out) {
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_autotune");
-  if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(c, GF_ERR_ARG, "gf_autotune: bad gauge");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB && gauge != GF_MAG)
+    return fail(c, GF_ERR_ARG, "gf_autotune: bad gauge");
   const size_t bytes = gf_field_bytes(g);
   void* scratch = nullptr;
   HIP_OR_FAIL(c, hipMalloc(&scratch, bytes));
