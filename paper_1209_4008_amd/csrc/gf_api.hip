@@ -839,7 +839,7 @@ gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, const void* U_
   // so that repeated tunings settle on the same kernel
   {
     const int kd = 3 * default_nt(g) + (default_tps(g) == 4 ? 2 : default_tps(g) == 2 ? 1 : 0);
-    if (times[kd] <= 1.015f * best) {
+    if (times[kd] <= 1.03f * best) {
       best_tps = default_tps(g);
       best_nt = default_nt(g);
     }
