@@ -182,7 +182,10 @@ def coulomb_main(args):
                          "site_updates_per_s": round(V / 2 * sa_n / (sa_ms * 1e-3), 0)},
            "overrelaxation": {"sweeps": r.sweeps, "sweeps_fp32": r.sweeps_lo,
                               "ms": round(or_ms, 1),
-                              "site_updates_per_s": round(V * r.sweeps / (or_ms * 1e-3), 0)},
+                              "site_updates_per_s": round(V * r.sweeps / (or_ms * 1e-3), 0),
+                              # 3 x (44 + 19 + 8 x 84) flop per site update with the
+                              # spatial K (the paper's Landau count is 2253)
+                              "gflops_2205": round(2205 * V * r.sweeps / (or_ms * 1e-3) / 1e9, 1)},
            "theta_t_max": float(th.max().item()), "theta_t_median": float(th.median().item()),
            "timeslices_below_1e-14": int((th < 1e-14).sum().item()),
            "F_t_mean": float(F.mean().item()),
@@ -589,6 +592,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(canon, dims, args)
+        if not args.no_extras:
+            extras.update(cpu_extras(canon, dims, args, ctx, torch, gf))
 
     out = {
         "metric": "Landau OR site-updates/s, HBM GB/s %peak; mixed vs FP64 time-to-theta<1e-14",
@@ -644,6 +649,58 @@ def cpu_baseline(canon, dims, args):
             "kind": "oracle",
             "sample": f"{n} FP64 overrelaxation sweeps (omega {args.omega}) of the "
                       f"{'x'.join(map(str, dims))} input, canonical 18-real layout"}
+
+
+def cpu_extras(canon, dims, args, ctx, torch, gf):
+    """The oracle on one host thread (2 sweeps of the same input), and the
+    8^4 configuration 0 fixed to theta < 1e-12 in FP64 by the oracle (all host
+    threads) and by the GPU (12 reals, same cadence)."""
+    import numpy as np
+
+    import inputs
+    import oracle
+
+    out = {}
+    U = canon.cpu().numpy().view(np.complex128).reshape(tuple(dims) + (4, 3, 3)).copy()
+    V = int(np.prod(dims))
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        for _ in range(2):
+            oracle.sweep(U, oracle.LANDAU, 0, args.omega)
+            oracle.sweep(U, oracle.LANDAU, 1, args.omega)
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    out["cpu_oracle_1_thread"] = {"site_updates_per_s": round(2 * V / dt, 1),
+                                  "sample": "2 FP64 sweeps of the benchmark input"}
+    d0 = (8, 8, 8, 8)
+    U0 = inputs.config0(d0, 0.3, 1)
+    ref = U0.copy()
+    ref[..., 2, :] = np.conj(np.cross(ref[..., 0, :], ref[..., 1, :]))  # the 12-real input
+    t0 = time.perf_counter()
+    ro = oracle.fix(ref, oracle.LANDAU, args.omega, 1e-12, 2000, 100, 1)
+    t_cpu = time.perf_counter() - t0
+    g0 = gf.Geom.make(d0, gf.FP64, gf.R12)
+    f0 = ctx.empty_field(g0)
+    c0 = torch.from_numpy(U0.view(np.float64).reshape(-1).copy()).to("cuda")
+    p0 = gf.fix_params(omega=args.omega, theta_target=1e-12, max_sweeps=2000, check_every=100,
+                       flags=gf.FLAG_GRAPH)
+    ctx.pack(g0, c0, f0)
+    ctx.fix(f0, g0, gf.LANDAU, p0)  # warm-up (graph capture, first launches)
+    ctx.pack(g0, c0, f0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r0 = ctx.fix(f0, g0, gf.LANDAU, p0)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    out["config0_8x8x8x8_time_to_theta_1e-12"] = {
+        "oracle_ms": round(1e3 * t_cpu, 1), "oracle_threads": threads, "oracle_sweeps": ro["sweeps"],
+        "gpu_ms": round(1e3 * t_gpu, 2), "gpu_sweeps": r0.sweeps,
+        "F_rel_diff": abs(r0.F - ro["F"]) / abs(ro["F"])}
+    log("cpu extras", out)
+    return out
 
 
 if __name__ == "__main__":
