@@ -254,3 +254,20 @@ def test_autotune_choice_and_parity_after(ctx, prec, storage):
         _half_sweep_check(ctx, U, prec, storage, gf.LANDAU)
     finally:
         ctx.set_sweep_variant(prec, storage, 0, -1)
+
+
+@pytest.mark.parametrize("prec,storage", COMBOS)
+def test_vanishing_subgroup_parts(ctx, prec, storage):
+    """Uniform cyclic permutation field: all subgroup parts of K vanish, every
+    subgroup is skipped, the field stays bit for bit, and the driver stops at
+    this stationary point (F = 0, theta = 0) without a sweep."""
+    dims = (4, 2, 4, 2)
+    P = np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]], dtype=np.complex128)
+    U = np.ascontiguousarray(np.broadcast_to(P, tuple(dims) + (4, 3, 3)))
+    f, g = upload(ctx, U, prec, storage)
+    for gauge in (gf.LANDAU, gf.COULOMB):
+        for p in (0, 1):
+            ctx.sweep(f, g, gauge, p, 1.7)
+        assert np.array_equal(download(ctx, f, g), U)
+    r = ctx.fix(f, g, gf.LANDAU, gf.fix_params(theta_target=1e-12, max_sweeps=100))
+    assert r.status == gf.OK and r.sweeps == 0 and r.F == 0.0 and r.theta == 0.0

@@ -458,3 +458,21 @@ def test_argument_errors():
         O.heatbath_half(U, L, 0, 0.0, 1, 0)
     with pytest.raises(ValueError):
         O.heatbath_half(U, L, 0, -1.0, 1, 0)
+
+
+def test_vanishing_subgroup_parts_are_skipped():
+    """Every link the cyclic permutation P (det 1): K is proportional to P + P^T,
+    whose three SU(2) parts vanish, so each subgroup is skipped and the field
+    is a stationary point with F = 0 and theta = 0 (not a maximum)."""
+    dims = (4, 2, 4, 2)
+    P = np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]], dtype=np.complex128)
+    U = np.ascontiguousarray(np.broadcast_to(P, tuple(dims) + (4, 3, 3)))
+    for gauge in (L, CLB):
+        W = U.copy()
+        for p in (0, 1):
+            O.sweep(W, gauge, p, 1.7)
+        assert np.array_equal(W, U)
+        assert O.functional(W, gauge)[0] == 0.0
+        assert O.theta_K(W, gauge)[0] == 0.0
+    r = O.fix(U.copy(), L, 1.7, 1e-12, 100)
+    assert r["converged"] and r["sweeps"] == 0 and r["F"] == 0.0
