@@ -469,6 +469,9 @@ static int ctx_nt(const gf_ctx* c, const gf_geom* g) {
 template <class UpdF>
 static gf_status launch_update(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge,
                                int32_t parity, UpdF make_upd, const char* what) {
+  using UpdD = decltype(make_upd.template operator()<double>());
+  if (gauge == GF_MAG && !MagCapable<UpdD>::value)
+    return fail(c, GF_ERR_UNSUPPORTED, "%s: not available for GF_MAG", what);
   const Lat L = make_lat(g);
   const int tps = ctx_tps(c, g), nt = ctx_nt(c, g);
   with_type(g, [&]<typename T, int NC>() {
@@ -557,6 +560,8 @@ gf_status gf_sweep_sr(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, int32
 template <class Upd>
 static gf_status update_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32_t gauge,
                                 int32_t parity, const Upd& upd, const char* what) {
+  if (gauge == GF_MAG && !MagCapable<Upd>::value)
+    return fail(c, GF_ERR_UNSUPPORTED, "%s: not available for GF_MAG", what);
   const Lat L = make_lat(g);
   const int tps = ctx_tps(c, g), nt = ctx_nt(c, g);
   auto go = [&]<int NC>() {
