@@ -40,6 +40,8 @@ def short_name(name):
     n = re.sub(r"UpdOR<\w+>", "UpdOR", n)
     n = re.sub(r"UpdHB<\w+>", "UpdHB", n)
     n = re.sub(r"UpdMicro<\w+>", "UpdMicro", n)
+    n = re.sub(r"UpdORForm<\w+>", "UpdORForm", n)
+    n = re.sub(r"UpdSR<\w+>", "UpdSR", n)
     return n.replace(" ", "")
 
 
