@@ -571,9 +571,8 @@ def main():
     avg_ms = kms[dom] / max(kn[dom], 1)
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
     tps, nt = ctx.get_sweep_variant(gf.FP32 if dom == 0 else gf.FP64, gf.R12)
-    kname = "k_update_half<%s,6,0,UpdOR,%d,%s,%s>" % (
-        "float" if dom == 0 else "double", tps, "true" if nt else "false",
-        "true" if dom == 0 else "false")
+    kname = "k_update_half<%s,6,0,UpdOR,%d,%d,%s>" % (
+        "float" if dom == 0 else "double", tps, nt, "true" if dom == 0 else "false")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": hbm_traffic(kname, dims),

@@ -188,19 +188,22 @@ gf_status gf_philox(gf_ctx* ctx, const uint32_t* ctr_dev, uint64_t seed, uint32_
 /* Variant of the sweep kernels for one (precision, storage) pair on this
  * context: tps = lanes per site (1, 2 or 4; with k lanes each lane owns the
  * forward and backward links of 4/k directions and the lanes add their parts
- * of K(x)), nontemporal = 1 to mark the link loads and stores as streaming.
+ * of K(x)), nontemporal = 0 for ordinary link accesses, 1 to mark the link
+ * loads and stores as streaming, 2 to stream the stores only (loads cached;
+ * pays when the cache holds part of the field between half-sweeps; the
+ * overrelaxation sweeps only, the other updates run 2 as 1).
  * tps = 0 / nontemporal = -1 restore the built-in defaults. */
 gf_status gf_set_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t tps,
                                int32_t nontemporal);
 gf_status gf_get_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t* tps,
                                int32_t* nontemporal);
 /* Autotuner: times the overrelaxation half-sweep for geom (its extents,
- * precision and storage) for the six variants (tps 1, 2, 4) x (nontemporal 0,
- * 1) on a scratch field (allocated and freed inside the call) that starts as
+ * precision and storage) for the nine variants (tps 1, 2, 4) x (nontemporal 0,
+ * 1, 2) on a scratch field (allocated and freed inside the call) that starts as
  * a copy of U_like (a device field of geom; NULL: the unit field), keeps the
  * fastest on this context and returns it (the built-in variant when it is
  * within 3% of the fastest, so that repeated tunings agree). The caller's fields are not
- * modified. ms_out (NULL or 6 floats, index 3*nontemporal + log2(tps))
+ * modified. ms_out (NULL or 9 floats, index 3*nontemporal + log2(tps))
  * receives the mean time per half-sweep of each. Synchronises the context
  * stream. */
 gf_status gf_autotune(gf_ctx* ctx, const gf_geom* geom, int32_t gauge, const void* U_like,

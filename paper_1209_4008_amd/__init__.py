@@ -254,14 +254,15 @@ class Context:
         return t.value, n.value
 
     def autotune(self, geom, gauge=LANDAU, U_like=None):
-        """Time the six sweep variants for geom on a copy of U_like (None: the
-        unit field); keep the fastest on this context.
+        """Time the nine sweep variants (lanes per site 1, 2, 4 x nontemporal
+        mode 0 none, 1 loads and stores, 2 stores only) for geom on a copy of
+        U_like (None: the unit field); keep the fastest on this context.
         Returns ((tps, nontemporal), {(tps, nontemporal): ms per half-sweep})."""
         t, n = C.c_int32(0), C.c_int32(0)
-        ms = (C.c_float * 6)()
+        ms = (C.c_float * 9)()
         self._check(lib().gf_autotune(self.h, C.byref(geom), int(gauge), _ptr(U_like),
                                       C.byref(t), C.byref(n), ms))
-        table = {(1 << (k % 3), k // 3): ms[k] for k in range(6)}
+        table = {(1 << (k % 3), k // 3): ms[k] for k in range(9)}
         return (t.value, n.value), table
 
     def stream_probe(self, src, dst, nbytes, kind):

@@ -362,9 +362,29 @@ gf_status gf_reunitarize(gf_ctx* c, void* U, const gf_geom* g) {
 // lanes per site and nontemporal accesses of the sweep kernels, per
 // (precision, storage); the autotuner overwrites these per context
 static int default_tps(const gf_geom* g) { return g->prec == GF_FP64 ? 4 : 2; }
+// variants timed by the autotuner: lanes per site 1, 2, 4 x nontemporal mode
+// kNTNone, kNTAll, kNTStores, index 3 * mode + log2(lanes)
+constexpr int kVariants = 9;
 static int default_nt(const gf_geom* g) { return g->prec == GF_FP64 ? 1 : 0; }
 
-template <typename T, int NC, int GAUGE, class Upd, bool NT>
+// the stores-only nontemporal mode is instantiated for the overrelaxation
+// sweep only (the kernel the autotuner times); the other updates run it as
+// kNTAll
+template <class Upd>
+struct HasStoreMode {
+  static constexpr bool value = false;
+};
+template <typename T>
+struct HasStoreMode<UpdOR<T>> {
+  static constexpr bool value = true;
+};
+template <class Upd>
+static int nt_mode(int nt) {
+  if (nt == kNTStores && !HasStoreMode<Upd>::value) return kNTAll;
+  return nt;
+}
+
+template <typename T, int NC, int GAUGE, class Upd, int NT>
 static void launch_update_v(gf_ctx* c, int tps, void* U, const Lat& L, int parity, const Upd& upd) {
   const uint64_t n = (uint64_t)L.vh * (uint64_t)tps;
   const dim3 grid(blocks_for(n));
@@ -398,7 +418,7 @@ struct MagCapable<UpdORForm<T>> {
   static constexpr bool value = true;
 };
 
-template <typename T, int NC, class Upd, bool NT, bool TRACK>
+template <typename T, int NC, class Upd, int NT, bool TRACK>
 static void launch_mag_v(gf_ctx* c, int tps, void* U, void* Gx, const Lat& L, int parity,
                          const Upd& upd) {
   const dim3 grid(blocks_for((uint64_t)L.vh * (uint64_t)tps));
@@ -423,21 +443,26 @@ static void launch_update_tps(gf_ctx* c, int tps, int nt, void* U, const Lat& L,
                               const Upd& upd) {
   if constexpr (GAUGE == kMAG) {
     if constexpr (MagCapable<Upd>::value) {
-      if (nt)
-        launch_mag_v<T, NC, Upd, true, false>(c, tps, U, nullptr, L, parity, upd);
+      if (nt != kNTNone)
+        launch_mag_v<T, NC, Upd, kNTAll, false>(c, tps, U, nullptr, L, parity, upd);
       else
-        launch_mag_v<T, NC, Upd, false, false>(c, tps, U, nullptr, L, parity, upd);
+        launch_mag_v<T, NC, Upd, kNTNone, false>(c, tps, U, nullptr, L, parity, upd);
     }
     return;
   }
-  if (nt)
-    launch_update_v<T, NC, GAUGE, Upd, true>(c, tps, U, L, parity, upd);
-  else
-    launch_update_v<T, NC, GAUGE, Upd, false>(c, tps, U, L, parity, upd);
+  const int mode = nt_mode<Upd>(nt);
+  if (mode == kNTAll) {
+    launch_update_v<T, NC, GAUGE, Upd, kNTAll>(c, tps, U, L, parity, upd);
+  } else if (mode == kNTStores) {
+    if constexpr (HasStoreMode<Upd>::value)
+      launch_update_v<T, NC, GAUGE, Upd, kNTStores>(c, tps, U, L, parity, upd);
+  } else {
+    launch_update_v<T, NC, GAUGE, Upd, kNTNone>(c, tps, U, L, parity, upd);
+  }
 }
 
 // FP32 half-sweep (any update) that also accumulates g(x) <- Gtot g(x) into Gx
-template <int NC, int GAUGE, bool NT, class Upd>
+template <int NC, int GAUGE, int NT, class Upd>
 static void launch_tracked_v(gf_ctx* c, int tps, void* U, void* Gx, const Lat& L, int parity,
                              const Upd& upd) {
   const dim3 grid(blocks_for((uint64_t)L.vh * (uint64_t)tps));
@@ -564,18 +589,27 @@ static gf_status update_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, 
     return fail(c, GF_ERR_UNSUPPORTED, "%s: not available for GF_MAG", what);
   const Lat L = make_lat(g);
   const int tps = ctx_tps(c, g), nt = ctx_nt(c, g);
+  const int mode = nt_mode<Upd>(nt);
+  auto go_gauge = [&]<int NC, int GAUGE>() {
+    if (mode == kNTAll) {
+      launch_tracked_v<NC, GAUGE, kNTAll>(c, tps, U, Gx, L, parity, upd);
+    } else if (mode == kNTStores) {
+      if constexpr (HasStoreMode<Upd>::value)
+        launch_tracked_v<NC, GAUGE, kNTStores>(c, tps, U, Gx, L, parity, upd);
+    } else {
+      launch_tracked_v<NC, GAUGE, kNTNone>(c, tps, U, Gx, L, parity, upd);
+    }
+  };
   auto go = [&]<int NC>() {
     if (gauge == GF_LANDAU) {
-      if (nt) launch_tracked_v<NC, kLandau, true>(c, tps, U, Gx, L, parity, upd);
-      else launch_tracked_v<NC, kLandau, false>(c, tps, U, Gx, L, parity, upd);
+      go_gauge.template operator()<NC, kLandau>();
     } else if (gauge == GF_MAG) {
       if constexpr (MagCapable<Upd>::value) {
-        if (nt) launch_mag_v<float, NC, Upd, true, true>(c, tps, U, Gx, L, parity, upd);
-        else launch_mag_v<float, NC, Upd, false, true>(c, tps, U, Gx, L, parity, upd);
+        if (nt != kNTNone) launch_mag_v<float, NC, Upd, kNTAll, true>(c, tps, U, Gx, L, parity, upd);
+        else launch_mag_v<float, NC, Upd, kNTNone, true>(c, tps, U, Gx, L, parity, upd);
       }
     } else {
-      if (nt) launch_tracked_v<NC, kCoulomb, true>(c, tps, U, Gx, L, parity, upd);
-      else launch_tracked_v<NC, kCoulomb, false>(c, tps, U, Gx, L, parity, upd);
+      go_gauge.template operator()<NC, kCoulomb>();
     }
   };
   if (g->storage == GF_R12)
@@ -766,7 +800,8 @@ gf_status gf_set_sweep_variant(gf_ctx* c, int32_t prec, int32_t storage, int32_t
   if (!c) return GF_ERR_ARG;
   if (!ps_ok(prec, storage)) return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: bad precision or storage");
   if (tps != 0 && !tps_ok(tps)) return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: tps must be 0, 1, 2 or 4");
-  if (nontemporal < -1 || nontemporal > 1) return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: nontemporal must be -1, 0 or 1");
+  if (nontemporal < -1 || nontemporal > 2)
+    return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: nontemporal must be -1, 0, 1 or 2");
   c->tps[prec == GF_FP64][storage == GF_R18] = tps;
   c->nt[prec == GF_FP64][storage == GF_R18] = nontemporal;
   return GF_OK;
@@ -804,13 +839,13 @@ gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, const void* U_
     });
   }
   const int reps = 20;
-  float times[6] = {0, 0, 0, 0, 0, 0};
+  float times[kVariants] = {};
   float best = 1e30f;
   int best_tps = default_tps(g), best_nt = default_nt(g);
   const int i64 = g->prec == GF_FP64, i18 = g->storage == GF_R18;
   const int saved_tps = c->tps[i64][i18], saved_nt = c->nt[i64][i18];
   gf_status st = GF_OK;
-  for (int k = 0; k < 6 && st == GF_OK; ++k) {
+  for (int k = 0; k < kVariants && st == GF_OK; ++k) {
     c->tps[i64][i18] = 1 << (k % 3);
     c->nt[i64][i18] = k / 3;
     for (int w = 0; w < 2 && st == GF_OK; ++w) st = gf_sweep(c, scratch, g, gauge, w & 1, 1.5);
@@ -1356,18 +1391,22 @@ gf_status upload_table(gf_batch* b, int k, const TableSet<T>& t, const BatchEntr
 template <typename T, int NC, class Upd, bool TRACK>
 void launch_batch_update(gf_ctx* c, int tps, int nt, const BatchEntry<T>* tab, int n, uint32_t blocks,
                          const int* active, int parity, const Upd& upd) {
-  auto go = [&]<int TPS, bool NT>() {
+  auto go = [&]<int TPS, int NT>() {
     hipLaunchKernelGGL((k_update_half_batch<T, NC, Upd, TPS, NT, TRACK>), dim3(blocks), dim3(kBlock),
                        0, c->stream, tab, n, active, parity, upd);
   };
-  if (nt) {
-    if (tps == 1) go.template operator()<1, true>();
-    else if (tps == 2) go.template operator()<2, true>();
-    else go.template operator()<4, true>();
+  auto go_tps = [&]<int NT>() {
+    if (tps == 1) go.template operator()<1, NT>();
+    else if (tps == 2) go.template operator()<2, NT>();
+    else go.template operator()<4, NT>();
+  };
+  const int mode = nt_mode<Upd>(nt);
+  if (mode == kNTAll) {
+    go_tps.template operator()<kNTAll>();
+  } else if (mode == kNTStores) {
+    if constexpr (HasStoreMode<Upd>::value) go_tps.template operator()<kNTStores>();
   } else {
-    if (tps == 1) go.template operator()<1, false>();
-    else if (tps == 2) go.template operator()<2, false>();
-    else go.template operator()<4, false>();
+    go_tps.template operator()<kNTNone>();
   }
 }
 

@@ -161,21 +161,28 @@ __host__ __device__ __forceinline__ size_t link_offset(uint32_t vp, int p, int m
          (size_t)(mu * NC) * kTile + (h & (kTile - 1));
 }
 
-// NT = true marks the accesses nontemporal (streaming: each link is read and
-// written once per half-sweep, with no reuse to keep in the caches).
+// Nontemporal modes of the link accesses, a tuning axis of the sweep kernels.
+// Each link is read and written once per half-sweep, so there is no reuse
+// inside a launch; what pays depends on how much of the field the Infinity
+// Cache keeps between half-sweeps:
+//   kNTNone    ordinary loads and stores,
+//   kNTAll     loads and stores streamed (fields far larger than the cache),
+//   kNTStores  stores streamed, loads cached (fields the cache partly holds).
+constexpr int kNTNone = 0, kNTAll = 1, kNTStores = 2;
+
 // q points at component 0 of the link.
-template <typename T, int NC, bool NT = false>
+template <typename T, int NC, int NT = kNTNone>
 __device__ __forceinline__ void load_link(const v2<T>* __restrict__ q, Su3<T>& A) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const v2<T>* p = q + c * kTile;
-    const v2<T> v = NT ? __builtin_nontemporal_load(p) : *p;
+    const v2<T> v = (NT == kNTAll) ? __builtin_nontemporal_load(p) : *p;
     A.e[c / 3][c % 3] = cx<T>(v.x, v.y);
   }
   if (NC == 6) rebuild_row2(A);
 }
 
-template <typename T, int NC, bool NT = false>
+template <typename T, int NC, int NT = kNTNone>
 __device__ __forceinline__ void store_link(v2<T>* __restrict__ q, const Su3<T>& A) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -183,7 +190,7 @@ __device__ __forceinline__ void store_link(v2<T>* __restrict__ q, const Su3<T>& 
     v.x = A.e[c / 3][c % 3].re;
     v.y = A.e[c / 3][c % 3].im;
     v2<T>* p = q + c * kTile;
-    if (NT)
+    if (NT != kNTNone)
       __builtin_nontemporal_store(v, p);
     else
       *p = v;

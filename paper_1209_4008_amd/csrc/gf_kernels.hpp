@@ -363,7 +363,7 @@ __device__ __forceinline__ void lane_sum(Su3<T>& K) {
 // field Gx (6 complex = rows 0, 1 per site, tiled like the links with one
 // direction), g(x) <- Gtot g(x); lane 0
 // of the site does it. gid = TPS * h + lane.
-template <typename T, int NC, int GAUGE, class Upd, int TPS, bool NT, bool TRACK>
+template <typename T, int NC, int GAUGE, class Upd, int TPS, int NT, bool TRACK>
 __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const Lat& L,
                                                  const int parity, const Upd& upd,
                                                  v2<T>* __restrict__ Gx, const uint32_t gid) {
@@ -454,7 +454,7 @@ struct SweepWaves {
   static constexpr int value = 1;
 };
 
-template <typename T, int NC, int GAUGE, class Upd, int TPS, bool NT, bool TRACK = false>
+template <typename T, int NC, int GAUGE, class Upd, int TPS, int NT, bool TRACK = false>
 __global__ __launch_bounds__(kBlock, (SweepWaves<T, TPS>::value)) void k_update_half(v2<T>* __restrict__ U, const Lat L,
                                                         const int parity, const Upd upd,
                                                         v2<T>* __restrict__ Gx = nullptr) {
@@ -589,7 +589,7 @@ __device__ __forceinline__ bool mag_top_eigvec(const T m[6], T v[3]) {
 // every lane finds the same maximiser and its power (Upd: g^omega from the
 // unit quaternion), and each lane transforms its own links in registers,
 // since M of the next subgroup depends on the updated links quadratically.
-template <typename T, int NC, class Upd, int TPS, bool NT, bool TRACK>
+template <typename T, int NC, class Upd, int TPS, int NT, bool TRACK>
 __device__ __forceinline__ void site_mag_update(v2<T>* __restrict__ U, const Lat& L,
                                                 const int parity, const Upd& upd,
                                                 v2<T>* __restrict__ Gx, const uint32_t gid) {
@@ -681,7 +681,7 @@ __device__ __forceinline__ void site_mag_update(v2<T>* __restrict__ U, const Lat
   }
 }
 
-template <typename T, int NC, class Upd, int TPS, bool NT, bool TRACK = false>
+template <typename T, int NC, class Upd, int TPS, int NT, bool TRACK = false>
 __global__ __launch_bounds__(kBlock) void k_mag_half(v2<T>* __restrict__ U, const Lat L,
                                                      const int parity, const Upd upd,
                                                      v2<T>* __restrict__ Gx = nullptr) {
@@ -742,7 +742,7 @@ __device__ __forceinline__ UpdSR<T> for_lattice(const UpdSR<T>& u, uint32_t l) {
   return v;
 }
 
-template <typename T, int NC, class Upd, int TPS, bool NT, bool TRACK>
+template <typename T, int NC, class Upd, int TPS, int NT, bool TRACK>
 __global__ __launch_bounds__(kBlock) void k_update_half_batch(const BatchEntry<T>* __restrict__ tab,
                                                               const int n,
                                                               const int* __restrict__ active,

@@ -44,7 +44,7 @@ def test_form_half_sweep_parity(ctx, dims, prec, storage, gauge, form):
     _check(ctx, U, prec, storage, gauge, 1.7, form)
 
 
-@pytest.mark.parametrize("nt", [0, 1])
+@pytest.mark.parametrize("nt", [0, 1, 2])
 @pytest.mark.parametrize("tps", [1, 2, 4])
 @pytest.mark.parametrize("prec", [gf.FP64, gf.FP32])
 def test_form_variants(ctx, prec, tps, nt):

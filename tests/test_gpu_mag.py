@@ -83,7 +83,7 @@ def test_mag_rough_field_validity(ctx, prec, storage):
         1e-13 if prec == gf.FP64 else 1e-5)
 
 
-@pytest.mark.parametrize("nt", [0, 1])
+@pytest.mark.parametrize("nt", [0, 1, 2])
 @pytest.mark.parametrize("tps", [1, 2, 4])
 @pytest.mark.parametrize("prec", [gf.FP64, gf.FP32])
 def test_mag_variants(ctx, prec, tps, nt):

@@ -71,7 +71,7 @@ def test_half_sweep_parity(ctx, dims, prec, storage, gauge):
     _half_sweep_check(ctx, U, prec, storage, gauge)
 
 
-@pytest.mark.parametrize("nt", [0, 1])
+@pytest.mark.parametrize("nt", [0, 1, 2])
 @pytest.mark.parametrize("tps", [1, 2, 4])
 @pytest.mark.parametrize("gauge", [gf.LANDAU, gf.COULOMB])
 @pytest.mark.parametrize("prec,storage", COMBOS)
@@ -243,7 +243,7 @@ def test_autotune_choice_and_parity_after(ctx, prec, storage):
     say("autotune", prec, storage)
     try:
         (tps, nt), table = ctx.autotune(g, gf.LANDAU, U_like=f)
-        assert set(table) == {(t, n) for t in (1, 2, 4) for n in (0, 1)}
+        assert set(table) == {(t, n) for t in (1, 2, 4) for n in (0, 1, 2)}
         assert all(v > 0 for v in table.values())
         assert table[(tps, nt)] <= 1.03 * min(table.values())
         default = (4, 1) if prec == gf.FP64 else (2, 0)
@@ -271,3 +271,46 @@ def test_vanishing_subgroup_parts(ctx, prec, storage):
         assert np.array_equal(download(ctx, f, g), U)
     r = ctx.fix(f, g, gf.LANDAU, gf.fix_params(theta_target=1e-12, max_sweeps=100))
     assert r.status == gf.OK and r.sweeps == 0 and r.F == 0.0 and r.theta == 0.0
+
+
+@pytest.mark.parametrize("tps", [1, 2, 4])
+def test_nontemporal_modes_change_no_bit(ctx, tps):
+    """The nontemporal modes are cache hints only: sweeps, the tracked mixed
+    driver and a batch give the same bits under modes 0, 1 and 2."""
+    dims = (4, 6, 8, 10)
+    U = inputs.config0(dims, 0.5, 19)
+    outs = []
+    for nt in (0, 1, 2):
+        say("nontemporal mode", nt, "lanes", tps)
+        for prec in (gf.FP32, gf.FP64):
+            ctx.set_sweep_variant(prec, gf.R12, tps, nt)
+        try:
+            res = []
+            for prec in (gf.FP32, gf.FP64):
+                f, g = upload(ctx, U, prec, gf.R12)
+                for k in range(4):
+                    ctx.sweep(f, g, gf.LANDAU, k % 2, 1.7)
+                res.append(download(ctx, f, g))
+            glo = gf.Geom.make(dims, gf.FP32, gf.R12)
+            hi, ghi = upload(ctx, U, gf.FP64, gf.R12)
+            lo = ctx.empty_field(glo)
+            p = gf.fix_params(omega=1.7, theta_target=1e-12, theta_switch=1e-6, max_sweeps=3000,
+                              check_every=100, flags=gf.FLAG_GRAPH)
+            r = ctx.fix_mixed(lo, glo, hi, ghi, gf.LANDAU, p)
+            res.append(download(ctx, hi, ghi))
+            b_f, b_g = upload(ctx, U, gf.FP64, gf.R12)
+            b = gf.Batch(ctx, [b_g], [b_f])
+            try:
+                rb = b.run(p)
+            finally:
+                b.close()
+            res.append(download(ctx, b_f, b_g))
+            res.append((r.sweeps, r.F, rb[0].sweeps, rb[0].F))
+            outs.append(res)
+        finally:
+            for prec in (gf.FP32, gf.FP64):
+                ctx.set_sweep_variant(prec, gf.R12, 0, -1)
+    for other in outs[1:]:
+        for a, b_ in zip(outs[0][:4], other[:4]):
+            assert np.array_equal(a, b_)
+        assert outs[0][4] == other[4]
