@@ -443,9 +443,13 @@ static void launch_update_tps(gf_ctx* c, int tps, int nt, void* U, const Lat& L,
                               const Upd& upd) {
   if constexpr (GAUGE == kMAG) {
     if constexpr (MagCapable<Upd>::value) {
-      if (nt != kNTNone)
+      const int mode = nt_mode<Upd>(nt);
+      if (mode == kNTAll)
         launch_mag_v<T, NC, Upd, kNTAll, false>(c, tps, U, nullptr, L, parity, upd);
-      else
+      else if (mode == kNTStores) {
+        if constexpr (HasStoreMode<Upd>::value)
+          launch_mag_v<T, NC, Upd, kNTStores, false>(c, tps, U, nullptr, L, parity, upd);
+      } else
         launch_mag_v<T, NC, Upd, kNTNone, false>(c, tps, U, nullptr, L, parity, upd);
     }
     return;
@@ -605,8 +609,14 @@ static gf_status update_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, 
       go_gauge.template operator()<NC, kLandau>();
     } else if (gauge == GF_MAG) {
       if constexpr (MagCapable<Upd>::value) {
-        if (nt != kNTNone) launch_mag_v<float, NC, Upd, kNTAll, true>(c, tps, U, Gx, L, parity, upd);
-        else launch_mag_v<float, NC, Upd, kNTNone, true>(c, tps, U, Gx, L, parity, upd);
+        if (mode == kNTAll) {
+          launch_mag_v<float, NC, Upd, kNTAll, true>(c, tps, U, Gx, L, parity, upd);
+        } else if (mode == kNTStores) {
+          if constexpr (HasStoreMode<Upd>::value)
+            launch_mag_v<float, NC, Upd, kNTStores, true>(c, tps, U, Gx, L, parity, upd);
+        } else {
+          launch_mag_v<float, NC, Upd, kNTNone, true>(c, tps, U, Gx, L, parity, upd);
+        }
       }
     } else {
       go_gauge.template operator()<NC, kCoulomb>();
