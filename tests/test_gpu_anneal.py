@@ -129,10 +129,16 @@ def test_coulomb_full_size_sampled(ctx, prec):
     cand = rng.choice(V, size=1024, replace=False)
     for kind in ("hb", "or"):
         f, g = upload(ctx, U, prec, gf.R12)
-        if kind == "hb":
-            ctx.heatbath_half(f, g, gf.COULOMB, 0, 1.45, 4, 0)
-        else:
-            ctx.sweep(f, g, gf.COULOMB, 0, 1.7)
+        try:
+            # the variant the Coulomb workload tunes and times
+            variant, _ = ctx.autotune(g, gf.COULOMB, U_like=f)
+            say("coulomb full size", kind, "precision", prec, "autotuned variant", variant)
+            if kind == "hb":
+                ctx.heatbath_half(f, g, gf.COULOMB, 0, 1.45, 4, 0)
+            else:
+                ctx.sweep(f, g, gf.COULOMB, 0, 1.7)
+        finally:
+            ctx.set_sweep_variant(prec, gf.R12, 0, -1)
         got = download(ctx, f, g).reshape(V, 4, 3, 3)
         ref = oracle_input(U, prec, gf.R12)
         sites = [int(s) for s in cand if site_parity(dims, s) == 0][:256]
