@@ -163,6 +163,17 @@ struct UpdMicro {
 // uniform on the sphere of radius sqrt(1 - X0^2).
 // Philox: key (seed lo, seed hi), counter (site, sweep, tag, attempt),
 // tag = 0x1000 | kind << 8 | subgroup, kind 0 = trial, 1 = direction.
+// transcendental functions of the sampler: in FP32 the hardware
+// approximations (relative error ~1e-6, below what the FP32 links and the
+// FP32 accept test resolve anyway); in FP64 the correctly rounded library
+// functions, which the parity tests against the oracle rely on
+__device__ __forceinline__ float hb_log(float x) { return __logf(x); }
+__device__ __forceinline__ double hb_log(double x) { return log(x); }
+__device__ __forceinline__ float hb_cos(float x) { return __cosf(x); }
+__device__ __forceinline__ double hb_cos(double x) { return cos(x); }
+__device__ __forceinline__ float hb_sin(float x) { return __sinf(x); }
+__device__ __forceinline__ double hb_sin(double x) { return sin(x); }
+
 constexpr uint32_t kTagKP = 0x1000u;
 constexpr uint32_t kTagDir = 0x1100u;
 constexpr uint32_t kMaxAttempts = 1024u;
@@ -182,8 +193,8 @@ struct UpdHB {
       const U4 r = philox4x32_10(site, sweep, kTagKP | (uint32_t)sg, att, k0, k1);
       const T u0 = unit_open<T>(r.v[0]), u1 = unit_open<T>(r.v[1]);
       const T u2 = unit_open<T>(r.v[2]), u3 = unit_open<T>(r.v[3]);
-      const T cs = cos(two_pi * u1);
-      const T l2 = -(log(u0) + cs * cs * log(u2)) / (2 * alpha);
+      const T cs = hb_cos(two_pi * u1);
+      const T l2 = -(hb_log(u0) + cs * cs * hb_log(u2)) / (2 * alpha);
       if (u3 * u3 <= 1 - l2) {
         lam2 = l2;
         break;
@@ -197,7 +208,7 @@ struct UpdHB {
     const T phi = two_pi * d1;
     // sqrt(1 - X0^2) = 2 lambda sqrt(1 - lambda^2) for X0 = 1 - 2 lambda^2
     const T rad = 2 * sqrt_t(lam2 * (1 - lam2));
-    const T X[4] = {1 - 2 * lam2, rad * sth * cos(phi), rad * sth * sin(phi), rad * cth};
+    const T X[4] = {1 - 2 * lam2, rad * sth * hb_cos(phi), rad * sth * hb_sin(phi), rad * cth};
     const T wh[4] = {w[0] / n, w[1] / n, w[2] / n, w[3] / n};
     qmul(X, wh, s);
     // renormalise: keeps repeated low-precision draws on SU(2)
