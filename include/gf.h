@@ -191,7 +191,8 @@ gf_status gf_philox(gf_ctx* ctx, const uint32_t* ctr_dev, uint64_t seed, uint32_
  * of K(x)), nontemporal = 0 for ordinary link accesses, 1 to mark the link
  * loads and stores as streaming, 2 to stream the stores only (loads cached;
  * pays when the cache holds part of the field between half-sweeps; the
- * overrelaxation sweeps only, the other updates run 2 as 1).
+ * overrelaxation and stochastic-relaxation sweeps, the annealing updates run
+ * 2 as 1).
  * tps = 0 / nontemporal = -1 restore the built-in defaults. */
 gf_status gf_set_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t tps,
                                int32_t nontemporal);

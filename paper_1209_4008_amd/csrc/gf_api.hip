@@ -368,14 +368,23 @@ constexpr int kVariants = 9;
 static int default_nt(const gf_geom* g) { return g->prec == GF_FP64 ? 1 : 0; }
 
 // the stores-only nontemporal mode is instantiated for the overrelaxation
-// sweep only (the kernel the autotuner times); the other updates run it as
-// kNTAll
+// sweeps (all forms of g^omega and stochastic relaxation: the same
+// bandwidth-bound sweep the autotuner times); the annealing updates run it
+// as kNTAll
 template <class Upd>
 struct HasStoreMode {
   static constexpr bool value = false;
 };
 template <typename T>
 struct HasStoreMode<UpdOR<T>> {
+  static constexpr bool value = true;
+};
+template <typename T>
+struct HasStoreMode<UpdORForm<T>> {
+  static constexpr bool value = true;
+};
+template <typename T>
+struct HasStoreMode<UpdSR<T>> {
   static constexpr bool value = true;
 };
 template <class Upd>

@@ -58,3 +58,21 @@ def test_sr_driver_is_its_sweeps(ctx):
     # the same gauge is reached as by overrelaxation (F of the FP64 oracle's OR run)
     ro = O.fix(oracle_input(U, gf.FP64, gf.R12), gf.LANDAU, 1.7, 1e-12, 3000, 50, 1)
     assert r.F == pytest.approx(ro["F"], rel=1e-9)
+
+
+@pytest.mark.parametrize("nt", [0, 1, 2])
+@pytest.mark.parametrize("tps", [1, 4])
+def test_sr_variants(ctx, tps, nt):
+    """Stochastic relaxation in every nontemporal mode and lanes per site."""
+    dims = (4, 6, 8, 10)
+    U = inputs.config0(dims, 0.6, 62)
+    ctx.set_sweep_variant(gf.FP64, gf.R12, tps, nt)
+    try:
+        ref = oracle_input(U, gf.FP64, gf.R12)
+        for par in (0, 1):
+            f, g = upload(ctx, ref, gf.FP64, gf.R12)
+            ctx.sweep_sr(f, g, gf.LANDAU, par, 1.2, 0.5, 321, 7)
+            O.sweep_sr(ref, gf.LANDAU, par, 1.2, 0.5, 321, 7)
+            assert np.abs(download(ctx, f, g) - ref).max() <= TOL[gf.FP64]
+    finally:
+        ctx.set_sweep_variant(gf.FP64, gf.R12, 0, -1)
