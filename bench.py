@@ -599,6 +599,12 @@ def main():
         del gsave
         extras["variants"] = variant_rates(ctx, torch, gf, canon, dims, args.omega)
         extras.update(stream_probes(ctx, torch))
+        # the same achieved rate against what plain streaming kernels reach on
+        # this GPU (copy: read + write of 2 GiB; rmw: in-place read-modify-write)
+        for probe in ("copy", "rmw"):
+            key = probe + "_GBps"
+            if extras.get(key):
+                roofline["frac_of_measured_" + probe] = round(achieved / extras[key], 4)
     extras["autotune"] = tuning
 
     cpu = None
