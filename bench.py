@@ -663,10 +663,21 @@ def cpu_baseline(canon, dims, args):
         oracle.sweep(U, oracle.LANDAU, 1, args.omega)
     dt = time.perf_counter() - t0
     log(f"cpu oracle: {n} sweeps in {dt:.1f} s on {threads} threads")
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(V * n / dt, 1), "unit": "site-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{n} FP64 overrelaxation sweeps (omega {args.omega}) of the "
-                      f"{'x'.join(map(str, dims))} input, canonical 18-real layout"}
+                      f"{'x'.join(map(str, dims))} input, canonical 18-real layout",
+            "host": {"cpu_model": model, "nproc": os.cpu_count(),
+                     "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}}
 
 
 def cpu_extras(canon, dims, args, ctx, torch, gf):
