@@ -237,8 +237,9 @@ gf_status gf_selftest_host(void) {
     for (uint32_t n = 0; n < 5000; ++n)
       if (fdiv(n * 7919u, f) != (n * 7919u) / d) return GF_ERR_UNSUPPORTED;
   }
-  const int shapes[][4] = {{2, 2, 2, 2}, {4, 4, 4, 4}, {6, 4, 2, 10}, {4, 6, 8, 10},
-                           {8, 2, 6, 4}, {2, 12, 2, 14}, {10, 6, 4, 2}, {24, 12, 12, 12}};
+  const int shapes[][4] = {{2, 2, 2, 2},     {4, 4, 4, 4},    {6, 4, 2, 10},  {4, 6, 8, 10},
+                           {8, 2, 6, 4},     {2, 12, 2, 14},  {10, 6, 4, 2},  {24, 12, 12, 12},
+                           {2, 2, 2, 65536}, {2, 2, 32768, 4}, {2, 16384, 2, 6}, {32768, 2, 2, 2}};
   for (const auto& d : shapes)
     if (!selftest_lattice(d[0], d[1], d[2], d[3])) return GF_ERR_UNSUPPORTED;
   return GF_OK;

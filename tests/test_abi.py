@@ -42,6 +42,11 @@ def test_geometry_validation_and_sizes():
     # V/2 is padded to whole tiles of 128 sites: 6x4x2x10 has 240 sites per parity
     assert gf.field_bytes(gf.Geom.make((6, 4, 2, 10), gf.FP32, gf.R18)) == 8 * 256 * 18 * 4
     assert gf.field_bytes(gf.Geom.make((2, 2, 2, 2), gf.FP64, gf.R12)) == 8 * 128 * 12 * 8
+    # the largest accepted volume, 2^30 sites: sizes computed without overflow
+    big = gf.Geom.make((256, 256, 128, 128), gf.FP64, gf.R18)
+    assert gf.check_geom(big) == gf.OK
+    assert gf.field_bytes(big) == 4 * 2 ** 30 * 18 * 8
+    assert gf.check_geom(gf.Geom.make((256, 256, 128, 130))) == gf.ERR_ARG
     for bad in [gf.Geom.make((7, 8, 8, 8)), gf.Geom.make((8, 8, 8, 0)),
                 gf.Geom.make((8, 8, 8, 8), 5, gf.R18), gf.Geom.make((8, 8, 8, 8), gf.FP32, 10),
                 gf.Geom.make((2048, 2048, 2048, 2))]:
