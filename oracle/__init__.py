@@ -42,6 +42,8 @@ def lib():
             "or_mag_sweep": (C.c_int, [d, i32p, C.c_int, C.c_double, C.c_int]),
             "or_mag_functional": (C.c_double, [d, i32p]),
             "or_mag_theta": (C.c_double, [d, i32p]),
+            "or_fix_coulomb_frozen": (C.c_int, [d, i32p, C.c_double, C.c_double, C.c_int32,
+                                                C.c_int32, C.c_int32, i32p, d, d, i32p]),
             "or_fix_mag": (C.c_int, [d, i32p, C.c_double, C.c_int, C.c_double, C.c_int32,
                                      C.c_int32, C.c_int32, i32p, d, d]),
             "or_sweep_form": (C.c_int, [d, i32p, C.c_int, C.c_int, C.c_double, C.c_int]),
@@ -163,6 +165,21 @@ def mag_functional(U):
 
 def mag_theta(U):
     return lib().or_mag_theta(_field(U), _dims(dims_of(U)))
+
+
+def fix_coulomb_frozen(U, omega, theta_target, max_sweeps, check_every=100, reunit_at_check=1):
+    nt = U.shape[0]
+    sw = C.c_int32(0)
+    F = np.zeros(nt)
+    th = np.zeros(nt)
+    fr = np.zeros(nt, dtype=np.int32)
+    rc = lib().or_fix_coulomb_frozen(_field(U), _dims(dims_of(U)), float(omega),
+                                     float(theta_target), int(max_sweeps), int(check_every),
+                                     int(reunit_at_check), C.byref(sw), _dptr(F), _dptr(th),
+                                     fr.ctypes.data_as(C.POINTER(C.c_int32)))
+    if rc < 0:
+        raise ValueError("or_fix_coulomb_frozen: bad arguments")
+    return {"converged": rc == 0, "sweeps": sw.value, "F": F, "theta": th, "frozen_at": fr}
 
 
 def fix_mag(U, omega, theta_target, max_sweeps, check_every=100, reunit_at_check=1, form=0):

@@ -104,6 +104,17 @@ int or_fix(double* U, const int32_t dims[4], int gauge, double omega, int form,
            int32_t reunit_at_check, int32_t* sweeps_out, double* F_out,
            double* theta_out);
 
+/* Coulomb gauge with each timeslice frozen (no longer swept) from the first
+ * check at which its theta_t is below the target; the timeslices are
+ * independent problems. F_out, theta_out: nt values each; frozen_at (or NULL):
+ * per timeslice the sweep count at which it was frozen, -1 if never.
+ * Returns 0 when every timeslice is frozen, 1 at max_sweeps, <0 on bad
+ * arguments. */
+int    or_fix_coulomb_frozen(double* U, const int32_t dims[4], double omega, double theta_target,
+                             int32_t max_sweeps, int32_t check_every, int32_t reunit_at_check,
+                             int32_t* sweeps_out, double* F_out, double* theta_out,
+                             int32_t* frozen_at);
+
 /* maximally Abelian gauge (named in Sec. 1 and the summary, functional from
  * the literature): maximise R = sum_{x,mu} sum_k |U_mu(x)_kk|^2 -------------- */
 /* M (4x4, row major) of the quadratic form R_x(a) = a^T M a + const of the 8

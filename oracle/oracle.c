@@ -828,6 +828,60 @@ int or_fix(double* U, const int32_t dims[4], int gauge, double omega, int form,
   return converged ? 0 : 1;
 }
 
+/* Coulomb gauge with converged timeslices frozen: the timeslices are
+ * independent gauge-fixing problems (K, F and theta of a timeslice involve its
+ * spatial links only), so at every check each timeslice whose theta_t is
+ * below the target stops being swept; its spatial links then stay as they
+ * are, while the temporal links it shares with a timeslice still being swept
+ * keep receiving that timeslice's transformations. Stops when every theta_t
+ * is below the target (all frozen) or at max_sweeps. F_out and theta_out
+ * receive nt values each; frozen_at (may be NULL) receives, per timeslice,
+ * the sweep count at which it was frozen (-1 if never). */
+int or_fix_coulomb_frozen(double* U, const int32_t dims[4], double omega, double theta_target,
+                          int32_t max_sweeps, int32_t check_every, int32_t reunit_at_check,
+                          int32_t* sweeps_out, double* F_out, double* theta_out,
+                          int32_t* frozen_at) {
+  if (!U || or_check_dims(dims) != 0 || check_every < 1 || max_sweeps < 0) return -1;
+  if (!(omega >= 1.0 && omega < 2.0) || !F_out || !theta_out) return -1;
+  lat_t L = make_lat(dims);
+  const int64_t nt = L.ext[0], Vs = L.V / nt;
+  unsigned char* active = (unsigned char*)malloc((size_t)nt);
+  for (int64_t t = 0; t < nt; ++t) {
+    active[t] = 1;
+    if (frozen_at) frozen_at[t] = -1;
+  }
+  int32_t sweeps = 0;
+  int converged = 0;
+  upd_t u = {UPD_OR, omega, 0.0, 0, 0, 0};
+  for (;;) {
+    if (sweeps > 0 && reunit_at_check) or_reunitarize(U, L.V * 4);
+    or_functional(U, dims, OR_COULOMB, F_out);
+    or_theta_K(U, dims, OR_COULOMB, theta_out);
+    int n_active = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+      if (active[t] && theta_out[t] < theta_target) {
+        active[t] = 0;
+        if (frozen_at) frozen_at[t] = sweeps;
+      }
+      n_active += active[t];
+    }
+    if (n_active == 0) { converged = 1; break; }
+    if (sweeps >= max_sweeps) break;
+    for (int32_t k = 0; k < check_every && sweeps < max_sweeps; ++k) {
+      for (int parity = 0; parity < 2; ++parity) {
+#pragma omp parallel for schedule(static)
+        for (int64_t s = 0; s < L.V; ++s)
+          if (site_parity(&L, s) == parity && active[s / Vs])
+            site_update(U, &L, OR_COULOMB, s, &u);
+      }
+      ++sweeps;
+    }
+  }
+  free(active);
+  if (sweeps_out) *sweeps_out = sweeps;
+  return converged ? 0 : 1;
+}
+
 /* ------------------------------------------------------------------------- */
 /* maximally Abelian gauge (named in Sec. 1 and the summary; the paper does   */
 /* not write out its functional): maximise                                    */

@@ -476,3 +476,36 @@ def test_vanishing_subgroup_parts_are_skipped():
         assert O.theta_K(W, gauge)[0] == 0.0
     r = O.fix(U.copy(), L, 1.7, 1e-12, 100)
     assert r["converged"] and r["sweeps"] == 0 and r["F"] == 0.0
+
+
+def test_coulomb_frozen_driver():
+    """Coulomb timeslices are independent problems; freezing each one once
+    its theta_t is below the target (i) changes nothing while none is frozen,
+    (ii) leaves a frozen timeslice's spatial links exactly as they were at
+    its freeze, (iii) still yields a gauge transform of the input with every
+    theta_t below the target."""
+    dims = (6, 4, 4, 6)
+    U = inputs.config0(dims, 0.5, 31)
+    # (i) target 0: nothing freezes, identical to the plain driver
+    A, B = U.copy(), U.copy()
+    ra = O.fix_coulomb_frozen(A, 1.7, 0.0, 60, check_every=20)
+    rb = O.fix(B, CLB, 1.7, 0.0, 60, check_every=20)
+    assert not ra["converged"] and ra["sweeps"] == rb["sweeps"] == 60
+    assert np.array_equal(A, B)
+    assert np.all(ra["frozen_at"] == -1)
+    # (iii) converged run
+    target = 1e-12
+    C = U.copy()
+    rc = O.fix_coulomb_frozen(C, 1.7, target, 4000, check_every=20, reunit_at_check=0)
+    assert rc["converged"] and np.all(rc["theta"] < target)
+    assert np.all(rc["frozen_at"] >= 0)
+    assert len(set(rc["frozen_at"].tolist())) > 1  # timeslices converge at different times
+    assert abs(O.plaquette(C) - O.plaquette(U)) < 1e-13
+    M = C.reshape(-1, 3, 3)
+    assert np.abs(M @ M.conj().transpose(0, 2, 1) - np.eye(3)).max() < 1e-12
+    # (ii) spatial links of each timeslice as at its freeze (no reunitarisation)
+    for t in np.unique(rc["frozen_at"]):
+        D = U.copy()
+        O.fix_coulomb_frozen(D, 1.7, target, int(t), check_every=20, reunit_at_check=0)
+        for ts in np.nonzero(rc["frozen_at"] == t)[0]:
+            assert np.array_equal(C[ts, :, :, :, 1:], D[ts, :, :, :, 1:])
