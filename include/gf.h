@@ -222,6 +222,16 @@ gf_status gf_stream_probe(gf_ctx* ctx, const void* src, void* dst, size_t bytes,
 #define GF_FLAG_TIMING 1u    /* record hipEvent kernel timings into the result */
 #define GF_FLAG_GRAPH 2u     /* replay the sweeps between checks as a hipGraph */
 #define GF_FLAG_NO_TRACK 4u  /* gf_fix_mixed: do not track g in the FP32 phase   */
+/* GF_COULOMB only (else GF_ERR_ARG; batches GF_ERR_UNSUPPORTED): freeze each
+ * timeslice from the first check at which its theta_t < the phase's target
+ * on (its sites are no longer updated; reunitarisation still covers the
+ * whole field); a phase ends when every timeslice is frozen. Coulomb gauge
+ * (Sec. 1: the condition on the spatial components only) is one independent
+ * problem per timeslice: F and theta_t involve the spatial links of
+ * timeslice t only, and a site update changes the spatial links of its own
+ * timeslice only, so the frozen timeslices keep the theta_t they converged
+ * with, and the sweeps go to the ones that have not. */
+#define GF_FLAG_FREEZE_TIMESLICES 8u
 
 typedef struct {
   double omega;            /* overrelaxation parameter, [1, 2)                         */
@@ -262,7 +272,8 @@ typedef struct {
   double kernel_ms[6];
   int64_t kernel_launches[6];
   int32_t sa_steps;        /* annealing steps done                                 */
-  int32_t reserved;
+  int32_t frozen_slice_sweeps; /* GF_FLAG_FREEZE_TIMESLICES: sum over sweeps of the
+                              number of frozen timeslices (work not done)         */
 } gf_fix_result;
 
 /* Runs the annealing schedule of params (if sa_steps > 0), then sweeps U (in

@@ -16,7 +16,7 @@ ERR_ARG, ERR_UNSUPPORTED, ERR_DEVICE, ERR_HIP, ERR_NONFINITE, ERR_NOMEM = -1, -2
 LANDAU, COULOMB, MAG = 0, 1, 2
 FP32, FP64 = 4, 8
 R12, R18 = 12, 18
-FLAG_TIMING, FLAG_GRAPH, FLAG_NO_TRACK = 1, 2, 4
+FLAG_TIMING, FLAG_GRAPH, FLAG_NO_TRACK, FLAG_FREEZE_TIMESLICES = 1, 2, 4, 8
 
 
 class GFError(RuntimeError):
@@ -58,14 +58,15 @@ class FixResult(C.Structure):
                 ("checks", C.c_int32), ("F", C.c_double), ("theta", C.c_double),
                 ("theta_at_switch", C.c_double), ("wall_ms", C.c_double),
                 ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_int64 * 6),
-                ("sa_steps", C.c_int32), ("reserved", C.c_int32)]
+                ("sa_steps", C.c_int32), ("frozen_slice_sweeps", C.c_int32)]
 
     def as_dict(self):
         return {"status": self.status, "sweeps": self.sweeps, "sweeps_lo": self.sweeps_lo,
                 "checks": self.checks, "F": self.F, "theta": self.theta,
                 "theta_at_switch": self.theta_at_switch, "wall_ms": self.wall_ms,
                 "kernel_ms": list(self.kernel_ms),
-                "kernel_launches": list(self.kernel_launches), "sa_steps": self.sa_steps}
+                "kernel_launches": list(self.kernel_launches), "sa_steps": self.sa_steps,
+                "frozen_slice_sweeps": self.frozen_slice_sweeps}
 
 
 # every symbol of include/gf.h with its ctypes signature

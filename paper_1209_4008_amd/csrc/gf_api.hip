@@ -31,6 +31,13 @@ struct gf_ctx {
   size_t gbuf_cap = 0;   // bytes
   hipStream_t capture = nullptr;  // private stream for hipGraph capture
   std::vector<hipEvent_t> pool;   // driver timing events, pairs (start, end)
+  // Coulomb drivers with GF_FLAG_FREEZE_TIMESLICES: one byte per timeslice,
+  // 0 = frozen; `tmask` is what the sweep launches pass (NULL outside such a
+  // driver call)
+  uint8_t* dev_tmask = nullptr;
+  uint8_t* host_tmask = nullptr;  // pinned
+  size_t tmask_cap = 0;
+  const uint8_t* tmask = nullptr;
 };
 
 static char g_create_err[512] = "no error";
@@ -138,6 +145,19 @@ static gf_status ensure_partial(gf_ctx* c, size_t n_doubles) {
   c->partial_cap = 0;
   HIP_OR_FAIL(c, hipMalloc(&c->partial, n_doubles * sizeof(double)));
   c->partial_cap = n_doubles;
+  return GF_OK;
+}
+
+static gf_status ensure_tmask(gf_ctx* c, size_t n) {
+  if (n <= c->tmask_cap) return GF_OK;
+  if (c->dev_tmask) HIP_OR_FAIL(c, hipFree(c->dev_tmask));
+  if (c->host_tmask) HIP_OR_FAIL(c, hipHostFree(c->host_tmask));
+  c->dev_tmask = nullptr;
+  c->host_tmask = nullptr;
+  c->tmask_cap = 0;
+  HIP_OR_FAIL(c, hipMalloc(&c->dev_tmask, n));
+  HIP_OR_FAIL(c, hipHostMalloc(&c->host_tmask, n, hipHostMallocDefault));
+  c->tmask_cap = n;
   return GF_OK;
 }
 
@@ -276,6 +296,8 @@ gf_status gf_destroy(gf_ctx* c) {
   if (c->dev_out) (void)hipFree(c->dev_out);
   if (c->host_out) (void)hipHostFree(c->host_out);
   if (c->gbuf) (void)hipFree(c->gbuf);
+  if (c->dev_tmask) (void)hipFree(c->dev_tmask);
+  if (c->host_tmask) (void)hipHostFree(c->host_tmask);
   if (c->capture) (void)hipStreamDestroy(c->capture);
   for (auto& e : c->pool) (void)hipEventDestroy(e);
   for (auto& e : c->ev)
@@ -396,20 +418,21 @@ static int nt_mode(int nt) {
 
 template <typename T, int NC, int GAUGE, class Upd, int NT>
 static void launch_update_v(gf_ctx* c, int tps, void* U, const Lat& L, int parity, const Upd& upd) {
+  const uint8_t* tm = GAUGE == kCoulomb ? c->tmask : nullptr;
   const uint64_t n = (uint64_t)L.vh * (uint64_t)tps;
   const dim3 grid(blocks_for(n));
   switch (tps) {
     case 1:
       hipLaunchKernelGGL((k_update_half<T, NC, GAUGE, Upd, 1, NT>), grid, dim3(kBlock), 0, c->stream,
-                         (v2<T>*)U, L, parity, upd);
+                         (v2<T>*)U, L, parity, upd, (v2<T>*)nullptr, tm);
       break;
     case 2:
       hipLaunchKernelGGL((k_update_half<T, NC, GAUGE, Upd, 2, NT>), grid, dim3(kBlock), 0, c->stream,
-                         (v2<T>*)U, L, parity, upd);
+                         (v2<T>*)U, L, parity, upd, (v2<T>*)nullptr, tm);
       break;
     default:
       hipLaunchKernelGGL((k_update_half<T, NC, GAUGE, Upd, 4, NT>), grid, dim3(kBlock), 0, c->stream,
-                         (v2<T>*)U, L, parity, upd);
+                         (v2<T>*)U, L, parity, upd, (v2<T>*)nullptr, tm);
       break;
   }
 }
@@ -479,19 +502,20 @@ static void launch_update_tps(gf_ctx* c, int tps, int nt, void* U, const Lat& L,
 template <int NC, int GAUGE, int NT, class Upd>
 static void launch_tracked_v(gf_ctx* c, int tps, void* U, void* Gx, const Lat& L, int parity,
                              const Upd& upd) {
+  const uint8_t* tm = GAUGE == kCoulomb ? c->tmask : nullptr;
   const dim3 grid(blocks_for((uint64_t)L.vh * (uint64_t)tps));
   switch (tps) {
     case 1:
       hipLaunchKernelGGL((k_update_half<float, NC, GAUGE, Upd, 1, NT, true>), grid, dim3(kBlock), 0,
-                         c->stream, (v2<float>*)U, L, parity, upd, (v2<float>*)Gx);
+                         c->stream, (v2<float>*)U, L, parity, upd, (v2<float>*)Gx, tm);
       break;
     case 2:
       hipLaunchKernelGGL((k_update_half<float, NC, GAUGE, Upd, 2, NT, true>), grid, dim3(kBlock), 0,
-                         c->stream, (v2<float>*)U, L, parity, upd, (v2<float>*)Gx);
+                         c->stream, (v2<float>*)U, L, parity, upd, (v2<float>*)Gx, tm);
       break;
     default:
       hipLaunchKernelGGL((k_update_half<float, NC, GAUGE, Upd, 4, NT, true>), grid, dim3(kBlock), 0,
-                         c->stream, (v2<float>*)U, L, parity, upd, (v2<float>*)Gx);
+                         c->stream, (v2<float>*)U, L, parity, upd, (v2<float>*)Gx, tm);
       break;
   }
 }
@@ -990,6 +1014,7 @@ struct Phase {
   int32_t checks = 0;
   int converged = 0;
   double F = 0, theta = 0;
+  int64_t skipped = 0;  // timeslice-sweeps not done (frozen timeslices)
 };
 
 gf_status check_params(gf_ctx* c, const gf_fix_params* p) {
@@ -1121,7 +1146,37 @@ gf_status capture_sweeps(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge,
   return GF_OK;
 }
 
-// sweeps `geom`'s field until theta < target or max_sweeps
+// sets the context's timeslice mask for the lifetime of a driver phase
+struct MaskScope {
+  gf_ctx* c;
+  explicit MaskScope(gf_ctx* ctx, const uint8_t* m) : c(ctx) { c->tmask = m; }
+  ~MaskScope() { c->tmask = nullptr; }
+};
+
+// Coulomb with GF_FLAG_FREEZE_TIMESLICES: after a check, freeze every
+// timeslice whose theta_t (host_out, as do_check left it) is below target;
+// returns the number still active and uploads the mask when it changed
+gf_status update_tmask(gf_ctx* c, const gf_geom* g, double target, int* n_active) {
+  bool changed = false;
+  int n = 0;
+  for (int t = 0; t < g->nt; ++t) {
+    if (c->host_tmask[t] && c->host_out[c->out_cap + t] < target) {
+      c->host_tmask[t] = 0;
+      changed = true;
+    }
+    n += c->host_tmask[t];
+  }
+  // the previous upload has completed: do_check synchronised the stream
+  if (changed && n > 0)
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->dev_tmask, c->host_tmask, (size_t)g->nt,
+                                  hipMemcpyHostToDevice, c->stream));
+  *n_active = n;
+  return GF_OK;
+}
+
+// sweeps `geom`'s field until theta < target or max_sweeps; with
+// GF_FLAG_FREEZE_TIMESLICES (Coulomb) until every timeslice has had
+// theta_t < target at a check, each timeslice frozen from that check on
 gf_status run_phase(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const gf_fix_params* p,
                     double target, bool first_check_reunit, Timer& tm, Phase& ph,
                     void* Gx = nullptr) {
@@ -1129,11 +1184,26 @@ gf_status run_phase(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const g
   const int cat = g->prec == GF_FP32 ? 0 : 1;
   // stochastic relaxation changes its kernel arguments every sweep: no replay
   const bool use_graph = (p->flags & GF_FLAG_GRAPH) != 0 && !(p->sr_prob > 0.0);
+  const bool freeze = gauge == GF_COULOMB && (p->flags & GF_FLAG_FREEZE_TIMESLICES) != 0;
+  if (freeze) {
+    if ((st = ensure_tmask(c, (size_t)g->nt)) != GF_OK) return st;
+    memset(c->host_tmask, 1, (size_t)g->nt);
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->dev_tmask, c->host_tmask, (size_t)g->nt,
+                                  hipMemcpyHostToDevice, c->stream));
+  }
+  MaskScope scope(c, freeze ? c->dev_tmask : nullptr);
   SweepGraph sg;
+  int n_active = g->nt;
   for (;;) {
     const bool reunit = p->reunit_at_check && (ph.sweeps > 0 || first_check_reunit);
     if ((st = do_check(c, U, g, gauge, reunit, tm, ph)) != GF_OK) return st;
-    if (ph.theta < target) {
+    if (freeze) {
+      if ((st = update_tmask(c, g, target, &n_active)) != GF_OK) return st;
+      if (n_active == 0) {
+        ph.converged = 1;
+        return GF_OK;
+      }
+    } else if (ph.theta < target) {
       ph.converged = 1;
       return GF_OK;
     }
@@ -1148,12 +1218,15 @@ gf_status run_phase(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const g
       return st;
     if ((st = tm.end(cat, 2 * (int64_t)n)) != GF_OK) return st;
     ph.sweeps += n;
+    ph.skipped += (int64_t)(g->nt - n_active) * n;
   }
 }
 
 void init_result(gf_fix_result* r) {
   memset(r, 0, sizeof *r);
 }
+
+int32_t clamp_i32(int64_t v) { return v > INT32_MAX ? INT32_MAX : (int32_t)v; }
 
 }  // namespace
 
@@ -1169,6 +1242,8 @@ gf_status gf_fix(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const gf_f
   if (!U || !r) return fail(c, GF_ERR_ARG, "gf_fix: NULL pointer");
   gf_status st = check_params(c, p);
   if (st != GF_OK) return st;
+  if ((p->flags & GF_FLAG_FREEZE_TIMESLICES) && gauge != GF_COULOMB)
+    return fail(c, GF_ERR_ARG, "gf_fix: GF_FLAG_FREEZE_TIMESLICES needs GF_COULOMB");
   init_result(r);
   const auto t0 = std::chrono::steady_clock::now();
   Timer tm{c, (p->flags & GF_FLAG_TIMING) != 0, r->kernel_ms, r->kernel_launches};
@@ -1180,6 +1255,7 @@ gf_status gf_fix(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const gf_f
   r->checks = ph.checks;
   r->F = ph.F;
   r->theta = ph.theta;
+  r->frozen_slice_sweeps = clamp_i32(ph.skipped);
   r->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (st != GF_OK) {
     r->status = st;
@@ -1212,6 +1288,8 @@ gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
   gf_status st = check_params(c, p);
   if (st != GF_OK) return st;
   if (!(p->theta_switch > 0.0)) return fail(c, GF_ERR_ARG, "gf_fix_mixed: theta_switch must be > 0");
+  if ((p->flags & GF_FLAG_FREEZE_TIMESLICES) && gauge != GF_COULOMB)
+    return fail(c, GF_ERR_ARG, "gf_fix_mixed: GF_FLAG_FREEZE_TIMESLICES needs GF_COULOMB");
   const bool track = (p->flags & GF_FLAG_NO_TRACK) == 0;
   const Lat L = make_lat(g_lo);
   if (track) {
@@ -1263,6 +1341,7 @@ gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
   r->checks = lo.checks + hi.checks;
   r->F = hi.checks ? hi.F : lo.F;
   r->theta = hi.checks ? hi.theta : lo.theta;
+  r->frozen_slice_sweeps = clamp_i32(lo.skipped + hi.skipped);
   r->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (st != GF_OK) {
     r->status = st;
@@ -1609,6 +1688,8 @@ gf_status gf_batch_run(gf_batch* b, const gf_fix_params* p, gf_fix_result* res) 
   if (st != GF_OK) return st;
   if (!(p->theta_switch > 0.0)) return fail(c, GF_ERR_ARG, "gf_batch_run: theta_switch must be > 0");
   if (p->or_form != 0) return fail(c, GF_ERR_UNSUPPORTED, "gf_batch_run: or_form must be 0");
+  if (p->flags & GF_FLAG_FREEZE_TIMESLICES)
+    return fail(c, GF_ERR_UNSUPPORTED, "gf_batch_run: GF_FLAG_FREEZE_TIMESLICES (batches are Landau)");
   const int n = b->n;
   for (int l = 0; l < n; ++l) init_result(&res[l]);
   const auto t0 = std::chrono::steady_clock::now();

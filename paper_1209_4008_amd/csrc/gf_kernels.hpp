@@ -374,16 +374,23 @@ __device__ __forceinline__ void lane_sum(Su3<T>& K) {
 // field Gx (6 complex = rows 0, 1 per site, tiled like the links with one
 // direction), g(x) <- Gtot g(x); lane 0
 // of the site does it. gid = TPS * h + lane.
+// tmask (Coulomb only, may be NULL): one byte per timeslice; the sites of a
+// timeslice whose byte is 0 are left alone. Coulomb gauge splits into one
+// problem per timeslice (its functional and theta involve spatial links
+// only), so a converged timeslice can be frozen while the others go on.
 template <typename T, int NC, int GAUGE, class Upd, int TPS, int NT, bool TRACK>
 __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const Lat& L,
                                                  const int parity, const Upd& upd,
-                                                 v2<T>* __restrict__ Gx, const uint32_t gid) {
+                                                 v2<T>* __restrict__ Gx, const uint32_t gid,
+                                                 const uint8_t* __restrict__ tmask) {
   static_assert(TPS == 1 || TPS == 2 || TPS == 4, "lanes per site");
   constexpr int DPL = 4 / TPS;  // directions per lane
   const uint32_t h = gid / TPS;
   const int r = (int)(gid % TPS);
   if (h >= L.vh) return;  // a site's lanes are all in range or all out
   const Site S = site_of(L, h, parity);
+  if constexpr (GAUGE == kCoulomb)
+    if (tmask != nullptr && tmask[S.t] == 0) return;  // all lanes of the site agree
   uint32_t hb[DPL];
   Su3<T> Uf[DPL], Ub[DPL];
 #pragma unroll
@@ -468,9 +475,10 @@ struct SweepWaves {
 template <typename T, int NC, int GAUGE, class Upd, int TPS, int NT, bool TRACK = false>
 __global__ __launch_bounds__(kBlock, (SweepWaves<T, TPS>::value)) void k_update_half(v2<T>* __restrict__ U, const Lat L,
                                                         const int parity, const Upd upd,
-                                                        v2<T>* __restrict__ Gx = nullptr) {
+                                                        v2<T>* __restrict__ Gx = nullptr,
+                                                        const uint8_t* __restrict__ tmask = nullptr) {
   site_half_update<T, NC, GAUGE, Upd, TPS, NT, TRACK>(U, L, parity, upd, Gx,
-                                                      blockIdx.x * kBlock + threadIdx.x);
+                                                      blockIdx.x * kBlock + threadIdx.x, tmask);
 }
 
 // ---------------------------------------------------------------------------
@@ -763,7 +771,7 @@ __global__ __launch_bounds__(kBlock) void k_update_half_batch(const BatchEntry<T
   const BatchEntry<T> e = tab[l];
   site_half_update<T, NC, kLandau, Upd, TPS, NT, TRACK>(
       e.U, e.L, parity, for_lattice(upd, e.index), e.Gx,
-      (blockIdx.x - e.first_block) * kBlock + threadIdx.x);
+      (blockIdx.x - e.first_block) * kBlock + threadIdx.x, nullptr);
 }
 
 // ---------------------------------------------------------------------------

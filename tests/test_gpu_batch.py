@@ -88,3 +88,11 @@ def test_batch_rejects_bad_input(ctx):
     f3, g3 = upload(ctx, U, gf.FP32, gf.R12)
     with pytest.raises(gf.GFError):
         gf.Batch(ctx, [g3], [f3])  # not FP64
+    b = gf.Batch(ctx, [g], [f])
+    try:
+        with pytest.raises(gf.GFError) as e:
+            b.run(gf.fix_params(omega=1.7, theta_target=1e-12, theta_switch=1e-6, max_sweeps=10,
+                                check_every=5, flags=gf.FLAG_FREEZE_TIMESLICES))
+        assert e.value.status == gf.ERR_UNSUPPORTED
+    finally:
+        b.close()

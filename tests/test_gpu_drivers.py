@@ -223,3 +223,59 @@ def test_full_size_sampled_parity(ctx, dims, beta, seed, prec):
     ctx.plaquette(f0, g0, P0)
     ctx.plaquette(f, g, P1)
     assert P1.item() == pytest.approx(P0.item(), abs=1e-12 if prec == gf.FP64 else 1e-5)
+
+
+@pytest.mark.parametrize("storage,flags", [(gf.R18, 0), (gf.R12, 0), (gf.R12, gf.FLAG_GRAPH)])
+def test_fix_coulomb_frozen_matches_oracle(ctx, storage, flags):
+    """Coulomb with converged timeslices frozen: the same check at which each
+    timeslice freezes as the oracle's freezing driver (through the count of
+    frozen timeslice-sweeps), the same sweeps, the same fixed field."""
+    dims = (8, 4, 6, 4)
+    U = inputs.config0(dims, 0.8, 4)
+    say("coulomb frozen", storage, flags)
+    f, g = upload(ctx, U, gf.FP64, storage)
+    p = gf.fix_params(omega=1.7, theta_target=1e-13, max_sweeps=3000, check_every=10,
+                      flags=flags | gf.FLAG_FREEZE_TIMESLICES)
+    r = ctx.fix(f, g, gf.COULOMB, p)
+    ref = oracle_input(U, gf.FP64, storage)
+    ro = O.fix_coulomb_frozen(ref, 1.7, 1e-13, 3000, 10, 1)
+    say(r.as_dict(), ro)
+    assert len(set(ro["frozen_at"].tolist())) > 3  # the timeslices freeze at different checks
+    assert r.status == gf.OK and ro["converged"] and r.sweeps == ro["sweeps"]
+    assert r.frozen_slice_sweeps == int(np.sum(ro["sweeps"] - ro["frozen_at"]))
+    assert r.theta == pytest.approx(ro["theta"].max(), rel=1e-6)
+    assert np.abs(download(ctx, f, g) - ref).max() < 1e-9
+    F, th = ctx.empty_out(dims[0]), ctx.empty_out(dims[0])
+    ctx.measure(f, g, gf.COULOMB, F, th)
+    assert np.allclose(F.cpu().numpy(), ro["F"], rtol=1e-10)
+    assert np.all(th.cpu().numpy() < 1e-13)
+
+
+def test_fix_coulomb_frozen_mixed(ctx):
+    """Freezing in both phases of the mixed driver (FP32 at theta_switch, FP64
+    at the target): every theta_t below the target, F per timeslice equal to
+    the FP64 oracle's, the plaquette unchanged."""
+    dims = (8, 6, 6, 6)
+    U = inputs.config0(dims, 0.3, 1)
+    r, P0, P1, fhi, ghi = _mixed(ctx, U, gf.COULOMB, gf.FLAG_FREEZE_TIMESLICES | gf.FLAG_GRAPH,
+                                 check_every=10)
+    ref = oracle_input(U, gf.FP64, gf.R12)
+    ro = O.fix(ref, gf.COULOMB, 1.7, 1e-14, 4000, 100, 1)
+    say("mixed frozen", r.as_dict())
+    assert r.status == gf.OK and r.theta < 1e-14 and r.frozen_slice_sweeps > 0
+    F, th = ctx.empty_out(dims[0]), ctx.empty_out(dims[0])
+    ctx.measure(fhi, ghi, gf.COULOMB, F, th)
+    assert np.all(th.cpu().numpy() < 1e-14)
+    assert np.allclose(F.cpu().numpy(), O.functional(ref, gf.COULOMB)[1], rtol=1e-10)
+    assert P1 == pytest.approx(P0, abs=1e-13)
+
+
+def test_fix_freeze_flag_errors(ctx):
+    U = inputs.config0((4, 4, 4, 4), 0.3, 1)
+    f, g = upload(ctx, U, gf.FP64, gf.R12)
+    p = gf.fix_params(omega=1.7, theta_target=1e-12, max_sweeps=10, check_every=5,
+                      flags=gf.FLAG_FREEZE_TIMESLICES)
+    for gauge in (gf.LANDAU, gf.MAG):
+        with pytest.raises(gf.GFError) as e:
+            ctx.fix(f, g, gauge, p)
+        assert e.value.status == gf.ERR_ARG
