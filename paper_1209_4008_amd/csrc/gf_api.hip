@@ -388,7 +388,9 @@ static int default_tps(const gf_geom* g) { return g->prec == GF_FP64 ? 4 : 2; }
 // variants timed by the autotuner: lanes per site 1, 2, 4 x nontemporal mode
 // kNTNone, kNTAll, kNTStores, index 3 * mode + log2(lanes)
 constexpr int kVariants = 9;
-static int default_nt(const gf_geom* g) { return g->prec == GF_FP64 ? 1 : 0; }
+// ordinary (cached) accesses: with the alternating sweep direction the
+// Infinity Cache serves the start of every half-sweep
+static int default_nt(const gf_geom*) { return kNTNone; }
 
 // the stores-only nontemporal mode is instantiated for the overrelaxation
 // sweeps (all forms of g^omega and stochastic relaxation: the same

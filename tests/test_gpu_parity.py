@@ -246,7 +246,7 @@ def test_autotune_choice_and_parity_after(ctx, prec, storage):
         assert set(table) == {(t, n) for t in (1, 2, 4) for n in (0, 1, 2)}
         assert all(v > 0 for v in table.values())
         assert table[(tps, nt)] <= 1.03 * min(table.values())
-        default = (4, 1) if prec == gf.FP64 else (2, 0)
+        default = (4, 0) if prec == gf.FP64 else (2, 0)
         if table[default] <= 1.03 * min(table.values()):
             assert (tps, nt) == default
         assert ctx.get_sweep_variant(prec, storage) == (tps, nt)
