@@ -279,3 +279,29 @@ def test_fix_freeze_flag_errors(ctx):
         with pytest.raises(gf.GFError) as e:
             ctx.fix(f, g, gauge, p)
         assert e.value.status == gf.ERR_ARG
+
+
+def test_fix_coulomb_frozen_partial_and_trivial(ctx):
+    """Stopped at max_sweeps with some timeslices frozen: the same state as
+    the oracle's freezing driver; an input that is already fixed freezes every
+    timeslice at the first check and sweeps nothing."""
+    dims = (8, 4, 6, 4)
+    U = inputs.config0(dims, 0.8, 4)
+    f, g = upload(ctx, U, gf.FP64, gf.R12)
+    p = gf.fix_params(omega=1.7, theta_target=1e-13, max_sweeps=350, check_every=10,
+                      flags=gf.FLAG_FREEZE_TIMESLICES | gf.FLAG_GRAPH)
+    r = ctx.fix(f, g, gf.COULOMB, p)
+    ref = oracle_input(U, gf.FP64, gf.R12)
+    ro = O.fix_coulomb_frozen(ref, 1.7, 1e-13, 350, 10, 1)
+    fa = ro["frozen_at"]
+    assert not ro["converged"] and np.any(fa >= 0) and np.any(fa < 0)
+    assert r.status == gf.NOT_CONVERGED and r.sweeps == 350
+    assert r.frozen_slice_sweeps == int(np.sum(np.where(fa >= 0, 350 - fa, 0)))
+    assert np.abs(download(ctx, f, g) - ref).max() < 1e-9
+    # already fixed: the result of the run above, continued to convergence
+    p.max_sweeps = 3000
+    ctx.fix(f, g, gf.COULOMB, p)
+    before = download(ctx, f, g)
+    r2 = ctx.fix(f, g, gf.COULOMB, p)
+    assert r2.status == gf.OK and r2.sweeps == 0 and r2.frozen_slice_sweeps == 0
+    assert np.array_equal(download(ctx, f, g), before)
