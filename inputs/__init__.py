@@ -41,6 +41,8 @@ def lib():
                                           C.c_void_p]),
             "gen_gpu_haar_copy": (C.c_int, [C.c_void_p, i32p, C.c_uint64, C.c_uint32,
                                             C.c_void_p]),
+            "gen_gpu_config0_packed": (C.c_int, [C.c_void_p, i32p, C.c_int32, C.c_int32,
+                                                 C.c_double, C.c_uint64, C.c_void_p]),
             "gen_gpu_heatbath_sweep": (C.c_int, [C.c_void_p, i32p, C.c_double, C.c_uint64,
                                                  C.c_uint32, C.c_void_p]),
         }
@@ -178,6 +180,17 @@ def gpu_config0(dims, eps=0.3, seed=1):
     _check(lib().gen_gpu_config0(C.c_void_p(U.data_ptr()), _dims(dims), float(eps), int(seed),
                                  _stream_ptr(torch)), "gen_gpu_config0")
     return U
+
+
+def gpu_config0_packed(F, dims, prec_bytes, nc, eps=0.3, seed=1):
+    """gpu_config0's links, rounded to float (prec_bytes 4) or double (8), written
+    into the gauge-fixing library's tiled device layout with nc = 6 (rows 0 and
+    1) or 9 complex per link; F is a CUDA tensor of the field's size in bytes."""
+    import torch
+    _check(lib().gen_gpu_config0_packed(C.c_void_p(F.data_ptr()), _dims(dims), int(prec_bytes),
+                                        int(nc), float(eps), int(seed), _stream_ptr(torch)),
+           "gen_gpu_config0_packed")
+    return F
 
 
 def gpu_haar_copy(U, dims, seed, copy):

@@ -368,6 +368,40 @@ __global__ void k_haar_copy(double* U, Lat L, uint64_t seed, uint32_t copy) {
   }
 }
 
+// config-0 links written straight into the gauge-fixing library's device
+// layout (its public header documents it), for lattices whose canonical FP64
+// form would not fit in device memory: complex element (p, mu, c, h) at
+//   p*4*nc*vp + (h/128)*128*4*nc + (mu*nc + c)*128 + h%128,
+// p = parity of the site, h = s >> 1, c = 3a + b < nc (nc = 6: rows 0 and 1;
+// nc = 9: all rows), vp = V/2 rounded up to a multiple of 128; T = float or
+// double, re and im interleaved. The link values are those of k_config0,
+// rounded to T.
+template <typename T>
+__device__ void config0_packed_link(T* F, const Lat& L, int nc, int64_t vp, double eps,
+                                    uint64_t seed, int64_t l) {
+  const int64_t s = l >> 2;
+  const int mu = (int)(l & 3);
+  const m3 A = config0_link(seed, L, s, mu, eps);
+  int64_t c4[4];
+  coords(L, s, c4);
+  const int64_t p = (c4[0] + c4[1] + c4[2] + c4[3]) & 1;
+  const int64_t h = s >> 1;
+  const int64_t base = p * 4 * nc * vp + (h / 128) * 128 * 4 * nc + (int64_t)mu * nc * 128 + h % 128;
+  for (int c = 0; c < nc; ++c) {
+    T* q = F + 2 * (base + (int64_t)c * 128);
+    q[0] = (T)A.e[c / 3][c % 3].re;
+    q[1] = (T)A.e[c / 3][c % 3].im;
+  }
+}
+
+// Grid-stride over the 4V links: a launch holds fewer than 2^32 work-items.
+template <typename T>
+__global__ void k_config0_packed(T* F, Lat L, int nc, int64_t vp, double eps, uint64_t seed) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < 4 * L.V; l += stride)
+    config0_packed_link(F, L, nc, vp, eps, seed, l);
+}
+
 // one heatbath phase: links U_mu(x) with x of the given parity (their staples
 // only involve links that this phase does not change)
 __global__ void k_heatbath(double* U, Lat L, int mu, int par, double beta, uint64_t seed,
@@ -485,6 +519,27 @@ int gen_gpu_config0(double* U, const int32_t dims[4], double eps, uint64_t seed,
   clear_stale_error();
   hipLaunchKernelGGL(k_config0, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      (hipStream_t)stream, U, L, eps, seed);
+  return launch_status();
+}
+
+// prec_bytes 4 (float) or 8 (double); nc 6 or 9; F holds 8 * vp * 2*nc * prec_bytes bytes
+int gen_gpu_config0_packed(void* F, const int32_t dims[4], int32_t prec_bytes, int32_t nc,
+                           double eps, uint64_t seed, void* stream) {
+  if (!F || !dims_ok(dims) || (prec_bytes != 4 && prec_bytes != 8) || (nc != 6 && nc != 9))
+    return -1;
+  const Lat L = make_lat(dims);
+  if (L.V > ((int64_t)1 << 30)) return -1;
+  const int64_t vp = (L.V / 2 + 127) / 128 * 128;
+  const int64_t n = 4 * L.V;
+  const int64_t want = (n + 255) / 256;
+  const unsigned blocks = (unsigned)(want < (1 << 20) ? want : (1 << 20));
+  clear_stale_error();
+  if (prec_bytes == 4)
+    hipLaunchKernelGGL(k_config0_packed<float>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (float*)F, L, (int)nc, vp, eps, seed);
+  else
+    hipLaunchKernelGGL(k_config0_packed<double>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (double*)F, L, (int)nc, vp, eps, seed);
   return launch_status();
 }
 
