@@ -625,6 +625,15 @@ def main():
         cpu = cpu_baseline(canon, dims, args)
         if not args.no_extras:
             extras.update(cpu_extras(canon, dims, args, ctx, torch, gf))
+            if "fp64_only" in extras and cpu and cpu.get("value"):
+                # a full FP64 oracle fix of this input would take too long to
+                # run; its time follows from the GPU run's sweep count (the same
+                # sequence of sweeps) and the oracle's measured rate
+                n = extras["fp64_only"]["sweeps"]
+                extras["oracle_fp64_time_to_theta_extrapolated"] = {
+                    "s": round(V * n / cpu["value"], 1), "sweeps": n,
+                    "basis": "FP64 sweeps of the GPU's pure-FP64 run x V / the oracle's "
+                             "site-updates/s on %d host threads (extrapolated, not run)" % cpu["cores"]}
 
     out = {
         "metric": "Landau OR site-updates/s, HBM GB/s %peak; mixed vs FP64 time-to-theta<1e-14",
