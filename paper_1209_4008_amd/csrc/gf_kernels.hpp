@@ -178,10 +178,75 @@ constexpr uint32_t kTagKP = 0x1000u;
 constexpr uint32_t kTagDir = 0x1100u;
 constexpr uint32_t kMaxAttempts = 1024u;
 
+// The first trial and the direction of each subgroup's draw do not depend on
+// the links: a site's heatbath step can draw them before its links arrive, so
+// that the Philox rounds and transcendentals overlap the loads. num = the
+// trial's -(log u0 + cos^2(2 pi u1) log u2), to be divided by 2 alpha.
+template <typename T>
+struct HBDraws {
+  T num[3], u3[3], cth[3], sth[3], cph[3], sph[3];
+};
+
 template <typename T>
 struct UpdHB {
   T temp;
   uint32_t k0, k1, sweep;
+  __device__ __forceinline__ HBDraws<T> draws(uint32_t site) const {
+    const T two_pi = (T)6.283185307179586476925286766559;
+    HBDraws<T> d;
+#pragma unroll
+    for (int sg = 0; sg < 3; ++sg) {
+      const U4 r = philox4x32_10(site, sweep, kTagKP | (uint32_t)sg, 0u, k0, k1);
+      const T u0 = unit_open<T>(r.v[0]), u1 = unit_open<T>(r.v[1]);
+      const T u2 = unit_open<T>(r.v[2]);
+      const T cs = hb_cos(two_pi * u1);
+      d.num[sg] = -(hb_log(u0) + cs * cs * hb_log(u2));
+      d.u3[sg] = unit_open<T>(r.v[3]);
+      const U4 q = philox4x32_10(site, sweep, kTagDir | (uint32_t)sg, 0u, k0, k1);
+      const T d0 = unit_open<T>(q.v[0]), d1 = unit_open<T>(q.v[1]);
+      d.cth[sg] = 2 * d0 - 1;
+      d.sth[sg] = sqrt_t(fmax(T(0), 1 - d.cth[sg] * d.cth[sg]));
+      const T phi = two_pi * d1;
+      d.cph[sg] = hb_cos(phi);
+      d.sph[sg] = hb_sin(phi);
+    }
+    return d;
+  }
+  // the step with the first trial and the direction taken from d (the same
+  // numbers operator() draws, combined in the same order)
+  __device__ __forceinline__ bool with_draws(const T w[4], uint32_t site, int sg, T s[4],
+                                             const HBDraws<T>& d) const {
+    const T n2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+    if (!(n2 > Tiny<T>::value)) return false;
+    const T n = sqrt_t(n2);
+    const T alpha = n / temp;
+    const T two_pi = (T)6.283185307179586476925286766559;
+    T lam2 = -1;
+    {
+      const T l2 = d.num[sg] / (2 * alpha);
+      if (d.u3[sg] * d.u3[sg] <= 1 - l2) lam2 = l2;
+    }
+    for (uint32_t att = 1; lam2 < 0 && att < kMaxAttempts; ++att) {
+      const U4 r = philox4x32_10(site, sweep, kTagKP | (uint32_t)sg, att, k0, k1);
+      const T u0 = unit_open<T>(r.v[0]), u1 = unit_open<T>(r.v[1]);
+      const T u2 = unit_open<T>(r.v[2]), u3 = unit_open<T>(r.v[3]);
+      const T cs = hb_cos(two_pi * u1);
+      const T l2 = -(hb_log(u0) + cs * cs * hb_log(u2)) / (2 * alpha);
+      if (u3 * u3 <= 1 - l2) lam2 = l2;
+    }
+    if (lam2 < 0) return false;  // attempt cap: subgroup left unchanged
+    const T rad = 2 * sqrt_t(lam2 * (1 - lam2));
+    const T X[4] = {1 - 2 * lam2, rad * d.sth[sg] * d.cph[sg], rad * d.sth[sg] * d.sph[sg],
+                    rad * d.cth[sg]};
+    const T wh[4] = {w[0] / n, w[1] / n, w[2] / n, w[3] / n};
+    qmul(X, wh, s);
+    const T rn = rsqrt_t(s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + s[3] * s[3]);
+    s[0] *= rn;
+    s[1] *= rn;
+    s[2] *= rn;
+    s[3] *= rn;
+    return true;
+  }
   __device__ __forceinline__ bool operator()(const T w[4], uint32_t site, int sg, T s[4]) const {
     const T n2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
     if (!(n2 > Tiny<T>::value)) return false;
@@ -291,14 +356,35 @@ __device__ __forceinline__ void subgroup_step(Su3<T>& K, Su3<T>& G, uint32_t sit
 // drop the products with the zeros of a unit matrix, so the general form
 // would do that work.) A declined step (degenerate subgroup) uses s = 1,
 // whose row operation is exact.
+// draws a site's update can take before its links arrive: the FP32 heatbath's
+// (see HBDraws); none for the other updates
+struct NoDraws {};
+template <class Upd>
+__device__ __forceinline__ NoDraws pre_draws(const Upd&, uint32_t) {
+  return {};
+}
+__device__ __forceinline__ HBDraws<float> pre_draws(const UpdHB<float>& u, uint32_t site) {
+  return u.draws(site);
+}
 template <typename T, class Upd>
-__device__ __forceinline__ void build_G(Su3<T>& K, Su3<T>& G, uint32_t site, const Upd& upd) {
+__device__ __forceinline__ bool call_upd(const Upd& u, const T w[4], uint32_t site, int sg, T s[4],
+                                         const NoDraws&) {
+  return u(w, site, sg, s);
+}
+__device__ __forceinline__ bool call_upd(const UpdHB<float>& u, const float w[4], uint32_t site,
+                                         int sg, float s[4], const HBDraws<float>& d) {
+  return u.with_draws(w, site, sg, s, d);
+}
+
+template <typename T, class Upd, class D = NoDraws>
+__device__ __forceinline__ void build_G(Su3<T>& K, Su3<T>& G, uint32_t site, const Upd& upd,
+                                        const D& dr = D()) {
   T w[4], s[4], t[4];
   subgroup_w<T, 0, 1>(K, w);
-  if (!upd(w, site, 0, s)) s[0] = 1, s[1] = s[2] = s[3] = 0;
+  if (!call_upd(upd, w, site, 0, s, dr)) s[0] = 1, s[1] = s[2] = s[3] = 0;
   left_su2<T, 0, 1>(K, s);
   subgroup_w<T, 0, 2>(K, w);
-  if (!upd(w, site, 1, t)) t[0] = 1, t[1] = t[2] = t[3] = 0;
+  if (!call_upd(upd, w, site, 1, t, dr)) t[0] = 1, t[1] = t[2] = t[3] = 0;
   left_su2<T, 0, 2>(K, t);
   // G2 G1: rows of G1 = (g00, g01, 0), (g10, g11, 0), (0, 0, 1)
   const Cx<T> g00 = cx(s[0], s[3]), g01 = cx(s[2], s[1]);
@@ -315,7 +401,7 @@ __device__ __forceinline__ void build_G(Su3<T>& K, Su3<T>& G, uint32_t site, con
   G.e[2][1] = cmul(t20, g01);
   G.e[2][2] = t22;
   subgroup_w<T, 1, 2>(K, w);
-  if (upd(w, site, 2, s)) left_su2<T, 1, 2>(G, s);
+  if (call_upd(upd, w, site, 2, s, dr)) left_su2<T, 1, 2>(G, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,6 +486,8 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
     load_link<T, NC, NT>(U + link_offset<NC>(L.vp, parity, mu, h), Uf[d]);
     load_link<T, NC, NT>(U + link_offset<NC>(L.vp, 1 - parity, mu, hb[d]), Ub[d]);
   }
+  const uint32_t site = 2 * h + S.xodd;
+  const auto dr = pre_draws(upd, site);  // while the loads are in flight
   Su3<T> K;
   set_zero(K);
 #pragma unroll
@@ -419,9 +507,8 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
       }
   }
   lane_sum<T, TPS>(K);
-  const uint32_t site = 2 * h + S.xodd;
   Su3<T> G;
-  build_G<T, Upd>(K, G, site, upd);
+  build_G<T, Upd>(K, G, site, upd, dr);
   if (TRACK && r == 0) {
     v2<T>* gp = Gx + link_offset<6, 1>(L.vp, parity, 0, h);
     Su3<T> gx, A;
