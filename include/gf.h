@@ -203,7 +203,7 @@ gf_status gf_get_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32
  * 1, 2) on a scratch field (allocated and freed inside the call) that starts as
  * a copy of U_like (a device field of geom; NULL: the unit field), keeps the
  * fastest on this context and returns it (the built-in variant when it is
- * within 3% of the fastest, so that repeated tunings agree). The caller's fields are not
+ * within 5% of the fastest, so that repeated tunings agree). The caller's fields are not
  * modified. ms_out (NULL or 9 floats, index 3*nontemporal + log2(tps))
  * receives the mean time per half-sweep of each. Synchronises the context
  * stream. */

@@ -921,11 +921,12 @@ gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, const void* U_
     c->nt[i64][i18] = saved_nt;
     return st;
   }
-  // variants within run-to-run noise of the fastest: keep the built-in one,
-  // so that repeated tunings settle on the same kernel
+  // variants within 5% of the fastest: keep the built-in one, so that
+  // repeated tunings settle on the same kernel (the scratch field's timings
+  // can differ from the caller's field's by a few percent)
   {
     const int kd = 3 * default_nt(g) + (default_tps(g) == 4 ? 2 : default_tps(g) == 2 ? 1 : 0);
-    if (times[kd] <= 1.03f * best) {
+    if (times[kd] <= 1.05f * best) {
       best_tps = default_tps(g);
       best_nt = default_nt(g);
     }

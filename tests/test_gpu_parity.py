@@ -233,7 +233,7 @@ def test_argument_errors_on_gpu(ctx):
 @pytest.mark.parametrize("prec,storage", [(gf.FP64, gf.R12), (gf.FP32, gf.R12)])
 def test_autotune_choice_and_parity_after(ctx, prec, storage):
     """The autotuner times six variants on a copy of the caller's field, leaves
-    that field untouched, keeps a variant within 3% of the fastest (the
+    that field untouched, keeps a variant within 5% of the fastest (the
     built-in one when it qualifies), and the tuned sweep still matches the
     oracle."""
     dims = (6, 4, 8, 10)
@@ -245,9 +245,9 @@ def test_autotune_choice_and_parity_after(ctx, prec, storage):
         (tps, nt), table = ctx.autotune(g, gf.LANDAU, U_like=f)
         assert set(table) == {(t, n) for t in (1, 2, 4) for n in (0, 1, 2)}
         assert all(v > 0 for v in table.values())
-        assert table[(tps, nt)] <= 1.03 * min(table.values())
+        assert table[(tps, nt)] <= 1.05 * min(table.values())
         default = (4, 0) if prec == gf.FP64 else (2, 0)
-        if table[default] <= 1.03 * min(table.values()):
+        if table[default] <= 1.05 * min(table.values()):
             assert (tps, nt) == default
         assert ctx.get_sweep_variant(prec, storage) == (tps, nt)
         assert np.array_equal(download(ctx, f, g), before)
