@@ -1485,6 +1485,9 @@ gf_status upload_table(gf_batch* b, int k, const TableSet<T>& t, const BatchEntr
     b->tab_cap = 4 * one;
   }
   char* p = (char*)b->d_tab + (size_t)k * one;
+  // kernels still queued on the context stream may read this slot (the
+  // context stream need not be the null stream that hipMemcpy orders with)
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   HIP_OR_FAIL(c, hipMemcpy(p, t.h.data(), t.h.size() * sizeof(BatchEntry<T>), hipMemcpyHostToDevice));
   *dev = (const BatchEntry<T>*)p;
   return GF_OK;
