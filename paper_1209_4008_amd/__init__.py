@@ -117,7 +117,7 @@ _lib = None
 
 
 def lib():
-    """Load libgf.so (built by __graft_entry__.build() / paper_1209_4008_amd/build.py)."""
+    """Load libgf.so (built by paper_1209_4008_amd/build.py)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
