@@ -96,3 +96,36 @@ def test_batch_rejects_bad_input(ctx):
         assert e.value.status == gf.ERR_UNSUPPORTED
     finally:
         b.close()
+
+
+def test_batch_on_a_side_stream(ctx):
+    """A context on a torch side stream (non-blocking with respect to the null
+    stream) gives the same bits as one on the current stream: annealing, both
+    phases and the lattice tables rewritten between them."""
+    import torch
+    Us = _inputs()
+    p = gf.fix_params(omega=1.7, theta_target=1e-13, theta_switch=1e-6, max_sweeps=4000,
+                      check_every=25, sa_steps=30, sa_micro=2, sa_T0=1.2, sa_T1=0.02,
+                      seed=23, flags=gf.FLAG_GRAPH)
+    outs = []
+    side = torch.cuda.Stream()
+    for c, s in ((ctx, None), (None, side)):
+        own = c is None
+        if own:
+            c = gf.Context(stream=s)
+        fields, geoms = [], []
+        for U in Us:
+            f, g = upload(c, U, gf.FP64, gf.R12)
+            torch.cuda.synchronize()  # the staging tensor was allocated on the current stream
+            fields.append(f)
+            geoms.append(g)
+        b = gf.Batch(c, geoms, fields)
+        res = b.run(p)
+        b.close()
+        torch.cuda.synchronize()
+        outs.append(([r.sweeps for r in res], [download(c, f, g) for f, g in zip(fields, geoms)]))
+        if own:
+            c.close()
+    assert outs[0][0] == outs[1][0]
+    for a, b2 in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b2)
