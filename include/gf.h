@@ -305,7 +305,11 @@ gf_status gf_fix_mixed(gf_ctx* ctx, void* U_lo, const gf_geom* geom_lo, void* U_
  * U: n caller-owned FP64 device fields, borrowed until gf_batch_destroy;
  * they hold the inputs and receive the results. The batch allocates its FP32
  * 12-real working fields and FP32 gauge-transformation fields (192 + 48 bytes
- * per site, padded sites included) at creation. Coulomb batches are GF_ERR_UNSUPPORTED. */
+ * per site, padded sites included) at creation. Coulomb batches are GF_ERR_UNSUPPORTED.
+ * Sweep variant: the context's (gf_set_sweep_variant, gf_autotune); with none
+ * set, the built-in lanes per site, and link accesses streamed (nontemporal 1)
+ * when the batch's fields of the phase's precision total more than 2 GiB
+ * (cached otherwise). */
 typedef struct gf_batch gf_batch;
 gf_status gf_batch_create(gf_ctx* ctx, int32_t n, const gf_geom* geoms, void* const* U,
                           int32_t gauge, gf_batch** out);
