@@ -104,9 +104,9 @@ int or_fix(double* U, const int32_t dims[4], int gauge, double omega, int form,
            int32_t reunit_at_check, int32_t* sweeps_out, double* F_out,
            double* theta_out);
 
-/* Coulomb gauge with each timeslice frozen (no longer swept) from the first
- * check at which its theta_t is below the target; the timeslices are
- * independent problems. F_out, theta_out: nt values each; frozen_at (or NULL):
+/* Coulomb gauge (Sec. 1) with each timeslice frozen (no longer swept) from
+ * the first check at which its theta_t is below the target; the timeslices
+ * are independent problems (a driver the paper does not describe). F_out, theta_out: nt values each; frozen_at (or NULL):
  * per timeslice the sweep count at which it was frozen, -1 if never.
  * Returns 0 when every timeslice is frozen, 1 at max_sweeps, <0 on bad
  * arguments. */

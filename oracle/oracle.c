@@ -828,8 +828,9 @@ int or_fix(double* U, const int32_t dims[4], int gauge, double omega, int form,
   return converged ? 0 : 1;
 }
 
-/* Coulomb gauge with converged timeslices frozen: the timeslices are
- * independent gauge-fixing problems (K, F and theta of a timeslice involve its
+/* Coulomb gauge (Sec. 1: the condition on the spatial components only) with
+ * converged timeslices frozen, a driver the paper does not describe: the
+ * timeslices are independent gauge-fixing problems (K, F and theta of a timeslice involve its
  * spatial links only), so at every check each timeslice whose theta_t is
  * below the target stops being swept; its spatial links then stay as they
  * are, while the temporal links it shares with a timeslice still being swept
