@@ -116,7 +116,7 @@ def variant_rates(ctx, torch, gf, canon, dims, omega, n=100):
                      "GBps": round(gbs, 1), "frac_peak": round(gbs / PEAK_HBM_GBS, 4),
                      "us_per_half_sweep": round(1e3 * ms / (2 * n), 2),
                      "variant": dict(zip(("lanes_per_site", "nontemporal"),
-                                         ctx.get_sweep_variant(prec, st)))}
+                                         ctx.sweep_variant_for(g)))}
         del f
     return var
 
@@ -583,7 +583,7 @@ def main():
     per_launch_bytes = (V // 2) * bytes_per_site[dom]
     avg_ms = kms[dom] / max(kn[dom], 1)
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-    tps, nt = ctx.get_sweep_variant(gf.FP32 if dom == 0 else gf.FP64, gf.R12)
+    tps, nt = ctx.sweep_variant_for(glo if dom == 0 else ghi)
     kname = "k_update_half<%s,6,0,UpdOR,%d,%d,%s>" % (
         "float" if dom == 0 else "double", tps, nt, "true" if dom == 0 else "false")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,

@@ -193,10 +193,18 @@ gf_status gf_philox(gf_ctx* ctx, const uint32_t* ctr_dev, uint64_t seed, uint32_
  * pays when the cache holds part of the field between half-sweeps; the
  * overrelaxation and stochastic-relaxation sweeps, the annealing updates run
  * 2 as 1).
- * tps = 0 / nontemporal = -1 restore the built-in defaults. */
+ * tps = 0 / nontemporal = -1 restore the built-in defaults: 4 lanes (FP64) or
+ * 2 (FP32); nontemporal 0 for fields of at most 2 GiB (the Infinity Cache
+ * then serves part of every half-sweep), 1 for larger ones. */
 gf_status gf_set_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t tps,
                                int32_t nontemporal);
+/* The variant set for (prec, storage), or the built-in one for a field of at
+ * most 2 GiB. */
 gf_status gf_get_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t* tps,
+                               int32_t* nontemporal);
+/* The variant the sweeps of `geom`'s field use on this context (the set one,
+ * else the built-in one for the field's size). */
+gf_status gf_sweep_variant_for(gf_ctx* ctx, const gf_geom* geom, int32_t* tps,
                                int32_t* nontemporal);
 /* Autotuner: times the overrelaxation half-sweep for geom (its extents,
  * precision and storage) for the nine variants (tps 1, 2, 4) x (nontemporal 0,
@@ -307,9 +315,8 @@ gf_status gf_fix_mixed(gf_ctx* ctx, void* U_lo, const gf_geom* geom_lo, void* U_
  * 12-real working fields and FP32 gauge-transformation fields (192 + 48 bytes
  * per site, padded sites included) at creation. Coulomb batches are GF_ERR_UNSUPPORTED.
  * Sweep variant: the context's (gf_set_sweep_variant, gf_autotune); with none
- * set, the built-in lanes per site, and link accesses streamed (nontemporal 1)
- * when the batch's fields of the phase's precision total more than 2 GiB
- * (cached otherwise). */
+ * set, the built-in one for the total size of the batch's fields of the
+ * phase's precision (see gf_set_sweep_variant). */
 typedef struct gf_batch gf_batch;
 gf_status gf_batch_create(gf_ctx* ctx, int32_t n, const gf_geom* geoms, void* const* U,
                           int32_t gauge, gf_batch** out);

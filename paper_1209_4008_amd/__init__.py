@@ -100,6 +100,7 @@ SIGNATURES = {
     "gf_set_sweep_variant": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "gf_get_sweep_variant": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int32)]),
+    "gf_sweep_variant_for": (C.c_int32, [_vp, _gp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "gf_autotune": (C.c_int32, [_vp, _gp, C.c_int32, _dp, C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "gf_stream_probe": (C.c_int32, [_vp, _dp, _dp, C.c_size_t, C.c_int32]),
@@ -252,6 +253,11 @@ class Context:
         t, n = C.c_int32(0), C.c_int32(0)
         self._check(lib().gf_get_sweep_variant(self.h, int(prec), int(storage), C.byref(t),
                                                C.byref(n)))
+        return t.value, n.value
+
+    def sweep_variant_for(self, geom):
+        t, n = C.c_int32(0), C.c_int32(0)
+        self._check(lib().gf_sweep_variant_for(self.h, C.byref(geom), C.byref(t), C.byref(n)))
         return t.value, n.value
 
     def autotune(self, geom, gauge=LANDAU, U_like=None):

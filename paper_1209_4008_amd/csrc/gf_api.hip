@@ -388,9 +388,16 @@ static int default_tps(const gf_geom* g) { return g->prec == GF_FP64 ? 4 : 2; }
 // variants timed by the autotuner: lanes per site 1, 2, 4 x nontemporal mode
 // kNTNone, kNTAll, kNTStores, index 3 * mode + log2(lanes)
 constexpr int kVariants = 9;
-// ordinary (cached) accesses: with the alternating sweep direction the
-// Infinity Cache serves the start of every half-sweep
-static int default_nt(const gf_geom*) { return kNTNone; }
+// Built-in nontemporal mode: ordinary (cached) accesses, with which the
+// alternating sweep direction lets the Infinity Cache serve the start of
+// every half-sweep. Fields many times larger than the 256 MB cache gain
+// nothing from it, and over several GB streamed accesses run faster (FP64
+// 12-real, 4 lanes: 56^4, 3.8 GB, 5.2 against 4.9 TB/s; 64^4, 6.4 GB, 5.5
+// against 5.3; 72^4, 10.3 GB, 5.1 against 4.5; at 48^4, 2 GB, the modes are
+// within 2%), so above 2 GiB the built-in mode streams loads and stores.
+constexpr size_t kStreamBytes = (size_t)2 << 30;
+static int default_nt_bytes(size_t bytes) { return bytes > kStreamBytes ? kNTAll : kNTNone; }
+static int default_nt(const gf_geom* g) { return default_nt_bytes(gf_field_bytes(g)); }
 
 // the stores-only nontemporal mode is instantiated for the overrelaxation
 // sweeps (all forms of g^omega and stochastic relaxation: the same
@@ -850,6 +857,15 @@ gf_status gf_set_sweep_variant(gf_ctx* c, int32_t prec, int32_t storage, int32_t
     return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: nontemporal must be -1, 0, 1 or 2");
   c->tps[prec == GF_FP64][storage == GF_R18] = tps;
   c->nt[prec == GF_FP64][storage == GF_R18] = nontemporal;
+  return GF_OK;
+}
+
+gf_status gf_sweep_variant_for(gf_ctx* c, const gf_geom* g, int32_t* tps, int32_t* nontemporal) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_sweep_variant_for");
+  if (!tps || !nontemporal) return fail(c, GF_ERR_ARG, "gf_sweep_variant_for: NULL pointer");
+  *tps = ctx_tps(c, g);
+  *nontemporal = ctx_nt(c, g);
   return GF_OK;
 }
 
@@ -1379,21 +1395,16 @@ struct gf_batch {
 
 namespace {
 
-// A batch sweeps all its fields in every launch. Fields many times larger
-// than the 256 MB Infinity Cache gain nothing from it, and over several GB
-// streamed accesses run faster (the 192-lattice batch, 10.8 GB in FP64
-// 12-real: 5.25 against 4.73 TB/s; single FP64 lattices, 4 lanes: 72^4, 10.3
-// GB, 5.1 against 4.5 TB/s, while at 48^4, 2 GB, the modes are within 2%).
-// So with no variant set on the context a batch whose fields total more than
-// 2 GiB streams its link accesses.
-constexpr size_t kBatchStreamBytes = (size_t)2 << 30;
+// A batch sweeps all its fields in every launch, so with no variant set on
+// the context its built-in mode follows their total size (the 192-lattice
+// batch, 10.8 GB in FP64 12-real: streamed 5.25 against cached 4.73 TB/s).
 int batch_nt(const gf_ctx* c, const gf_batch* b, bool lo) {
   const std::vector<gf_geom>& gs = lo ? b->g32 : b->g64;
   const int t = c->nt[gs[0].prec == GF_FP64][gs[0].storage == GF_R18];
   if (t >= 0) return t;
   size_t total = 0;
   for (const gf_geom& g : gs) total += gf_field_bytes(&g);
-  return total > kBatchStreamBytes ? kNTAll : kNTNone;
+  return default_nt_bytes(total);
 }
 
 template <typename T>
