@@ -124,7 +124,7 @@ def variant_rates(ctx, torch, gf, canon, dims, omega, n=100):
 def hbm_traffic(kname, dims):
     """HBM bytes per launch of kname from the committed counter summary, or None
     when there is none for this lattice or the kernel sources changed since."""
-    from paper_1209_4008_amd import prof_summary
+    import prof_summary
 
     path = os.path.join(ROOT, "profiles", "sweep_hbm_counters_%s.md" % "x".join(map(str, dims)))
     data = prof_summary.load_counters(path)

@@ -1,0 +1,408 @@
+// gf_core.hip -- libgf context, layout conversion, reductions, tuning and
+// bandwidth probes.
+#include "gf_host.hpp"
+
+char g_create_err[512] = "no error";
+
+// ---------------------------------------------------------------------------
+// C ABI (C linkage comes from the declarations in gf.h)
+// ---------------------------------------------------------------------------
+
+const char* gf_version(void) { return "libgf 0.1 (gfx950)"; }
+
+gf_status gf_check_geom(const gf_geom* geom) { return geom_ok(geom) ? GF_OK : GF_ERR_ARG; }
+
+size_t gf_field_bytes(const gf_geom* geom) {
+  if (!geom_ok(geom)) return 0;
+  const uint64_t V = (uint64_t)geom->nt * geom->nz * geom->ny * geom->nx;
+  return (size_t)(8 * padded_half(V / 2) * (uint64_t)geom->storage * (uint64_t)geom->prec);
+}
+
+// The device index arithmetic (site_of, back_h, fwd_h) run on the host for
+// every site of a set of lattices, against the canonical definition
+// s = ((t*nz + z)*ny + y)*nx + x, parity (t+x+y+z) mod 2, h = s >> 1.
+static int selftest_lattice(int nt, int nz, int ny, int nx) {
+  gf_geom g = {nt, nz, ny, nx, GF_FP64, GF_R18};
+  const Lat L = make_lat(&g);
+  auto canon = [&](int64_t t, int64_t z, int64_t y, int64_t x) {
+    return ((t * nz + z) * ny + y) * nx + x;
+  };
+  for (int p = 0; p < 2; ++p)
+    for (uint32_t h = 0; h < L.vh; ++h) {
+      const Site S = site_of(L, h, p);
+      if (S.t >= (uint32_t)nt || S.z >= (uint32_t)nz || S.y >= (uint32_t)ny || S.x >= (uint32_t)nx)
+        return 0;
+      const int64_t s = canon(S.t, S.z, S.y, S.x);
+      if ((s >> 1) != h || (int)((S.t + S.z + S.y + S.x) & 1) != p || S.xodd != (S.x & 1)) return 0;
+      const int64_t c[4] = {S.t, S.x, S.y, S.z};
+      const int64_t e[4] = {nt, nx, ny, nz};
+      for (int mu = 0; mu < 4; ++mu) {
+        int64_t b[4] = {c[0], c[1], c[2], c[3]}, f[4] = {c[0], c[1], c[2], c[3]};
+        b[mu] = (b[mu] - 1 + e[mu]) % e[mu];
+        f[mu] = (f[mu] + 1) % e[mu];
+        const uint32_t hb = back_h(L, h, S, mu), hf = fwd_h(L, h, S, mu);
+        if (hb >= L.vh || hf >= L.vh) return 0;
+        if ((uint64_t)(canon(b[0], b[3], b[2], b[1]) >> 1) != hb) return 0;
+        if ((uint64_t)(canon(f[0], f[3], f[2], f[1]) >> 1) != hf) return 0;
+      }
+    }
+  // the tiled element offsets of every (parity, direction, component, site)
+  // are distinct and lie inside the field of 8 * NC * vp elements; the same
+  // for the one-matrix-per-site fields (2 * 6 * vp elements)
+  if (L.vp % kTile != 0 || L.vp < L.vh || L.vp - L.vh >= kTile) return 0;
+  {
+    std::vector<unsigned char> seen((size_t)2 * 6 * L.vp, 0);
+    for (int pp = 0; pp < 2; ++pp)
+      for (uint32_t h = 0; h < L.vh; ++h)
+        for (int cc = 0; cc < 6; ++cc) {
+          const size_t e = link_offset<6, 1>(L.vp, pp, 0, h) + (size_t)cc * kTile;
+          if (e >= seen.size() || seen[e]) return 0;
+          seen[e] = 1;
+        }
+  }
+  for (int NC : {6, 9}) {
+    std::vector<unsigned char> seen((size_t)8 * NC * L.vp, 0);
+    for (uint32_t pm = 0; pm < 8; ++pm)
+      for (uint32_t h = 0; h < L.vh; ++h) {
+        const int pp = (int)(pm >> 2), mu = (int)(pm & 3);
+        const size_t base = NC == 6 ? link_offset<6>(L.vp, pp, mu, h) : link_offset<9>(L.vp, pp, mu, h);
+        for (int cc = 0; cc < NC; ++cc) {
+          const size_t e = base + (size_t)cc * kTile;
+          if (e >= seen.size() || seen[e]) return 0;
+          seen[e] = 1;
+        }
+      }
+  }
+  return 1;
+}
+
+gf_status gf_selftest_host(void) {
+  // exact division for the divisors the geometry can produce
+  for (uint32_t d = 1; d <= 4096; d = d < 64 ? d + 1 : d + 37) {
+    const FastDiv f = make_fastdiv(d);
+    const uint32_t probes[] = {0u, 1u, d - 1, d, d + 1, 2 * d - 1, 1000003u, 0x7ffffffeu,
+                               0x7fffffffu, 123456789u};
+    for (uint32_t n : probes)
+      if (host_fdiv(n, f) != n / d || fdiv(n, f) != n / d) return GF_ERR_UNSUPPORTED;
+    for (uint32_t n = 0; n < 5000; ++n)
+      if (fdiv(n * 7919u, f) != (n * 7919u) / d) return GF_ERR_UNSUPPORTED;
+  }
+  const int shapes[][4] = {{2, 2, 2, 2},     {4, 4, 4, 4},    {6, 4, 2, 10},  {4, 6, 8, 10},
+                           {8, 2, 6, 4},     {2, 12, 2, 14},  {10, 6, 4, 2},  {24, 12, 12, 12},
+                           {2, 2, 2, 65536}, {2, 2, 32768, 4}, {2, 16384, 2, 6}, {32768, 2, 2, 2}};
+  for (const auto& d : shapes)
+    if (!selftest_lattice(d[0], d[1], d[2], d[3])) return GF_ERR_UNSUPPORTED;
+  return GF_OK;
+}
+
+const char* gf_last_error(const gf_ctx* ctx) { return ctx ? ctx->err : g_create_err; }
+
+gf_status gf_create(int device, void* hip_stream, gf_ctx** out) {
+  if (!out) return fail(nullptr, GF_ERR_ARG, "gf_create: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0)
+    return fail(nullptr, GF_ERR_DEVICE, "gf_create: no GPU device available");
+  if (device < 0 || device >= n)
+    return fail(nullptr, GF_ERR_ARG, "gf_create: device %d out of range (%d devices)", device, n);
+  if (hipSetDevice(device) != hipSuccess)
+    return fail(nullptr, GF_ERR_DEVICE, "gf_create: hipSetDevice(%d) failed", device);
+  gf_ctx* c = new gf_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+    delete c;
+    return fail(nullptr, GF_ERR_HIP, "gf_create: hipEventCreate failed");
+  }
+  snprintf(c->err, sizeof c->err, "no error");
+  *out = c;
+  return GF_OK;
+}
+
+gf_status gf_destroy(gf_ctx* c) {
+  if (!c) return GF_ERR_ARG;
+  (void)hipSetDevice(c->device);
+  if (c->partial) (void)hipFree(c->partial);
+  if (c->dev_out) (void)hipFree(c->dev_out);
+  if (c->host_out) (void)hipHostFree(c->host_out);
+  if (c->gbuf) (void)hipFree(c->gbuf);
+  if (c->dev_tmask) (void)hipFree(c->dev_tmask);
+  if (c->host_tmask) (void)hipHostFree(c->host_tmask);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
+  for (auto& e : c->pool) (void)hipEventDestroy(e);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+  return GF_OK;
+}
+
+gf_status gf_pack(gf_ctx* c, const gf_geom* g, const double* src, void* dst) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_pack");
+  if (!src || !dst) return fail(c, GF_ERR_ARG, "gf_pack: NULL pointer");
+  const Lat L = make_lat(g);
+  with_type(g, [&]<typename T, int NC>() {
+    hipLaunchKernelGGL((k_pack<T, NC>), dim3(blocks_for(2ull * L.vh), 4), dim3(kBlock), 0,
+                       c->stream, src, (v2<T>*)dst, L);
+  });
+  return launch_check(c, "gf_pack");
+}
+
+gf_status gf_unpack(gf_ctx* c, const gf_geom* g, const void* src, double* dst) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_unpack");
+  if (!src || !dst) return fail(c, GF_ERR_ARG, "gf_unpack: NULL pointer");
+  const Lat L = make_lat(g);
+  with_type(g, [&]<typename T, int NC>() {
+    hipLaunchKernelGGL((k_unpack<T, NC>), dim3(blocks_for(2ull * L.vh), 4), dim3(kBlock), 0,
+                       c->stream, (const v2<T>*)src, dst, L);
+  });
+  return launch_check(c, "gf_unpack");
+}
+
+template <typename Ts, int NCs>
+static void launch_convert_to(gf_ctx* c, const gf_geom* d, const void* src, void* dst,
+                              const Lat& L, int reunit) {
+  with_type(d, [&]<typename Td, int NCd>() {
+    hipLaunchKernelGGL((k_convert<Ts, NCs, Td, NCd>), dim3(blocks_for(L.vh), 8), dim3(kBlock), 0,
+                       c->stream, (const v2<Ts>*)src, (v2<Td>*)dst, L.vh, L.vp, reunit);
+  });
+}
+
+gf_status gf_convert(gf_ctx* c, const gf_geom* s, const void* src, const gf_geom* d, void* dst,
+                     int32_t reunitarize) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, s, "gf_convert(src)");
+  CHECK_GEOM(c, d, "gf_convert(dst)");
+  if (!same_extents(s, d)) return fail(c, GF_ERR_ARG, "gf_convert: extents differ");
+  if (!src || !dst) return fail(c, GF_ERR_ARG, "gf_convert: NULL pointer");
+  const size_t bs = gf_field_bytes(s), bd = gf_field_bytes(d);
+  const char *ps = (const char*)src, *pd = (const char*)dst;
+  if (ps < pd + bd && pd < ps + bs) return fail(c, GF_ERR_ARG, "gf_convert: buffers overlap");
+  const Lat L = make_lat(s);
+  with_type(s, [&]<typename Ts, int NCs>() {
+    launch_convert_to<Ts, NCs>(c, d, src, dst, L, reunitarize ? 1 : 0);
+  });
+  return launch_check(c, "gf_convert");
+}
+
+gf_status gf_reunitarize(gf_ctx* c, void* U, const gf_geom* g) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_reunitarize");
+  if (!U) return fail(c, GF_ERR_ARG, "gf_reunitarize: NULL pointer");
+  const Lat L = make_lat(g);
+  with_type(g, [&]<typename T, int NC>() {
+    hipLaunchKernelGGL((k_reunitarize<T, NC>), dim3(blocks_for(L.vh), 8), dim3(kBlock), 0,
+                       c->stream, (v2<T>*)U, L.vh, L.vp);
+  });
+  return launch_check(c, "gf_reunitarize");
+}
+
+gf_status measure_impl(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge,
+                              double* F, double* th) {
+  const Lat L = make_lat(g);
+  const uint32_t bpt = blocks_for(L.st);
+  gf_status st = ensure_partial(c, (size_t)2 * bpt * L.nt);
+  if (st != GF_OK) return st;
+  const dim3 grid(bpt, L.nt);
+  with_type(g, [&]<typename T, int NC>() {
+    if (gauge == GF_LANDAU)
+      hipLaunchKernelGGL((k_measure<T, NC, kLandau>), grid, dim3(kBlock), 0, c->stream,
+                         (const v2<T>*)U, L, c->partial);
+    else if (gauge == GF_COULOMB)
+      hipLaunchKernelGGL((k_measure<T, NC, kCoulomb>), grid, dim3(kBlock), 0, c->stream,
+                         (const v2<T>*)U, L, c->partial);
+    else
+      hipLaunchKernelGGL((k_measure_mag<T, NC>), grid, dim3(kBlock), 0, c->stream,
+                         (const v2<T>*)U, L, c->partial);
+  });
+  const double V = 2.0 * L.vh, Vs = V / L.nt;
+  if (gauge != GF_COULOMB)
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial,
+                       bpt * L.nt, 12.0 * V, 3.0 * V, F, th);
+  else
+    hipLaunchKernelGGL(k_finish, dim3(L.nt), dim3(kBlock), 0, c->stream,
+                       (const double*)c->partial, bpt, 9.0 * Vs, 3.0 * Vs, F, th);
+  return launch_check(c, "gf_measure");
+}
+
+gf_status gf_measure(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, double* F,
+                     double* th) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_measure");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB && gauge != GF_MAG)
+    return fail(c, GF_ERR_ARG, "gf_measure: bad gauge");
+  if (!U || (!F && !th)) return fail(c, GF_ERR_ARG, "gf_measure: NULL pointer");
+  return measure_impl(c, U, g, gauge, F, th);
+}
+
+gf_status gf_functional(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, double* F) {
+  if (!F) return fail(c, GF_ERR_ARG, "gf_functional: NULL output");
+  return gf_measure(c, U, g, gauge, F, nullptr);
+}
+
+gf_status gf_theta(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, double* th) {
+  if (!th) return fail(c, GF_ERR_ARG, "gf_theta: NULL output");
+  return gf_measure(c, U, g, gauge, nullptr, th);
+}
+
+gf_status gf_plaquette(gf_ctx* c, const void* U, const gf_geom* g, double* P) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_plaquette");
+  if (!U || !P) return fail(c, GF_ERR_ARG, "gf_plaquette: NULL pointer");
+  const Lat L = make_lat(g);
+  const uint32_t nb = blocks_for(L.vh);
+  gf_status st = ensure_partial(c, (size_t)2 * nb);
+  if (st != GF_OK) return st;
+  with_type(g, [&]<typename T, int NC>() {
+    hipLaunchKernelGGL((k_plaquette<T, NC>), dim3(nb), dim3(kBlock), 0, c->stream,
+                       (const v2<T>*)U, L, c->partial);
+  });
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial, nb,
+                     6.0 * 2.0 * L.vh, 1.0, P, (double*)nullptr);
+  return launch_check(c, "gf_plaquette");
+}
+
+gf_status gf_philox(gf_ctx* c, const uint32_t* ctr, uint64_t seed, uint32_t* out, int64_t n) {
+  CHECK_CTX(c);
+  if (!ctr || !out || n < 0) return fail(c, GF_ERR_ARG, "gf_philox: bad arguments");
+  if (n == 0) return GF_OK;
+  hipLaunchKernelGGL(k_philox, dim3(blocks_for((uint64_t)n)), dim3(kBlock), 0, c->stream, ctr, out,
+                     n, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return launch_check(c, "gf_philox");
+}
+
+// ---------------------------------------------------------------------------
+// tuning
+// ---------------------------------------------------------------------------
+static int tps_ok(int32_t t) { return t == 1 || t == 2 || t == 4; }
+static int ps_ok(int32_t prec, int32_t storage) {
+  return (prec == GF_FP32 || prec == GF_FP64) && (storage == GF_R12 || storage == GF_R18);
+}
+
+gf_status gf_set_sweep_variant(gf_ctx* c, int32_t prec, int32_t storage, int32_t tps,
+                               int32_t nontemporal) {
+  if (!c) return GF_ERR_ARG;
+  if (!ps_ok(prec, storage)) return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: bad precision or storage");
+  if (tps != 0 && !tps_ok(tps)) return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: tps must be 0, 1, 2 or 4");
+  if (nontemporal < -1 || nontemporal > 2)
+    return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: nontemporal must be -1, 0, 1 or 2");
+  c->tps[prec == GF_FP64][storage == GF_R18] = tps;
+  c->nt[prec == GF_FP64][storage == GF_R18] = nontemporal;
+  return GF_OK;
+}
+
+gf_status gf_sweep_variant_for(gf_ctx* c, const gf_geom* g, int32_t* tps, int32_t* nontemporal) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_sweep_variant_for");
+  if (!tps || !nontemporal) return fail(c, GF_ERR_ARG, "gf_sweep_variant_for: NULL pointer");
+  *tps = ctx_tps(c, g);
+  *nontemporal = ctx_nt(c, g);
+  return GF_OK;
+}
+
+gf_status gf_get_sweep_variant(gf_ctx* c, int32_t prec, int32_t storage, int32_t* tps,
+                               int32_t* nontemporal) {
+  if (!c || !tps || !nontemporal) return GF_ERR_ARG;
+  if (!ps_ok(prec, storage)) return fail(c, GF_ERR_ARG, "gf_get_sweep_variant: bad precision or storage");
+  gf_geom g = {2, 2, 2, 2, prec, storage};
+  *tps = ctx_tps(c, &g);
+  *nontemporal = ctx_nt(c, &g);
+  return GF_OK;
+}
+
+gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, const void* U_like,
+                      int32_t* tps_out, int32_t* nt_out, float* ms_out) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_autotune");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB && gauge != GF_MAG)
+    return fail(c, GF_ERR_ARG, "gf_autotune: bad gauge");
+  const size_t bytes = gf_field_bytes(g);
+  void* scratch = nullptr;
+  HIP_OR_FAIL(c, hipMalloc(&scratch, bytes));
+  const Lat L = make_lat(g);
+  if (U_like) {
+    if (hipMemcpyAsync(scratch, U_like, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+      (void)hipFree(scratch);
+      return fail(c, GF_ERR_HIP, "gf_autotune: copy of the sample field failed");
+    }
+  } else {
+    with_type(g, [&]<typename T, int NC>() {
+      hipLaunchKernelGGL((k_fill_unit<T, NC, 4>), dim3(blocks_for(L.vp), 8), dim3(kBlock), 0,
+                         c->stream, (v2<T>*)scratch, L.vp);
+    });
+  }
+  const int reps = 20;
+  float times[kVariants] = {};
+  float best = 1e30f;
+  int best_tps = default_tps(g), best_nt = default_nt(g);
+  const int i64 = g->prec == GF_FP64, i18 = g->storage == GF_R18;
+  const int saved_tps = c->tps[i64][i18], saved_nt = c->nt[i64][i18];
+  gf_status st = GF_OK;
+  for (int k = 0; k < kVariants && st == GF_OK; ++k) {
+    c->tps[i64][i18] = 1 << (k % 3);
+    c->nt[i64][i18] = k / 3;
+    for (int w = 0; w < 2 && st == GF_OK; ++w) st = gf_sweep(c, scratch, g, gauge, w & 1, 1.5);
+    if (st != GF_OK) break;
+    if (hipEventRecord(c->ev[0], c->stream) != hipSuccess) st = GF_ERR_HIP;
+    for (int w = 0; w < 2 * reps && st == GF_OK; ++w) st = gf_sweep(c, scratch, g, gauge, w & 1, 1.5);
+    if (st != GF_OK) break;
+    float ms = 0;
+    if (hipEventRecord(c->ev[1], c->stream) != hipSuccess || hipEventSynchronize(c->ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) != hipSuccess) {
+      st = fail(c, GF_ERR_HIP, "gf_autotune: event timing failed");
+      break;
+    }
+    ms /= (float)(2 * reps);
+    times[k] = ms;
+    if (ms_out) ms_out[k] = ms;
+    if (ms < best) {
+      best = ms;
+      best_tps = 1 << (k % 3);
+      best_nt = k / 3;
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(scratch);
+  if (st != GF_OK) {
+    c->tps[i64][i18] = saved_tps;
+    c->nt[i64][i18] = saved_nt;
+    return st;
+  }
+  // variants within 5% of the fastest: keep the built-in one, so that
+  // repeated tunings settle on the same kernel (the scratch field's timings
+  // can differ from the caller's field's by a few percent)
+  {
+    const int kd = 3 * default_nt(g) + (default_tps(g) == 4 ? 2 : default_tps(g) == 2 ? 1 : 0);
+    if (times[kd] <= 1.05f * best) {
+      best_tps = default_tps(g);
+      best_nt = default_nt(g);
+    }
+  }
+  c->tps[i64][i18] = best_tps;
+  c->nt[i64][i18] = best_nt;
+  if (tps_out) *tps_out = best_tps;
+  if (nt_out) *nt_out = best_nt;
+  return GF_OK;
+}
+
+gf_status gf_stream_probe(gf_ctx* c, const void* src, void* dst, size_t bytes, int32_t kind) {
+  CHECK_CTX(c);
+  if (!dst || (kind != 1 && !src) || (bytes % 16) != 0 || kind < 0 || kind > 2)
+    return fail(c, GF_ERR_ARG, "gf_stream_probe: bad arguments");
+  const size_t n = bytes / 16;
+  if (n == 0) return GF_OK;
+  if (n > ((size_t)1 << 36)) return fail(c, GF_ERR_ARG, "gf_stream_probe: too large");
+  const unsigned grid = blocks_for(n);
+  if (kind == 2 && bytes < (size_t)grid * sizeof(double))
+    return fail(c, GF_ERR_ARG, "gf_stream_probe: dst too small for the partial sums");
+  if (kind == 0)
+    hipLaunchKernelGGL(k_probe_copy, dim3(grid), dim3(kBlock), 0, c->stream, (const double2*)src,
+                       (double2*)dst, n);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_probe_rmw, dim3(grid), dim3(kBlock), 0, c->stream, (v2<double>*)dst, n);
+  else
+    hipLaunchKernelGGL(k_probe_read, dim3(grid), dim3(kBlock), 0, c->stream, (const double2*)src,
+                       (double*)dst, n);
+  return launch_check(c, "gf_stream_probe");
+}

@@ -1086,7 +1086,7 @@ __global__ __launch_bounds__(kBlock) void k_finish_batch(const BatchEntry<T>* __
 }
 
 // one block per output group: sums n_per partial pairs starting at group*n_per
-__global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ partial,
+static __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ partial,
                                                    uint32_t n_per, double norm0, double norm1,
                                                    double* __restrict__ out0,
                                                    double* __restrict__ out1) {
@@ -1334,12 +1334,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_gauge(v2<T>* __restrict__ U,
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_probe_copy(const double2* __restrict__ a,
+static __global__ __launch_bounds__(kBlock) void k_probe_copy(const double2* __restrict__ a,
                                                        double2* __restrict__ b, const size_t n) {
   const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) b[i] = a[i];
 }
-__global__ __launch_bounds__(kBlock) void k_probe_rmw(v2<double>* __restrict__ b, const size_t n) {
+static __global__ __launch_bounds__(kBlock) void k_probe_rmw(v2<double>* __restrict__ b, const size_t n) {
   const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   v2<double> v = __builtin_nontemporal_load(b + i);
@@ -1347,7 +1347,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_rmw(v2<double>* __restrict__ b
   v.y *= 2.0;
   __builtin_nontemporal_store(v, b + i);
 }
-__global__ __launch_bounds__(kBlock) void k_probe_read(const double2* __restrict__ a,
+static __global__ __launch_bounds__(kBlock) void k_probe_read(const double2* __restrict__ a,
                                                        double* __restrict__ out, const size_t n) {
   __shared__ double lds[kBlock / 64];
   const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1357,7 +1357,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_read(const double2* __restrict
   if (threadIdx.x == 0) out[blockIdx.x] = acc;
 }
 
-__global__ __launch_bounds__(kBlock) void k_philox(const uint32_t* __restrict__ ctr,
+static __global__ __launch_bounds__(kBlock) void k_philox(const uint32_t* __restrict__ ctr,
                                                    uint32_t* __restrict__ out, const int64_t n,
                                                    const uint32_t k0, const uint32_t k1) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;

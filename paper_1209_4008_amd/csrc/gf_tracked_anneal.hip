@@ -1,0 +1,34 @@
+// gf_tracked_anneal.hip -- FP32 stochastic-relaxation and annealing
+// half-sweeps with the site transformations accumulated into a
+// gauge-transformation field.
+#include "gf_host.hpp"
+
+gf_status sweep_sr_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32_t gauge,
+                                  int32_t parity, double omega, double prob, uint64_t seed,
+                                  uint64_t sweep) {
+  UpdSR<float> upd;
+  upd.omega = (float)omega;
+  upd.prob = prob;
+  upd.k0 = (uint32_t)seed;
+  upd.k1 = (uint32_t)(seed >> 32);
+  upd.sweep = (uint32_t)sweep;
+  return update_tracked(c, U, Gx, g, gauge, parity, upd, "tracked stochastic relaxation");
+}
+
+// one annealing step on an FP32 field with g tracking
+gf_status anneal_step_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32_t gauge,
+                                     double T, uint64_t seed, uint64_t sweep, int32_t n_micro) {
+  UpdHB<float> hb;
+  hb.temp = (float)T;
+  hb.k0 = (uint32_t)seed;
+  hb.k1 = (uint32_t)(seed >> 32);
+  hb.sweep = (uint32_t)sweep;
+  gf_status st;
+  for (int p = 0; p < 2; ++p)
+    if ((st = update_tracked(c, U, Gx, g, gauge, p, hb, "tracked heatbath")) != GF_OK) return st;
+  UpdMicro<float> mc;
+  for (int k = 0; k < n_micro; ++k)
+    for (int p = 0; p < 2; ++p)
+      if ((st = update_tracked(c, U, Gx, g, gauge, p, mc, "tracked microcanonical")) != GF_OK) return st;
+  return GF_OK;
+}

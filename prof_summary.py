@@ -1,8 +1,9 @@
 """Summaries of rocprofv3 output for the profiles/ folder.
 
-  python -m paper_1209_4008_amd.prof_summary kernels STATS_CSV --command CMD
-  python -m paper_1209_4008_amd.prof_summary counters FETCH_CSV WRITE_CSV --command CMD
+  python prof_summary.py kernels STATS_CSV --command CMD
+  python prof_summary.py counters FETCH_CSV WRITE_CSV --command CMD
 
+Measurement support for bench.py and profiles/, not part of the library.
 `kernels` turns a --kernel-trace --stats kernel_stats.csv into a table of
 calls and average durations. `counters` turns two --pmc runs (FETCH_SIZE, then
 WRITE_SIZE, in KiB per dispatch) of `bench.py --probe` into HBM bytes per
@@ -21,7 +22,7 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/gf_device.hpp", "csrc/gf_kernels.hpp")
+KERNEL_SOURCES = ("paper_1209_4008_amd/csrc/gf_device.hpp", "paper_1209_4008_amd/csrc/gf_kernels.hpp")
 PROBE_BYTES = 2 * 1024 ** 3
 
 
