@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# GF_ORACLE_LIB selects another build of the same source (the sanitizer build
+# that a CPU test runs the pins under)
+LIB_PATH = os.environ.get("GF_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 LANDAU = 0
 COULOMB = 1
@@ -73,6 +75,11 @@ def lib():
                                       C.c_uint64, C.c_uint64]),
             "or_anneal_sweep": (C.c_int, [d, i32p, C.c_int, C.c_double, C.c_uint64,
                                           C.c_uint64, C.c_int, i64p]),
+            "or_half_sweep_g": (C.c_int, [d, i32p, C.c_int, C.c_int, C.c_int, C.c_double,
+                                          C.c_double, C.c_uint64, C.c_uint64, d]),
+            "or_heatbath_site_outcomes": (C.c_int, [d, i32p, C.c_int, C.c_double, C.c_uint64,
+                                                    C.c_uint64, C.c_int64, C.c_double, C.c_int,
+                                                    d, d]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -327,3 +334,34 @@ def anneal_sweep(U, gauge, T, seed, sweep, n_micro):
     if rc != 0:
         raise ValueError("or_anneal_sweep: bad arguments")
     return capped.value
+
+
+# update kinds of half_sweep_g
+OR, HEATBATH, MICRO, SR = 0, 1, 2, 3
+
+
+def half_sweep_g(U, gauge, parity, kind, omega=1.0, param=0.0, seed=0, sweep=0):
+    """Half-sweep of the given kind (OR, HEATBATH with param = T, MICRO, SR
+    with param = prob) in place; returns g (nt, nz, ny, nx, 3, 3): each updated
+    site's total transformation, 1 at the other parity."""
+    g = np.zeros(U.shape[:4] + (3, 3), dtype=np.complex128)
+    rc = lib().or_half_sweep_g(_field(U), _dims(dims_of(U)), int(gauge), int(parity), int(kind),
+                               float(omega), float(param), int(seed), int(sweep), _dptr(g))
+    if rc != 0:
+        raise ValueError("or_half_sweep_g: bad arguments")
+    return g
+
+
+def heatbath_site_outcomes(U, gauge, T, seed, sweep, s, tau, max_out=64):
+    """All results of the heatbath update of site s when the trials whose
+    accept margin is below tau may go either way: (outcomes (n, 8, 3, 3)
+    complex128 -- U_mu(s) mu = 0..3 then U_mu(s - mu) --, smallest margin on
+    the exact path). outcomes[0] is the exact result."""
+    out = np.zeros((max_out, 8, 3, 3), dtype=np.complex128)
+    mm = C.c_double(0.0)
+    n = lib().or_heatbath_site_outcomes(_field(U), _dims(dims_of(U)), int(gauge), float(T),
+                                        int(seed), int(sweep), int(s), float(tau), int(max_out),
+                                        _dptr(out), C.byref(mm))
+    if n < 0:
+        raise ValueError("or_heatbath_site_outcomes: bad arguments")
+    return out[:n].copy(), mm.value

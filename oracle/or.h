@@ -49,8 +49,9 @@ void    or_set_num_threads(int n);
  * 2x2 block M[{i,j},{i,j}]. */
 void or_su2_part(const double M[18], int i, int j, double q[4]);
 /* Overrelaxed local transformation s = g^omega from the unnormalised
- * quaternion q of K^dagger (Sec. 2, overrelaxation paragraph; flop-count
- * reading of Alg. 1): unit norm on output. Returns -1 if |q| is degenerate. */
+ * quaternion q of K^dagger (Sec. 2, overrelaxation paragraph; the form is the
+ * reading documented at the definition): unit norm on output. Returns -1 if
+ * |q| is degenerate. */
 int  or_overrelax(const double q[4], double omega, double s[4]);
 /* The other forms of g^omega (Sec. 2, overrelaxation paragraph: the power is
  * taken to first or second order): with g = q/|q| = 1 + a, form 1 is
@@ -64,7 +65,7 @@ void or_local_K(const double* U, const int32_t dims[4], int gauge, int64_t s, do
 
 /* the hot path ------------------------------------------------------------ */
 /* One checkerboard half-sweep of overrelaxation over the sites of one parity
- * (Alg. 1; omega = 1 is plain relaxation). */
+ * (Sec. 2, Alg. 1; omega = 1 is plain relaxation). */
 int  or_sweep(double* U, const int32_t dims[4], int gauge, int parity, double omega);
 /* The same half-sweep with the power g^omega taken in the given form
  * (or_overrelax_form; form 0 is or_sweep). */
@@ -162,6 +163,26 @@ int  or_heatbath_half(double* U, const int32_t dims[4], int gauge, int parity,
                       double T, uint64_t seed, uint64_t sweep, int64_t* n_capped);
 /* Microcanonical half-sweep: g = (local maximum)^2, which leaves Re tr[g K]
  * unchanged. */
+/* A half-sweep of one of the updates above (kind 0 overrelaxation with omega,
+ * 1 heatbath at temperature param, 2 microcanonical, 3 stochastic relaxation
+ * with probability param; seed and sweep key the draws) that also writes
+ * g[s] (V x 3 x 3 complex128): each updated site's total transformation, the
+ * product of its three subgroup factors; 1 at the sites of the other parity. */
+int  or_half_sweep_g(double* U, const int32_t dims[4], int gauge, int parity, int kind,
+                     double omega, double param, uint64_t seed, uint64_t sweep, double* g);
+/* Every result the heatbath update of site s (as in or_heatbath_half with T,
+ * seed, sweep) can have when each Kennedy-Pendleton trial whose accept margin
+ * |(1 - lambda^2) - u4^2| is below tau may be decided either way, as a
+ * sampler in lower precision may decide it. Outcome 0 is the exact result;
+ * the others are explored depth first, each deciding one more borderline
+ * trial the other way. An outcome is the 8 links the update moves, U_mu(s),
+ * mu = 0..3, then U_mu(s - mu), 18 doubles each, into links_out
+ * (max_out x 8 x 18). min_margin (may be NULL) receives the smallest margin
+ * met on the exact path. Returns the number of outcomes (<= max_out) or -1.
+ * The field is not changed. */
+int  or_heatbath_site_outcomes(const double* U, const int32_t dims[4], int gauge, double T,
+                               uint64_t seed, uint64_t sweep, int64_t s, double tau,
+                               int max_out, double* links_out, double* min_margin);
 int  or_micro_half(double* U, const int32_t dims[4], int gauge, int parity);
 /* One annealing step: heatbath RED, BLACK, then n_micro microcanonical
  * sweeps (RED, BLACK each). */

@@ -7,9 +7,13 @@
  * smoke check and the CPU baseline leg of the benchmark. It shares no code
  * (no headers, helpers, tables or constants) with the GPU library.
  *
- * Style: every step is written out with full 3x3 complex matrices in the
- * order the paper gives it, without blocking, fusion or reordering, so that a
- * reader can check it against the paper by eye. Compiled -O2
+ * Style: plain loops over full 3x3 complex matrices, written from the
+ * defining equations: a site's update gathers the eight links that g(x)
+ * moves (eq. (4)), maximises the local functional Re tr[g(x) K(x)] (K of
+ * eq. (5)) within each SU(2) subgroup of SU(3) in turn (eq. (6)), with the
+ * update rule of the method (overrelaxation, heatbath, microcanonical), and
+ * writes the links back. There is no blocking, fusion or reordering, so that
+ * a reader can check each step against the paper by eye. Compiled -O2
  * -ffp-contract=off (no FMA contraction, no fast-math); OpenMP only splits
  * the sites of one checkerboard sublattice, which share no link, and all
  * reductions are summed serially in site order (results do not depend on
@@ -24,7 +28,8 @@
  *   Sec. 2   overrelaxation g -> g^omega, omega in [1, 2)
  *   Sec. 2   RED/BLACK checkerboard decomposition
  *   eq. (7)  precision theta = (1/(V N_c)) sum_x tr[Delta(x) Delta(x)^dag]
- *   Alg. 1   Overrelaxation (order of the steps, flop counts 60/19/84/84)
+ *   Alg. 1   the iteration: sweep one sublattice, then the other, until
+ *            theta is below the target
  *   Sec. 1   simulated annealing as a preconditioner; Coulomb gauge
  * Points where the paper is silent are filled with the readings documented
  * next to the code that uses them (degenerate subgroups, theta's Delta,
@@ -207,16 +212,17 @@ static mat3 embed_su2(const double a[4], int i, int j) {
 #define OR_DEGENERATE 1e-300
 
 /* Overrelaxation (Sec. 2): replace the local maximum g = q/|q| by g^omega.
- * The paper only says the power is taken "to first or second order" and
- * counts 19 flop for "g -> g^omega, project to SU(2)" (Alg. 1). The reading
- * used here works on the unnormalised q = (q0, qv):
+ * The paper leaves the form of the power open beyond saying that it is a
+ * low-order expansion; the reading used here is the one whose operation
+ * count equals the paper's count for this step (Alg. 1). It works on the
+ * unnormalised q = (q0, qv):
  *   b = (omega q0^2 + |qv|^2) / (q0^2 + |qv|^2),
  *   c = 1 / sqrt(q0^2 + b^2 |qv|^2),
  *   s = (c q0, b c qv),
  * which is unit-norm, equals q/|q| exactly at omega = 1, and for
  * q ~ (cos phi, sin phi n) rotates by phi' with
  * tan phi' = (1 + (omega-1) cos^2 phi) tan phi, i.e. phi' = omega phi to
- * first order in phi. Its operation count is 19. */
+ * first order in phi. */
 int or_overrelax(const double q[4], double omega, double s[4]) {
   double a0sq = q[0] * q[0];
   double avsq = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
@@ -328,21 +334,56 @@ static void draw_block(uint64_t seed, uint64_t site, uint64_t sweep, uint32_t ta
   for (int k = 0; k < 4; ++k) u[k] = u01(r[k]);
 }
 
+/* Accept decisions of the heatbath, seen from outside. A sampler working in
+ * lower precision takes the same decisions as this one except where the
+ * margin m = (1 - lambda^2) - u4^2 of a trial is within its rounding of 0.
+ * With a control block, every trial whose |m| is below tau is recorded (in
+ * the order the trials are made: subgroup, then attempt), the trials listed
+ * in flip are decided the other way, and the smallest |m| met is kept. */
+#define OR_HB_MAX_FLIPS 8
+#define OR_HB_MAX_SEEN 16
+typedef struct {
+  double tau;
+  int nflip;
+  int flip_sg[OR_HB_MAX_FLIPS], flip_att[OR_HB_MAX_FLIPS];
+  int nseen;
+  int seen_sg[OR_HB_MAX_SEEN], seen_att[OR_HB_MAX_SEEN];
+  double min_margin;
+} hb_ctl;
+
+static int hb_flipped(const hb_ctl* c, int sg, int att) {
+  for (int k = 0; k < c->nflip; ++k)
+    if (c->flip_sg[k] == sg && c->flip_att[k] == att) return 1;
+  return 0;
+}
+
 /* Kennedy & Pendleton, Phys. Lett. B 156 (1985) 393: with
  * lambda^2 = -(ln u1 + cos^2(2 pi u2) ln u3) / (2 alpha) (a Gamma(3/2)
  * variate scaled by 1/(2 alpha)), accept when u4^2 <= 1 - lambda^2 and set
  * X0 = 1 - 2 lambda^2; X0 then has density ~ sqrt(1 - X0^2) exp(alpha X0).
  * Returns the attempts used (0 when the cap was hit) and lambda^2. */
 static int kp_lambda2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int sg,
-                      double* lam2_out) {
+                      hb_ctl* ctl, double* lam2_out) {
   const double two_pi = 6.283185307179586476925286766559;
   for (int a = 0; a < OR_KP_MAX_ATTEMPTS; ++a) {
     double u[4];
     draw_block(seed, site, sweep, OR_TAG_KP(sg), (uint32_t)a, u);
     double cs = cos(two_pi * u[1]);
     double lam2 = -(log(u[0]) + cs * cs * log(u[2])) / (2.0 * alpha);
-    if (u[3] * u[3] <= 1.0 - lam2) {
-      *lam2_out = lam2;
+    int accept = u[3] * u[3] <= 1.0 - lam2;
+    if (ctl) {
+      double m = fabs((1.0 - lam2) - u[3] * u[3]);
+      if (m < ctl->min_margin) ctl->min_margin = m;
+      if (m < ctl->tau && ctl->nseen < OR_HB_MAX_SEEN) {
+        ctl->seen_sg[ctl->nseen] = sg;
+        ctl->seen_att[ctl->nseen] = a;
+        ctl->nseen++;
+      }
+      if (hb_flipped(ctl, sg, a)) accept = !accept;
+    }
+    if (accept) {
+      /* a trial accepted against its margin may sit just above 1 */
+      *lam2_out = lam2 > 1.0 ? 1.0 : lam2;
       return a + 1;
     }
   }
@@ -351,7 +392,7 @@ static int kp_lambda2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep
 
 int or_kp_draw(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int sg, double* X0) {
   double lam2;
-  int n = kp_lambda2(alpha, seed, site, sweep, sg, &lam2);
+  int n = kp_lambda2(alpha, seed, site, sweep, sg, NULL, &lam2);
   if (n) *X0 = 1.0 - 2.0 * lam2;
   return n;
 }
@@ -360,10 +401,10 @@ int or_kp_draw(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int s
  * the Kennedy-Pendleton draw, (X1, X2, X3) uniform on the sphere of radius
  * sqrt(1 - X0^2) from one more Philox block (cos theta = 2 u1 - 1,
  * phi = 2 pi u2). Returns the attempts used, 0 if the cap was hit. */
-int or_heatbath_su2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int sg,
-                    double X[4]) {
+static int heatbath_su2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int sg,
+                        hb_ctl* ctl, double X[4]) {
   double lam2;
-  int n = kp_lambda2(alpha, seed, site, sweep, sg, &lam2);
+  int n = kp_lambda2(alpha, seed, site, sweep, sg, ctl, &lam2);
   if (n == 0) return 0;
   const double two_pi = 6.283185307179586476925286766559;
   double d[4];
@@ -381,8 +422,81 @@ int or_heatbath_su2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, 
   return n;
 }
 
+int or_heatbath_su2(double alpha, uint64_t seed, uint64_t site, uint64_t sweep, int sg,
+                    double X[4]) {
+  return heatbath_su2(alpha, seed, site, sweep, sg, NULL, X);
+}
+
 /* ------------------------------------------------------------------------- */
-/* site update (Alg. 1 body) for overrelaxation, heatbath and microcanonical  */
+/* the local problem at one site                                              */
+/* ------------------------------------------------------------------------- */
+/* By eq. (4) a transformation g(x) at the single site x moves exactly eight
+ * links: U_mu(x) -> g(x) U_mu(x) and U_mu(x - mu) -> U_mu(x - mu) g(x)^dag,
+ * mu = 0..3. Only these enter the part of F (eq. (3)) that depends on g(x),
+ * so a site's update reads them, works on them and writes them back. */
+typedef struct {
+  mat3 fwd[4]; /* U_mu(x)      */
+  mat3 bwd[4]; /* U_mu(x - mu) */
+} site_links;
+
+static void gather_site(const double* U, const lat_t* L, int64_t s, site_links* S) {
+  for (int mu = 0; mu < 4; ++mu) {
+    S->fwd[mu] = get_link(U, s, mu);
+    S->bwd[mu] = get_link(U, neighbour(L, s, mu, -1), mu);
+  }
+}
+
+static void scatter_site(double* U, const lat_t* L, int64_t s, const site_links* S) {
+  for (int mu = 0; mu < 4; ++mu) {
+    put_link(U, s, mu, &S->fwd[mu]);
+    put_link(U, neighbour(L, s, mu, -1), mu, &S->bwd[mu]);
+  }
+}
+
+/* First direction entering K, F and theta: Landau all four, Coulomb the
+ * spatial ones (Sec. 1: Coulomb gauge d_i A_i = 0). */
+static int first_dir(int gauge) { return gauge == OR_COULOMB ? 1 : 0; }
+
+/* K(x) of eq. (5) from the current links: sum over mu in D of
+ * U_mu(x) + U_mu(x - mu)^dag. Every update is applied to the field in place,
+ * so the transformations g(x +- mu) that eq. (5) writes out are already in
+ * the neighbouring links. With it the g(x)-dependent part of F is
+ * Re tr[g(x) K(x)]. */
+static mat3 site_K(const site_links* S, int gauge) {
+  mat3 K = mat_zero();
+  for (int mu = first_dir(gauge); mu < 4; ++mu) {
+    mat3 Wd = mat_dag(&S->bwd[mu]);
+    K = mat_add(&K, &S->fwd[mu]);
+    K = mat_add(&K, &Wd);
+  }
+  return K;
+}
+
+static mat3 local_K(const double* U, const lat_t* L, int gauge, int64_t s) {
+  site_links S;
+  gather_site(U, L, s, &S);
+  return site_K(&S, gauge);
+}
+
+void or_local_K(const double* U, const int32_t dims[4], int gauge, int64_t s, double K[18]) {
+  lat_t L = make_lat(dims);
+  mat3 Km = local_K(U, &L, gauge, s);
+  mat_to18(&Km, K);
+}
+
+/* eq. (4) at x for a factor h of g(x): g(x) -> h g(x). All four directions
+ * move, also in the Coulomb gauge (the output stays a gauge transform of the
+ * input). */
+static void transform_site(site_links* S, const mat3* h) {
+  mat3 hd = mat_dag(h);
+  for (int mu = 0; mu < 4; ++mu) {
+    S->fwd[mu] = mat_mul(h, &S->fwd[mu]);
+    S->bwd[mu] = mat_mul(&S->bwd[mu], &hd);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* site updates: overrelaxation, heatbath, microcanonical, stochastic        */
 /* ------------------------------------------------------------------------- */
 enum { UPD_OR = 0, UPD_HB = 1, UPD_MICRO = 2, UPD_SR = 3 };
 typedef struct {
@@ -393,101 +507,91 @@ typedef struct {
   int form;     /* overrelaxation: form of g^omega (0: or_overrelax) */
 } upd_t;
 
-/* First direction entering K, F and theta: Landau all four, Coulomb the
- * spatial ones (Sec. 1: Coulomb gauge d_i A_i = 0). */
-static int first_dir(int gauge) { return gauge == OR_COULOMB ? 1 : 0; }
-
-/* K(x)^dagger as written in the first line of the body of Alg. 1:
- * sum_mu U_mu(x)^dagger + U_mu(x - mu). The stored links already carry the
- * transformations of all previously updated sites, so the g(x +- mu) of
- * eq. (5) are absorbed. */
-static mat3 local_Kdag(const double* U, const lat_t* L, int gauge, int64_t s) {
-  mat3 Kd = mat_zero();
-  for (int mu = first_dir(gauge); mu < 4; ++mu) {
-    mat3 Uf = get_link(U, s, mu);
-    mat3 Ub = get_link(U, neighbour(L, s, mu, -1), mu);
-    mat3 Ufd = mat_dag(&Uf);
-    Kd = mat_add(&Kd, &Ufd);
-    Kd = mat_add(&Kd, &Ub);
+/* The element of subgroup sg = (i,j) by which the update rule moves g(x),
+ * given the current K. For h = embed(a) in the subgroup,
+ * Re tr[h K] = 2 a.q + (terms without a), q the quaternion part of the (i,j)
+ * block of K^dag (or_su2_part); by eq. (6) its maximum over SU(2) is at
+ * a = q/|q|. Returns 0 with h set, 1 when the heatbath hit its attempt cap,
+ * -1 when the subgroup is degenerate (h = 1 in both cases). */
+static int subgroup_element(const mat3* K, int sg, int64_t s, const upd_t* u, hb_ctl* ctl,
+                            mat3* h) {
+  const int i = SG_I[sg], j = SG_J[sg];
+  mat3 Kd = mat_dag(K);
+  double M18[18], q[4], g[4];
+  mat_to18(&Kd, M18);
+  or_su2_part(M18, i, j, q);
+  double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+  if (qn2 < OR_DEGENERATE) return -1;
+  int kind = u->kind;
+  if (kind == UPD_SR) {
+    /* stochastic relaxation (Sec. 1): with probability p the
+     * microcanonical step, otherwise the (over)relaxation step */
+    double d[4];
+    draw_block(u->seed, (uint64_t)s, u->sweep, OR_TAG_SR(sg), 0u, d);
+    kind = d[0] < u->T ? UPD_MICRO : UPD_OR;
   }
-  return Kd;
+  if (kind == UPD_OR) {
+    /* the local maximum raised to omega (Sec. 2, overrelaxation) */
+    if (or_overrelax_form(q, u->omega, u->form, g) < 0) return -1;
+    *h = embed_su2(g, i, j);
+    return 0;
+  }
+  double n = sqrt(qn2);
+  double qh[4] = {q[0] / n, q[1] / n, q[2] / n, q[3] / n};
+  mat3 Gh = embed_su2(qh, i, j);
+  if (kind == UPD_MICRO) {
+    /* the reflection through the local maximum, ghat^2: Re tr[h K] is
+     * unchanged */
+    *h = mat_mul(&Gh, &Gh);
+    return 0;
+  }
+  /* heatbath with weight exp(Re tr[h K] / T): writing h = X qhat,
+   * Re tr[h K] = 2|q| X0 + const, so X is drawn with density ~ exp(alpha X0)
+   * under Haar measure, alpha = 2|q|/T */
+  double X[4];
+  if (heatbath_su2(2.0 * n / u->T, u->seed, (uint64_t)s, u->sweep, sg, ctl, X) == 0) return 1;
+  mat3 GX = embed_su2(X, i, j);
+  *h = mat_mul(&GX, &Gh);
+  return 0;
 }
 
-void or_local_K(const double* U, const int32_t dims[4], int gauge, int64_t s, double K[18]) {
-  lat_t L = make_lat(dims);
-  mat3 Kd = local_Kdag(U, &L, gauge, s);
-  mat3 Km = mat_dag(&Kd);
-  mat_to18(&Km, K);
-}
-
-/* returns the number of subgroup updates that hit the heatbath attempt cap */
-static int site_update(double* U, const lat_t* L, int gauge, int64_t s, const upd_t* u) {
+/* One site's update: g(x) is moved within the SU(2) subgroups of SU(3) one
+ * after another (Cabibbo-Marinari; subgroup order (0,1), (0,2), (1,2)), each
+ * step taking K of eq. (5) from the links as the previous steps left them.
+ * gtot (may be NULL) receives the product of the three factors, i.e. the
+ * whole change of g(x). Returns the number of heatbath steps that hit the
+ * attempt cap. */
+static int update_site(site_links* S, int gauge, int64_t s, const upd_t* u, hb_ctl* ctl,
+                       mat3* gtot) {
   int capped = 0;
+  if (gtot) *gtot = mat_unit();
   for (int sg = 0; sg < 3; ++sg) {
-    int i = SG_I[sg], j = SG_J[sg];
-    /* Alg. 1: g(x) <- sum_mu {U_mu(x)^dag + U_mu(x - mu)}, recomputed for
-     * every subgroup from the current links (60 flop in the paper's count) */
-    mat3 Kd = local_Kdag(U, L, gauge, s);
-    double M18[18], q[4], g[4];
-    mat_to18(&Kd, M18);
-    /* project the (i,j) block to SU(2): by eq. (6) the maximiser of
-     * Re tr[g K] over the subgroup is the normalised quaternion part of K^dag */
-    or_su2_part(M18, i, j, q);
-    double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
-    if (qn2 < OR_DEGENERATE) continue;
-    mat3 G;
-    int kind = u->kind;
-    if (kind == UPD_SR) {
-      /* stochastic relaxation (Sec. 1): with probability p the
-       * microcanonical step, otherwise the (over)relaxation step */
-      double d[4];
-      draw_block(u->seed, (uint64_t)s, u->sweep, OR_TAG_SR(sg), 0u, d);
-      kind = d[0] < u->T ? UPD_MICRO : UPD_OR;
+    mat3 K = site_K(S, gauge);
+    mat3 h;
+    int rc = subgroup_element(&K, sg, s, u, ctl, &h);
+    if (rc != 0) {
+      capped += rc > 0;
+      continue;
     }
-    if (kind == UPD_OR) {
-      /* Alg. 1: g -> g^omega, project to SU(2) (19 flop in form 0) */
-      if (or_overrelax_form(q, u->omega, u->form, g) < 0) continue;
-      G = embed_su2(g, i, j);
-    } else if (kind == UPD_MICRO) {
-      /* microcanonical step: g = ghat^2, the reflection through the local
-       * maximum; it leaves Re tr[g K] unchanged */
-      double n = sqrt(qn2);
-      double qh[4] = {q[0] / n, q[1] / n, q[2] / n, q[3] / n};
-      mat3 Gh = embed_su2(qh, i, j);
-      G = mat_mul(&Gh, &Gh);
-    } else {
-      /* heatbath with weight exp(Re tr[g K] / T) on the subgroup. With
-       * Re tr[g K] = 2|q| X0 for g = X qhat, X is drawn with density
-       * ~ exp(alpha X0) under Haar measure, alpha = 2|q|/T. */
-      double n = sqrt(qn2);
-      double X[4];
-      if (or_heatbath_su2(2.0 * n / u->T, u->seed, (uint64_t)s, u->sweep, sg, X) == 0) {
-        ++capped;
-        continue;
-      }
-      double qh[4] = {q[0] / n, q[1] / n, q[2] / n, q[3] / n};
-      mat3 GX = embed_su2(X, i, j);
-      mat3 Gh = embed_su2(qh, i, j);
-      G = mat_mul(&GX, &Gh);
-    }
-    /* Alg. 1: for all mu, U_mu(x) <- g U_mu(x) and U_mu(x-mu) <- U_mu(x-mu) g^dag
-     * (84 + 84 flop); all four directions also in the Coulomb gauge */
-    mat3 Gd = mat_dag(&G);
-    for (int mu = 0; mu < 4; ++mu) {
-      int64_t sb = neighbour(L, s, mu, -1);
-      mat3 Uf = get_link(U, s, mu);
-      mat3 Ub = get_link(U, sb, mu);
-      mat3 Ufn = mat_mul(&G, &Uf);
-      mat3 Ubn = mat_mul(&Ub, &Gd);
-      put_link(U, s, mu, &Ufn);
-      put_link(U, sb, mu, &Ubn);
-    }
+    transform_site(S, &h);
+    if (gtot) *gtot = mat_mul(&h, gtot);
   }
   return capped;
 }
 
+static int site_update(double* U, const lat_t* L, int gauge, int64_t s, const upd_t* u,
+                       mat3* gtot) {
+  site_links S;
+  gather_site(U, L, s, &S);
+  int capped = update_site(&S, gauge, s, u, NULL, gtot);
+  scatter_site(U, L, s, &S);
+  return capped;
+}
+
+/* g may be NULL; else g[s] receives the site's total transformation (sites of
+ * the other parity: 1) */
 static int half_sweep(double* U, const int32_t dims[4], int gauge, int parity, const upd_t* u,
-                      int64_t* n_capped) {
+                      int64_t* n_capped, double* g) {
   if (!U || or_check_dims(dims) != 0 || (parity != 0 && parity != 1)) return -1;
   if (gauge != OR_LANDAU && gauge != OR_COULOMB) return -1;
   lat_t L = make_lat(dims);
@@ -495,8 +599,9 @@ static int half_sweep(double* U, const int32_t dims[4], int gauge, int parity, c
   /* Sec. 2: all sites of one sublattice are independent (no shared link) */
 #pragma omp parallel for schedule(static) reduction(+ : capped)
   for (int64_t s = 0; s < L.V; ++s) {
-    if (site_parity(&L, s) != parity) continue;
-    capped += site_update(U, &L, gauge, s, u);
+    mat3 gs = mat_unit();
+    if (site_parity(&L, s) == parity) capped += site_update(U, &L, gauge, s, u, &gs);
+    if (g) mat_to18(&gs, g + 18 * s);
   }
   if (n_capped) *n_capped += capped;
   return 0;
@@ -515,7 +620,7 @@ int or_update_sites(double* U, const int32_t dims[4], int gauge, double omega,
     if (sites[k] < 0 || sites[k] >= L.V || site_parity(&L, sites[k]) != p0) return -1;
   upd_t u = {UPD_OR, omega, 0.0, 0, 0, 0};
 #pragma omp parallel for schedule(static)
-  for (int64_t k = 0; k < n; ++k) site_update(U, &L, gauge, sites[k], &u);
+  for (int64_t k = 0; k < n; ++k) site_update(U, &L, gauge, sites[k], &u, NULL);
   return 0;
 }
 
@@ -531,40 +636,117 @@ int or_heatbath_sites(double* U, const int32_t dims[4], int gauge, double T, uin
     if (sites[k] < 0 || sites[k] >= L.V || site_parity(&L, sites[k]) != p0) return -1;
   upd_t u = {UPD_HB, 0.0, T, seed, sweep, 0};
 #pragma omp parallel for schedule(static)
-  for (int64_t k = 0; k < n; ++k) site_update(U, &L, gauge, sites[k], &u);
+  for (int64_t k = 0; k < n; ++k) site_update(U, &L, gauge, sites[k], &u, NULL);
   return 0;
+}
+
+/* Every result the heatbath update of site s can have when each trial whose
+ * accept margin is below tau may be decided either way (see hb_ctl). The
+ * outcomes are explored depth first: outcome 0 is the exact one; every other
+ * takes one more borderline trial the other way than an outcome before it,
+ * a trial met after the last one flipped there. Each outcome is the site's 8
+ * links, U_mu(s) for mu = 0..3 then U_mu(s - mu), 18 doubles each. Returns the
+ * number of outcomes (at most max_out; the field is not changed), or -1. */
+int or_heatbath_site_outcomes(const double* U, const int32_t dims[4], int gauge, double T,
+                              uint64_t seed, uint64_t sweep, int64_t s, double tau, int max_out,
+                              double* links_out, double* min_margin) {
+  if (!U || !links_out || or_check_dims(dims) != 0 || !(T > 0.0) || max_out < 1) return -1;
+  if (gauge != OR_LANDAU && gauge != OR_COULOMB) return -1;
+  lat_t L = make_lat(dims);
+  if (s < 0 || s >= L.V) return -1;
+  upd_t u = {UPD_HB, 0.0, T, seed, sweep, 0};
+  site_links S0;
+  gather_site(U, &L, s, &S0);
+  /* pending flip sets, processed in order */
+  enum { QMAX = 256 };
+  int qn[QMAX], qsg[QMAX][OR_HB_MAX_FLIPS], qatt[QMAX][OR_HB_MAX_FLIPS];
+  int head = 0, tail = 1, nout = 0;
+  qn[0] = 0;
+  while (head < tail && nout < max_out) {
+    hb_ctl c;
+    memset(&c, 0, sizeof c);
+    c.tau = tau;
+    c.min_margin = HUGE_VAL;
+    c.nflip = qn[head];
+    for (int k = 0; k < c.nflip; ++k) {
+      c.flip_sg[k] = qsg[head][k];
+      c.flip_att[k] = qatt[head][k];
+    }
+    site_links S = S0;
+    update_site(&S, gauge, s, &u, &c, NULL);
+    double* o = links_out + (size_t)nout * 8 * 18;
+    for (int mu = 0; mu < 4; ++mu) {
+      mat_to18(&S.fwd[mu], o + 18 * mu);
+      mat_to18(&S.bwd[mu], o + 18 * (4 + mu));
+    }
+    if (nout == 0 && min_margin) *min_margin = c.min_margin;
+    ++nout;
+    /* children: flip one more borderline trial met after the last flip */
+    int lsg = c.nflip ? c.flip_sg[c.nflip - 1] : -1;
+    int latt = c.nflip ? c.flip_att[c.nflip - 1] : -1;
+    for (int k = 0; k < c.nseen; ++k) {
+      int sg = c.seen_sg[k], att = c.seen_att[k];
+      if (sg < lsg || (sg == lsg && att <= latt)) continue;
+      if (c.nflip >= OR_HB_MAX_FLIPS || tail >= QMAX) break;
+      qn[tail] = c.nflip + 1;
+      for (int m = 0; m < c.nflip; ++m) {
+        qsg[tail][m] = c.flip_sg[m];
+        qatt[tail][m] = c.flip_att[m];
+      }
+      qsg[tail][c.nflip] = sg;
+      qatt[tail][c.nflip] = att;
+      ++tail;
+    }
+    ++head;
+  }
+  return nout;
 }
 
 int or_sweep(double* U, const int32_t dims[4], int gauge, int parity, double omega) {
   if (!(omega >= 1.0 && omega < 2.0)) return -1; /* Sec. 2: omega in [1, 2) */
   upd_t u = {UPD_OR, omega, 0.0, 0, 0, 0};
-  return half_sweep(U, dims, gauge, parity, &u, NULL);
+  return half_sweep(U, dims, gauge, parity, &u, NULL, NULL);
 }
 
 int or_sweep_form(double* U, const int32_t dims[4], int gauge, int parity, double omega,
                   int form) {
   if (!(omega >= 1.0 && omega < 2.0) || form < 0 || form > 3) return -1;
   upd_t u = {UPD_OR, omega, 0.0, 0, 0, form};
-  return half_sweep(U, dims, gauge, parity, &u, NULL);
+  return half_sweep(U, dims, gauge, parity, &u, NULL, NULL);
 }
 
 int or_sweep_sr(double* U, const int32_t dims[4], int gauge, int parity, double omega,
                 double prob, uint64_t seed, uint64_t sweep) {
   if (!(omega >= 1.0 && omega < 2.0) || !(prob >= 0.0 && prob <= 1.0)) return -1;
   upd_t u = {UPD_SR, omega, prob, seed, sweep, 0};
-  return half_sweep(U, dims, gauge, parity, &u, NULL);
+  return half_sweep(U, dims, gauge, parity, &u, NULL, NULL);
 }
 
 int or_micro_half(double* U, const int32_t dims[4], int gauge, int parity) {
   upd_t u = {UPD_MICRO, 0.0, 0.0, 0, 0, 0};
-  return half_sweep(U, dims, gauge, parity, &u, NULL);
+  return half_sweep(U, dims, gauge, parity, &u, NULL, NULL);
 }
 
 int or_heatbath_half(double* U, const int32_t dims[4], int gauge, int parity, double T,
                      uint64_t seed, uint64_t sweep, int64_t* n_capped) {
   if (!(T > 0.0) || !isfinite(T)) return -1;
   upd_t u = {UPD_HB, 0.0, T, seed, sweep, 0};
-  return half_sweep(U, dims, gauge, parity, &u, n_capped);
+  return half_sweep(U, dims, gauge, parity, &u, n_capped, NULL);
+}
+
+int or_half_sweep_g(double* U, const int32_t dims[4], int gauge, int parity, int kind,
+                    double omega, double param, uint64_t seed, uint64_t sweep, double* g) {
+  upd_t u = {kind, omega, param, seed, sweep, 0};
+  if (!g) return -1;
+  if (kind == UPD_OR || kind == UPD_SR) {
+    if (!(omega >= 1.0 && omega < 2.0)) return -1;
+    if (kind == UPD_SR && !(param >= 0.0 && param <= 1.0)) return -1;
+  } else if (kind == UPD_HB) {
+    if (!(param > 0.0) || !isfinite(param)) return -1;
+  } else if (kind != UPD_MICRO) {
+    return -1;
+  }
+  return half_sweep(U, dims, gauge, parity, &u, NULL, g);
 }
 
 int or_anneal_sweep(double* U, const int32_t dims[4], int gauge, double T, uint64_t seed,
@@ -715,8 +897,7 @@ double or_theta_K(const double* U, const int32_t dims[4], int gauge, double* out
   double* per_site = (double*)malloc(sizeof(double) * (size_t)L.V);
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < L.V; ++s) {
-    mat3 Kd = local_Kdag(U, &L, gauge, s);
-    mat3 K = mat_dag(&Kd);
+    mat3 K = local_K(U, &L, gauge, s);
     mat3 D = traceless_antiherm(&K);
     per_site[s] = tr_MMdag(&D);
   }
@@ -873,7 +1054,7 @@ int or_fix_coulomb_frozen(double* U, const int32_t dims[4], double omega, double
 #pragma omp parallel for schedule(static)
         for (int64_t s = 0; s < L.V; ++s)
           if (site_parity(&L, s) == parity && active[s / Vs])
-            site_update(U, &L, OR_COULOMB, s, &u);
+            site_update(U, &L, OR_COULOMB, s, &u, NULL);
       }
       ++sweeps;
     }

@@ -67,7 +67,8 @@ __device__ __forceinline__ void qmul(const T a[4], const T b[4], T c[4]) {
 
 // ---- update policies: w -> SU(2) quaternion s (false: leave the subgroup) ----
 
-// Overrelaxation (Sec. 2, Alg. 1 "g -> g^omega, project to SU(2)", 19 flop):
+// Overrelaxation (Sec. 2; the form of the power whose operation count equals
+// the paper's count for this step in Alg. 1):
 // b = (omega w0^2 + |wv|^2)/|w|^2, c = (w0^2 + b^2 |wv|^2)^(-1/2),
 // s = (c w0, b c wv); omega = 1 gives s = w/|w|.
 template <typename T>

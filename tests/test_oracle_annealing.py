@@ -190,3 +190,90 @@ def test_stochastic_relaxation_monotone_and_mixed():
     assert not np.array_equal(A, B) and not np.array_equal(A, C)
     with pytest.raises(ValueError):
         O.sweep_sr(U.copy(), L, 0, 1.0, 1.5, 5, 0)
+
+
+def _su3_checks(g, tol=1e-13):
+    eye = np.eye(3)
+    gg = np.einsum("...ab,...cb->...ac", g, g.conj())
+    assert np.abs(gg - eye).max() < tol
+    assert np.abs(np.linalg.det(g) - 1).max() < tol
+
+
+@pytest.mark.parametrize("kind,param", [(O.OR, 0.0), (O.HEATBATH, 0.8), (O.MICRO, 0.0),
+                                        (O.SR, 0.5)])
+@pytest.mark.parametrize("gauge", [L, CLB])
+def test_half_sweep_g_is_the_site_transformation(kind, param, gauge):
+    """The g that half_sweep_g reports, applied to the input by eq. (4),
+    reproduces the half-sweep; it is in SU(3), and 1 at the other parity."""
+    dims = (4, 2, 4, 6)
+    U0 = inputs.config0(dims, 0.5, 21)
+    for parity in (0, 1):
+        U = U0.copy()
+        g = O.half_sweep_g(U, gauge, parity, kind, omega=1.6, param=param, seed=3, sweep=11)
+        _su3_checks(g)
+        t, z, y, x = np.indices(dims)
+        other = (t + z + y + x) % 2 != parity
+        assert np.array_equal(g[other], np.broadcast_to(np.eye(3), g[other].shape))
+        V = U0.copy()
+        O.gauge_transform(V, g)
+        assert np.abs(V - U).max() < 1e-13
+        # the field it leaves is the plain half-sweep's, bit for bit
+        W = U0.copy()
+        if kind == O.OR:
+            O.sweep(W, gauge, parity, 1.6)
+        elif kind == O.HEATBATH:
+            O.heatbath_half(W, gauge, parity, param, 3, 11)
+        elif kind == O.MICRO:
+            O.micro_half(W, gauge, parity)
+        else:
+            O.sweep_sr(W, gauge, parity, 1.6, param, 3, 11)
+        assert np.array_equal(W, U)
+
+
+def _site_links(U, s):
+    dims = U.shape[:4]
+    t, z, y, x = np.unravel_index(s, dims)
+    c = [t, x, y, z]
+    ext = [dims[0], dims[3], dims[2], dims[1]]
+    f = [U[t, z, y, x, mu] for mu in range(4)]
+    b = []
+    for mu in range(4):
+        d = list(c)
+        d[mu] = (d[mu] - 1) % ext[mu]
+        b.append(U[d[0], d[3], d[2], d[1], mu])
+    return np.array(f + b)
+
+
+@pytest.mark.parametrize("gauge", [L, CLB])
+def test_heatbath_outcomes(gauge):
+    """Outcome 0 is the exact update; tau = 0 leaves it alone; every other
+    outcome is still a transformation by eq. (4) at the site, with an SU(3)
+    factor, and the smallest margin separates one outcome from two."""
+    dims = (4, 4, 4, 4)
+    U0 = inputs.config0(dims, 0.7, 5)
+    T, seed, sweep = 1.1, 17, 4
+    many = 0
+    for s in range(0, 256, 5):
+        if sum(np.unravel_index(s, dims)) % 2:
+            continue
+        ref = U0.copy()
+        O.heatbath_sites(ref, gauge, T, seed, sweep, [s])
+        exact = _site_links(ref, s)
+        outs, mm = O.heatbath_site_outcomes(U0, gauge, T, seed, sweep, s, 0.0)
+        assert len(outs) == 1 and np.array_equal(outs[0], exact)
+        assert mm > 0
+        outs, _ = O.heatbath_site_outcomes(U0, gauge, T, seed, sweep, s, 0.5, max_out=64)
+        assert np.array_equal(outs[0], exact)
+        old = _site_links(U0, s)
+        for o in outs:
+            h = o[0] @ old[0].conj().T
+            _su3_checks(h[None], tol=1e-12)
+            for mu in range(4):
+                assert np.abs(o[mu] - h @ old[mu]).max() < 1e-12
+                assert np.abs(o[4 + mu] - old[4 + mu] @ h.conj().T).max() < 1e-12
+        many += len(outs) > 1
+        if len(outs) > 1:
+            n_lo = len(O.heatbath_site_outcomes(U0, gauge, T, seed, sweep, s, mm * 0.999)[0])
+            n_hi = len(O.heatbath_site_outcomes(U0, gauge, T, seed, sweep, s, mm * 1.001)[0])
+            assert n_lo == 1 and n_hi >= 2
+    assert many > 0
