@@ -1,20 +1,28 @@
 """Benchmark: Landau overrelaxation gauge fixing on one MI355X.
 
-Workload (default): a 32^4 SU(3) configuration from a quenched Wilson-action
-heatbath at beta = 6.0 (cold start, 300 sweeps, Philox seed 2), generated on
-the GPU before the timed region. One benchmark step is the whole hot path for
-that configuration: pack the canonical FP64 field into the FP64 12-real
-device layout, conversion to FP32, FP32 overrelaxation
-(omega = 1.7) with a check of F and theta every 100 sweeps until
-theta < 1e-6 while the accumulated gauge transformation is tracked, that
-transformation applied in FP64 to the FP64 input, FP64 sweeps until
-theta < 1e-14.
+Headline workload (default, --workload landau48): a 48^4 SU(3) configuration
+from a quenched Wilson-action heatbath at beta = 6.2 (cold start, 400 sweeps,
+Philox seed 3), generated on the GPU before anything is timed; the field
+(2.04 GB in FP64 12-real storage) is eight times the 256 MB Infinity Cache,
+so the sweeps run at HBM speed.
 
-value = site updates per second of the whole step (V x sweeps / step time).
-Also reported: the pure-FP64 time to theta < 1e-14 on the same input, the
-per-kernel rates of the four storage variants, the roofline of the dominant
-sweep kernel (HIP-event timings of its launches inside the timed region) and
-the CPU oracle timed on a bounded sample.
+One benchmark step is a fixed block of that configuration's gauge fixing:
+1000 sweeps (RED + BLACK half-sweeps, omega = 1.7) of the FP64 12-real field,
+replayed from a captured hipGraph of 100 sweeps, with the F/theta check
+(reunitarisation, F, theta in FP64) every 100 sweeps -- the FP64 phase that
+takes most of the time of the mixed-precision fix. The steps continue one
+fix of the input. value = site updates per second over the timed steps
+(V x sweeps / time); the roofline object reports the FP64 12-real sweep
+kernel (HIP events around its launches in the timed steps).
+
+Beside the steps, run once each and timed in full: the mixed-precision fix
+(FP32 12-real with g tracked until theta < 1e-6, FP64 projection and
+transformation, FP64 12-real until theta < 1e-14) and the pure-FP64 fix of the
+same input to theta < 1e-14, giving the mixed-vs-FP64 time to theta and the
+final-F difference; the same pair on the 32^4 beta = 6.0 configuration
+(300 sweeps, seed 2), whose FP64 field (403 MB) the Infinity Cache partly
+holds; the storage variants; bandwidth probes; and the CPU oracle timed on a
+bounded sample.
 """
 import argparse
 import json
@@ -55,10 +63,13 @@ def parse():
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the sweeps between checks one by one instead of replaying a "
                          "captured hipGraph")
-    ap.add_argument("--workload", default="landau32",
-                    choices=("landau32", "mixed48", "coulomb", "batch", "scan", "mag"),
-                    help="landau32 (default, the benchmark line): 32^4 beta 6.0 mixed fix; "
-                         "mixed48: 48^4 beta 6.2 mixed vs FP64; coulomb: 32^3x64 beta 6.0 with "
+    ap.add_argument("--block", type=int, default=1000,
+                    help="landau48: sweeps per benchmark step")
+    ap.add_argument("--workload", default="landau48",
+                    choices=("landau48", "landau32", "coulomb", "batch", "scan", "mag"),
+                    help="landau48 (default, the benchmark line): 48^4 beta 6.2, steps are "
+                         "1000-sweep blocks of the FP64 fix, plus the full mixed and FP64 fixes; "
+                         "landau32: 32^4 beta 6.0, each step a full mixed fix; coulomb: 32^3x64 beta 6.0 with "
                          "3000 annealing steps then the mixed Coulomb fix; batch: 64 Haar copies "
                          "each of 16^4, 24^4, 12^3x24 with 2000 annealing steps then the mixed fix; "
                          "scan: 32^4 sweeps and time against the precision switch, omega and the "
@@ -484,6 +495,208 @@ def probe_main(args):
     print(json.dumps(res), flush=True)
 
 
+def timed_fix(ctx, torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t0
+
+
+def kernel_roofline(kms, kn, V, bytes_per_site, kname, dims):
+    """achieved algorithmic bandwidth of a sweep kernel from pooled HIP-event
+    timings (total ms, launches)"""
+    per_launch = (V // 2) * bytes_per_site
+    avg_ms = kms / max(kn, 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": hbm_traffic(kname, dims),
+            "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 3), "launches": kn,
+            "bytes_per_launch": per_launch}
+
+
+def tune_phases(ctx, gf, canon, pairs, gauge):
+    tuning = {}
+    for g, f in pairs:
+        ctx.pack(g, canon, f)
+        best, ms = ctx.autotune(g, gauge, U_like=f)
+        name = ("fp32" if g.prec == gf.FP32 else "fp64") + ("_r12" if g.storage == gf.R12 else "_r18")
+        tuning[name] = {"lanes_per_site": best[0], "nontemporal": best[1],
+                        "us_per_half_sweep": {f"tps{k[0]}_nt{k[1]}": round(v * 1e3, 2)
+                                              for k, v in ms.items()}}
+        log(f"autotune {name}: {tuning[name]}")
+    return tuning
+
+
+def mixed_vs_fp64(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi, params, V):
+    """the full mixed fix and the full FP64 fix of the same input, each timed"""
+    ctx.pack(ghi, canon, U_hi)
+    r, t_mixed = timed_fix(ctx, torch, lambda: ctx.fix_mixed(U_lo, glo, U_hi, ghi, gf.LANDAU,
+                                                             params))
+    log(f"mixed: {r.sweeps} sweeps ({r.sweeps_lo} FP32) in {t_mixed:.2f} s, theta {r.theta:.3e}")
+    ctx.pack(ghi, canon, U_hi)
+    r64, t64 = timed_fix(ctx, torch, lambda: ctx.fix(U_hi, ghi, gf.LANDAU, params))
+    log(f"fp64: {r64.sweeps} sweeps in {t64:.2f} s, theta {r64.theta:.3e}")
+    return r, t_mixed, r64, t64, {
+        "mixed": {"time_ms": round(1e3 * t_mixed, 1), "sweeps": r.sweeps,
+                  "sweeps_fp32": r.sweeps_lo, "status": r.status, "F": r.F, "theta": r.theta,
+                  "site_updates_per_s": round(V * r.sweeps / t_mixed, 0)},
+        "fp64_only": {"time_ms": round(1e3 * t64, 1), "sweeps": r64.sweeps, "status": r64.status,
+                      "F": r64.F, "theta": r64.theta,
+                      "site_updates_per_s": round(V * r64.sweeps / t64, 0)},
+        "mixed_speedup_vs_fp64": round(t64 / t_mixed, 4),
+        "final_F_rel_diff_mixed_vs_fp64": abs(r.F - r64.F) / abs(r64.F)}
+
+
+def landau32_secondary(ctx, torch, gf, inputs, args):
+    """32^4 beta 6.0 (300 sweeps, seed 2): mixed and FP64 fixes to theta < 1e-14
+    and the FP64 sweep kernel's rate, which the Infinity Cache assists here."""
+    dims = (32, 32, 32, 32)
+    V = 32 ** 4
+    canon = inputs.gpu_heatbath(dims, 6.0, 300, 2, progress=100)
+    glo = gf.Geom.make(dims, gf.FP32, gf.R12)
+    ghi = gf.Geom.make(dims, gf.FP64, gf.R12)
+    U_lo, U_hi = ctx.empty_field(glo), ctx.empty_field(ghi)
+    tuning = tune_phases(ctx, gf, canon, ((glo, U_lo), (ghi, U_hi)), gf.LANDAU)
+    params = gf.fix_params(omega=args.omega, theta_target=1e-14, theta_switch=1e-6,
+                           max_sweeps=args.max_sweeps, check_every=args.check_every,
+                           flags=gf.FLAG_TIMING | gf.FLAG_GRAPH)
+    r, t_mixed, r64, t64, out = mixed_vs_fp64(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi,
+                                              params, V)
+    tps, nt = ctx.sweep_variant_for(ghi)
+    kname = "k_update_half<double,6,0,UpdOR,%d,%d,false>" % (tps, nt)
+    roof = kernel_roofline(r64.kernel_ms[1], r64.kernel_launches[1], V, 16 * 12 * 8, kname, dims)
+    roof["infinity_cache_assisted"] = True
+    out.update({"lattice": list(dims), "beta": 6.0, "roofline_fp64_sweep": roof,
+                "autotune": tuning})
+    del U_lo, U_hi, canon
+    return out
+
+
+def headline_main(args):
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1209_4008_amd as gf
+
+    dims = (48, 48, 48, 48)
+    beta, therm, seed = 6.2, 400, 3
+    V = int(np.prod(dims))
+    torch.cuda.set_device(0)
+    ctx = gf.Context(0)
+    log("device", torch.cuda.get_device_name(0), "lattice", dims)
+    t0 = time.time()
+    canon = inputs.gpu_heatbath(dims, beta, therm, seed, progress=100)
+    torch.cuda.synchronize()
+    log(f"heatbath input ready in {time.time() - t0:.1f} s")
+    g64c = gf.Geom.make(dims, gf.FP64, gf.R18)
+    P = ctx.empty_out(1)
+    tmp = ctx.empty_field(g64c)
+    ctx.pack(g64c, canon, tmp)
+    ctx.plaquette(tmp, g64c, P)
+    plaq = P.item()
+    del tmp
+    log(f"plaquette {plaq:.6f}")
+    glo = gf.Geom.make(dims, gf.FP32, gf.R12)
+    ghi = gf.Geom.make(dims, gf.FP64, gf.R12)
+    U_lo, U_hi = ctx.empty_field(glo), ctx.empty_field(ghi)
+    tuning = {} if args.no_tune else tune_phases(ctx, gf, canon, ((glo, U_lo), (ghi, U_hi)),
+                                                 gf.LANDAU)
+    flags = gf.FLAG_TIMING | (0 if args.no_graph else gf.FLAG_GRAPH)
+    # a step: args.block sweeps of the FP64 fix of the input (theta_target 0:
+    # the block always runs in full), checks every check_every sweeps
+    block = gf.fix_params(omega=args.omega, theta_target=0.0, max_sweeps=args.block,
+                          check_every=args.check_every, flags=flags)
+    ctx.pack(ghi, canon, U_hi)
+    for k in range(args.warmup):
+        r = ctx.fix(U_hi, ghi, gf.LANDAU, block)
+        log(f"warmup {k}: {r.sweeps} sweeps, theta {r.theta:.3e}, wall {r.wall_ms:.1f} ms")
+    torch.cuda.synchronize()
+    results = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        results.append(ctx.fix(U_hi, ghi, gf.LANDAU, block))
+        log(f"step {k}: {results[-1].sweeps} sweeps, theta {results[-1].theta:.3e}, "
+            f"F {results[-1].F:.12f}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+    sweeps = sum(r.sweeps for r in results)
+    value = V * sweeps / elapsed
+    tps, nt = ctx.sweep_variant_for(ghi)
+    kname = "k_update_half<double,6,0,UpdOR,%d,%d,false>" % (tps, nt)
+    roofline = kernel_roofline(sum(r.kernel_ms[1] for r in results),
+                               sum(r.kernel_launches[1] for r in results), V, 16 * 12 * 8,
+                               kname, dims)
+    log("roofline", roofline)
+
+    full_params = gf.fix_params(omega=args.omega, theta_target=args.theta_target,
+                                theta_switch=args.theta_switch,
+                                max_sweeps=max(args.max_sweeps, 60000),
+                                check_every=args.check_every, flags=flags)
+    extras = {}
+    r, t_mixed, r64, t64, cmp = mixed_vs_fp64(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi,
+                                              full_params, V)
+    extras.update(cmp)
+    extras["mixed_fp64_phase_roofline"] = kernel_roofline(r.kernel_ms[1], r.kernel_launches[1],
+                                                          V, 16 * 12 * 8, kname, dims)
+    del U_lo, U_hi
+    if not args.no_extras:
+        extras["variants"] = variant_rates(ctx, torch, gf, canon, dims, args.omega, n=50)
+        extras.update(stream_probes(ctx, torch))
+        for probe in ("copy", "rmw"):
+            key = probe + "_GBps"
+            if extras.get(key):
+                roofline["frac_of_measured_" + probe] = round(roofline["achieved"] / extras[key], 4)
+        extras["landau32"] = landau32_secondary(ctx, torch, gf, inputs, args)
+        l32 = extras["landau32"]["roofline_fp64_sweep"]
+        if extras.get("copy_GBps"):
+            l32["frac_of_measured_copy"] = round(l32["achieved"] / extras["copy_GBps"], 4)
+    extras["autotune"] = tuning
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(canon, dims, args)
+        if not args.no_extras:
+            extras.update(cpu_extras(canon, dims, args, ctx, torch, gf, sweeps_1t=1))
+        if cpu and cpu.get("value"):
+            n = r64.sweeps
+            extras["oracle_fp64_time_to_theta_extrapolated"] = {
+                "s": round(V * n / cpu["value"], 1), "sweeps": n,
+                "basis": "FP64 sweeps of the GPU's pure-FP64 run x V / the oracle's "
+                         "site-updates/s on %d host threads (extrapolated, not run)" % cpu["cores"]}
+    out = {
+        "metric": "Landau OR site-updates/s, HBM GB/s %peak; mixed vs FP64 time-to-theta<1e-14",
+        "value": round(value, 1),
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "landau-gauge-fix 48x48x48x48 wilson-heatbath beta=6.2 (400 sweeps, "
+                               "seed 3): each step %d sweeps of the fp64-r12 fix (omega %g, check "
+                               "every %d, hipGraph); beside it the full mixed fp32-r12 -> fp64-r12 "
+                               "(switch %g) and pure fp64-r12 fixes to theta<%g"
+                               % (args.block, args.omega, args.check_every, args.theta_switch,
+                                  args.theta_target),
+                   "lattice": list(dims), "beta": beta, "omega": args.omega,
+                   "check_every": args.check_every, "plaquette": round(plaq, 6),
+                   "sweeps_per_step": sweeps / args.steps,
+                   "gflops_2253": round(value * FLOP_PER_SITE / 1e9, 1)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    out.update(extras)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -504,9 +717,9 @@ def main():
     if args.workload == "mag":
         mag_main(args)
         return
-    if args.workload == "mixed48":
-        args.dims, args.beta, args.seed, args.therm = "48,48,48,48", 6.2, 3, 400
-        args.max_sweeps = max(args.max_sweeps, 60000)
+    if args.workload == "landau48":
+        headline_main(args)
+        return
     import numpy as np
     import torch
 
@@ -702,7 +915,7 @@ def cpu_baseline(canon, dims, args):
                      "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}}
 
 
-def cpu_extras(canon, dims, args, ctx, torch, gf):
+def cpu_extras(canon, dims, args, ctx, torch, gf, sweeps_1t=2):
     """The oracle on one host thread (2 sweeps of the same input), and the
     8^4 configuration 0 fixed to theta < 1e-12 in FP64 by the oracle (all host
     threads) and by the GPU (12 reals, same cadence)."""
@@ -718,14 +931,14 @@ def cpu_extras(canon, dims, args, ctx, torch, gf):
     oracle.set_num_threads(1)
     try:
         t0 = time.perf_counter()
-        for _ in range(2):
+        for _ in range(sweeps_1t):
             oracle.sweep(U, oracle.LANDAU, 0, args.omega)
             oracle.sweep(U, oracle.LANDAU, 1, args.omega)
         dt = time.perf_counter() - t0
     finally:
         oracle.set_num_threads(threads)
-    out["cpu_oracle_1_thread"] = {"site_updates_per_s": round(2 * V / dt, 1),
-                                  "sample": "2 FP64 sweeps of the benchmark input"}
+    out["cpu_oracle_1_thread"] = {"site_updates_per_s": round(sweeps_1t * V / dt, 1),
+                                  "sample": "%d FP64 sweeps of the benchmark input" % sweeps_1t}
     d0 = (8, 8, 8, 8)
     U0 = inputs.config0(d0, 0.3, 1)
     ref = U0.copy()

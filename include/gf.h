@@ -184,6 +184,35 @@ gf_status gf_anneal_sweep(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gau
 gf_status gf_philox(gf_ctx* ctx, const uint32_t* ctr_dev, uint64_t seed, uint32_t* out_dev,
                     int64_t n);
 
+/* ---- FP32 updates that track the site transformation ---------------------- */
+/* The gauge-transformation field that the FP32 phase of gf_fix_mixed
+ * accumulates (Sec. 1, eq. (4): the result of a gauge fixing is the input
+ * transformed by one g(x) per site): FP32, rows 0 and 1 of g(x) (row 2 =
+ * conj(row0 x row1)), tiled like a 12-real device field with one direction:
+ *   elem(p, c, h) at offset p*6*Vp + (h/128)*128*6 + c*128 + h%128, c = 3a + b.
+ * Host-only: its size in bytes, 96 Vp; 0 if geom is invalid. */
+size_t gf_gauge_bytes(const gf_geom* geom);
+/* G <- 1 at every site (the padding sites included). */
+gf_status gf_gauge_unit(gf_ctx* ctx, const gf_geom* geom, void* G);
+/* G -> canonical complex128 g[s][a][b] (9 complex per site, row 2 rebuilt in
+ * FP64) in device memory. */
+gf_status gf_gauge_unpack(gf_ctx* ctx, const gf_geom* geom, const void* G, double* g_canon_dev);
+/* gf_sweep, gf_heatbath_half and gf_micro_half on an FP32 field that also
+ * accumulate each updated site's whole transformation Gtot (the product of
+ * its three subgroup factors) into G: g(x) <- Gtot g(x), rows 0 and 1 then
+ * re-orthonormalised in FP32. Starting from G = 1, any sequence of such calls
+ * leaves U equal to the input transformed by G (eq. (4)), up to FP32
+ * rounding. geom must be FP32 (else GF_ERR_UNSUPPORTED); G (gf_gauge_bytes of
+ * geom) must not overlap U. The heatbath and microcanonical calls reject
+ * GF_MAG; gf_sweep_tracked takes all gauges. */
+gf_status gf_sweep_tracked(gf_ctx* ctx, void* U, void* G, const gf_geom* geom, int32_t gauge,
+                           int32_t parity, double omega);
+gf_status gf_heatbath_half_tracked(gf_ctx* ctx, void* U, void* G, const gf_geom* geom,
+                                   int32_t gauge, int32_t parity, double T, uint64_t seed,
+                                   uint64_t sweep);
+gf_status gf_micro_half_tracked(gf_ctx* ctx, void* U, void* G, const gf_geom* geom,
+                                int32_t gauge, int32_t parity);
+
 /* ---- tuning --------------------------------------------------------------- */
 /* Variant of the sweep kernels for one (precision, storage) pair on this
  * context: tps = lanes per site (1, 2 or 4; with k lanes each lane owns the

@@ -97,6 +97,13 @@ SIGNATURES = {
     "gf_anneal_sweep": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.c_double, C.c_uint64,
                                     C.c_uint64, C.c_int32]),
     "gf_philox": (C.c_int32, [_vp, _dp, C.c_uint64, _dp, C.c_int64]),
+    "gf_gauge_bytes": (C.c_size_t, [_gp]),
+    "gf_gauge_unit": (C.c_int32, [_vp, _gp, _dp]),
+    "gf_gauge_unpack": (C.c_int32, [_vp, _gp, _dp, _dp]),
+    "gf_sweep_tracked": (C.c_int32, [_vp, _dp, _dp, _gp, C.c_int32, C.c_int32, C.c_double]),
+    "gf_heatbath_half_tracked": (C.c_int32, [_vp, _dp, _dp, _gp, C.c_int32, C.c_int32,
+                                             C.c_double, C.c_uint64, C.c_uint64]),
+    "gf_micro_half_tracked": (C.c_int32, [_vp, _dp, _dp, _gp, C.c_int32, C.c_int32]),
     "gf_set_sweep_variant": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "gf_get_sweep_variant": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int32)]),
@@ -134,6 +141,10 @@ def lib():
 
 def field_bytes(geom):
     return int(lib().gf_field_bytes(C.byref(geom)))
+
+
+def gauge_bytes(geom):
+    return int(lib().gf_gauge_bytes(C.byref(geom)))
 
 
 def check_geom(geom):
@@ -182,6 +193,12 @@ class Context:
     # ---- memory helpers (torch as allocator) -------------------------------
     def empty_field(self, geom):
         n = field_bytes(geom)
+        if n == 0:
+            raise GFError(ERR_ARG, "invalid geometry")
+        return self.torch.empty(n, dtype=self.torch.uint8, device="cuda")
+
+    def empty_gauge(self, geom):
+        n = gauge_bytes(geom)
         if n == 0:
             raise GFError(ERR_ARG, "invalid geometry")
         return self.torch.empty(n, dtype=self.torch.uint8, device="cuda")
@@ -241,6 +258,25 @@ class Context:
     def anneal_sweep(self, U, geom, gauge, T, seed, sweep, n_micro):
         return self._check(lib().gf_anneal_sweep(self.h, _ptr(U), C.byref(geom), int(gauge),
                                                  float(T), int(seed), int(sweep), int(n_micro)))
+
+    def gauge_unit(self, geom, G):
+        return self._check(lib().gf_gauge_unit(self.h, C.byref(geom), _ptr(G)))
+
+    def gauge_unpack(self, geom, G, g_canon):
+        return self._check(lib().gf_gauge_unpack(self.h, C.byref(geom), _ptr(G), _ptr(g_canon)))
+
+    def sweep_tracked(self, U, G, geom, gauge, parity, omega):
+        return self._check(lib().gf_sweep_tracked(self.h, _ptr(U), _ptr(G), C.byref(geom),
+                                                  int(gauge), int(parity), float(omega)))
+
+    def heatbath_half_tracked(self, U, G, geom, gauge, parity, T, seed, sweep):
+        return self._check(lib().gf_heatbath_half_tracked(self.h, _ptr(U), _ptr(G), C.byref(geom),
+                                                          int(gauge), int(parity), float(T),
+                                                          int(seed), int(sweep)))
+
+    def micro_half_tracked(self, U, G, geom, gauge, parity):
+        return self._check(lib().gf_micro_half_tracked(self.h, _ptr(U), _ptr(G), C.byref(geom),
+                                                       int(gauge), int(parity)))
 
     def philox(self, ctr, seed, out, n):
         return self._check(lib().gf_philox(self.h, _ptr(ctr), int(seed), _ptr(out), int(n)))

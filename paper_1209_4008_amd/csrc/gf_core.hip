@@ -186,6 +186,32 @@ gf_status gf_convert(gf_ctx* c, const gf_geom* s, const void* src, const gf_geom
   return launch_check(c, "gf_convert");
 }
 
+size_t gf_gauge_bytes(const gf_geom* geom) {
+  if (!geom_ok(geom)) return 0;
+  const uint64_t V = (uint64_t)geom->nt * geom->nz * geom->ny * geom->nx;
+  return (size_t)(2 * 6 * padded_half(V / 2) * 2 * sizeof(float));
+}
+
+gf_status gf_gauge_unit(gf_ctx* c, const gf_geom* g, void* G) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_gauge_unit");
+  if (!G) return fail(c, GF_ERR_ARG, "gf_gauge_unit: NULL pointer");
+  const Lat L = make_lat(g);
+  hipLaunchKernelGGL((k_fill_unit<float, 6, 1>), dim3(blocks_for(L.vp), 2), dim3(kBlock), 0,
+                     c->stream, (v2<float>*)G, L.vp);
+  return launch_check(c, "gf_gauge_unit");
+}
+
+gf_status gf_gauge_unpack(gf_ctx* c, const gf_geom* g, const void* G, double* dst) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_gauge_unpack");
+  if (!G || !dst) return fail(c, GF_ERR_ARG, "gf_gauge_unpack: NULL pointer");
+  const Lat L = make_lat(g);
+  hipLaunchKernelGGL((k_unpack_gauge<float>), dim3(blocks_for(2ull * L.vh)), dim3(kBlock), 0,
+                     c->stream, (const v2<float>*)G, dst, L);
+  return launch_check(c, "gf_gauge_unpack");
+}
+
 gf_status gf_reunitarize(gf_ctx* c, void* U, const gf_geom* g) {
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_reunitarize");

@@ -438,3 +438,14 @@ gf_status sweep_sr_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32
                            uint64_t sweep);
 gf_status anneal_step_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32_t gauge,
                               double T, uint64_t seed, uint64_t sweep, int32_t n_micro);
+
+// validation shared by the tracked entry points
+#define CHECK_TRACKED(c, U, G, g, what)                                                  \
+  do {                                                                                   \
+    if (!(U) || !(G)) return fail((c), GF_ERR_ARG, "%s: NULL pointer", what);            \
+    if ((g)->prec != GF_FP32)                                                            \
+      return fail((c), GF_ERR_UNSUPPORTED, "%s: FP32 fields only", what);                \
+    const char *a_ = (const char*)(U), *b_ = (const char*)(G);                           \
+    if (a_ < b_ + gf_gauge_bytes(g) && b_ < a_ + gf_field_bytes(g))                      \
+      return fail((c), GF_ERR_ARG, "%s: field and gauge field overlap", what);           \
+  } while (0)

@@ -1255,6 +1255,26 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const v2<T>* __restrict__ src
   }
 }
 
+// gauge-transformation field (rows 0 and 1 of g, ND = 1) -> canonical
+// complex128 g[s][3][3], row 2 rebuilt in FP64; grid ceil(V/kBlock)
+template <typename Tg>
+__global__ __launch_bounds__(kBlock) void k_unpack_gauge(const v2<Tg>* __restrict__ G,
+                                                         double* __restrict__ dst, const Lat L) {
+  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= 2 * L.vh) return;
+  const uint32_t h = s >> 1;
+  const Site S = site_of(L, h, 0);
+  const int p = (int)((S.t + S.z + S.y + (s & 1u)) & 1u);
+  Su3<double> A;
+  load_link_f64<Tg, 6>(G + link_offset<6, 1>(L.vp, p, 0, h), A);
+  double* q = dst + (size_t)s * 18;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    q[2 * c] = A.e[c / 3][c % 3].re;
+    q[2 * c + 1] = A.e[c / 3][c % 3].im;
+  }
+}
+
 // the unit field in the device layout (scratch fields of the autotuner, the
 // gauge-transformation field of the mixed-precision driver, ND = 1); grid.y =
 // 2 * ND (parity, direction), padding sites included (grid.x covers vp)

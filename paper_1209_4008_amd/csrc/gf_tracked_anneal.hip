@@ -32,3 +32,30 @@ gf_status anneal_step_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, in
       if ((st = update_tracked(c, U, Gx, g, gauge, p, mc, "tracked microcanonical")) != GF_OK) return st;
   return GF_OK;
 }
+
+gf_status gf_heatbath_half_tracked(gf_ctx* c, void* U, void* G, const gf_geom* g, int32_t gauge,
+                                   int32_t parity, double T, uint64_t seed, uint64_t sweep) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_heatbath_half_tracked");
+  CHECK_GAUGE_PARITY(c, gauge, parity, "gf_heatbath_half_tracked");
+  REJECT_MAG(c, gauge, "gf_heatbath_half_tracked");
+  CHECK_TRACKED(c, U, G, g, "gf_heatbath_half_tracked");
+  if (!(T > 0.0) || !std::isfinite(T))
+    return fail(c, GF_ERR_ARG, "gf_heatbath_half_tracked: T must be > 0");
+  UpdHB<float> hb;
+  hb.temp = (float)T;
+  hb.k0 = (uint32_t)seed;
+  hb.k1 = (uint32_t)(seed >> 32);
+  hb.sweep = (uint32_t)sweep;
+  return update_tracked(c, U, G, g, gauge, parity, hb, "gf_heatbath_half_tracked");
+}
+
+gf_status gf_micro_half_tracked(gf_ctx* c, void* U, void* G, const gf_geom* g, int32_t gauge,
+                                int32_t parity) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_micro_half_tracked");
+  CHECK_GAUGE_PARITY(c, gauge, parity, "gf_micro_half_tracked");
+  REJECT_MAG(c, gauge, "gf_micro_half_tracked");
+  CHECK_TRACKED(c, U, G, g, "gf_micro_half_tracked");
+  return update_tracked(c, U, G, g, gauge, parity, UpdMicro<float>(), "gf_micro_half_tracked");
+}

@@ -85,3 +85,63 @@ def sites_links(dims, sites):
             sb = ((b[0] * nz + b[3]) * ny + b[2]) * nx + b[1]
             out.append((sb, mu))
     return out
+
+
+def back_index(dims):
+    """b[s, mu] = canonical index of s - mu (periodic)"""
+    nt, nz, ny, nx = dims
+    t, z, y, x = np.indices(dims)
+    out = np.empty(tuple(dims) + (4,), dtype=np.int64)
+    for mu, (dt, dz, dy, dx) in enumerate([(1, 0, 0, 0), (0, 0, 0, 1), (0, 0, 1, 0),
+                                           (0, 1, 0, 0)]):
+        out[..., mu] = ((((t - dt) % nt) * nz + (z - dz) % nz) * ny + (y - dy) % ny) * nx + \
+            (x - dx) % nx
+    return out.reshape(-1, 4)
+
+
+def site_errors(dims, got, ref, parity):
+    """(sites of `parity`, max |got - ref| over each site's 8 links)"""
+    V = int(np.prod(dims))
+    el = np.abs(got.reshape(V, 4, 3, 3) - ref.reshape(V, 4, 3, 3)).max(axis=(2, 3))
+    b = back_index(dims)
+    t, z, y, x = np.indices(dims)
+    sites = np.flatnonzero(((t + z + y + x) % 2).reshape(-1) == parity)
+    fw = el[sites].max(axis=1)
+    bw = el[b[sites], np.arange(4)[None, :]].max(axis=1)
+    return sites, np.maximum(fw, bw)
+
+
+def eight_links(U, dims, s, b):
+    """U_mu(s), mu = 0..3, then U_mu(s - mu): the links a site update moves"""
+    V = int(np.prod(dims))
+    U4 = U.reshape(V, 4, 3, 3)
+    return np.concatenate([U4[s], U4[b[s], np.arange(4)]])
+
+
+def heatbath_sites_check(dims, U_in, got, ref, gauge, T, seed, sweep, sites, bar, tau, what):
+    """Heatbath half-sweep result `got` (GPU) against `ref` (oracle, from U_in)
+    at the given sites of one parity. A site within `bar` passes; a site
+    beyond it must have a borderline Kennedy-Pendleton trial (margin < tau,
+    oracle.heatbath_site_outcomes) and match one of the outcomes that deciding
+    such trials either way gives. Returns the number of borderline sites."""
+    import oracle as O
+    b = back_index(dims)
+    border = 0
+    worst = 0.0
+    for s in sites:
+        s = int(s)
+        g8 = eight_links(got, dims, s, b)
+        e = np.abs(g8 - eight_links(ref, dims, s, b)).max()
+        if e <= bar:
+            worst = max(worst, e)
+            continue
+        outs, mm = O.heatbath_site_outcomes(U_in, gauge, T, seed, sweep, s, tau)
+        assert len(outs) > 1, (what, "site", s, "has no borderline trial (smallest margin",
+                               mm, ") yet differs by", e)
+        best = min(np.abs(g8 - o).max() for o in outs)
+        assert best <= bar, (what, "site", s, "matches none of", len(outs),
+                             "outcomes; closest", best)
+        border += 1
+    say(what, f"max err at exactly decided sites {worst:.2e};",
+        f"borderline sites {border} of {len(sites)}")
+    return border

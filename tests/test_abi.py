@@ -53,6 +53,10 @@ def test_geometry_validation_and_sizes():
         assert gf.check_geom(bad) == gf.ERR_ARG
         assert gf.field_bytes(bad) == 0
     assert gf.lib().gf_check_geom(None) == gf.ERR_ARG
+    # gauge-transformation field: FP32 rows 0 and 1 (6 complex) per padded site
+    assert gf.gauge_bytes(gf.Geom.make((6, 4, 2, 10), gf.FP32, gf.R12)) == 2 * 256 * 6 * 8
+    assert gf.gauge_bytes(gf.Geom.make((32,) * 4, gf.FP32, gf.R18)) == 32 ** 4 * 6 * 8
+    assert gf.gauge_bytes(gf.Geom.make((7, 8, 8, 8))) == 0
 
 
 def test_calls_without_context_are_rejected_on_host():

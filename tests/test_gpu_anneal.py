@@ -6,7 +6,8 @@ import pytest
 import inputs
 import oracle as O
 import paper_1209_4008_amd as gf
-from gpu_helpers import TOL, download, host_canon, oracle_input, say, site_parity, sites_links, upload
+from gpu_helpers import (TOL, download, heatbath_sites_check, host_canon, oracle_input, say,
+                         site_parity, sites_links, upload)
 
 pytestmark = pytest.mark.gpu
 
@@ -142,19 +143,24 @@ def test_coulomb_full_size_sampled(ctx, prec):
         got = download(ctx, f, g).reshape(V, 4, 3, 3)
         ref = oracle_input(U, prec, gf.R12)
         sites = [int(s) for s in cand if site_parity(dims, s) == 0][:256]
-        if kind == "hb":
-            O.heatbath_sites(ref, gf.COULOMB, 1.45, 4, 0, sites)
-        else:
-            O.update_sites(ref, gf.COULOMB, 1.7, sites)
-        r4 = ref.reshape(V, 4, 3, 3)
-        errs = [np.abs(got[s, mu] - r4[s, mu]).max() for s, mu in sites_links(dims, sites)]
-        tol = TOL[prec] if kind == "or" else (1e-12 if prec == gf.FP64 else 1e-3)
         if kind == "hb" and prec == gf.FP32:
-            # FP32 draws may take a different accept/reject decision than the
-            # FP64 oracle at a few sites; the rest agree to FP32 rounding
-            assert np.mean(np.array(errs) <= 1e-4) > 0.95
+            # per site to the FP32 bar; a site whose FP32 draw decided a
+            # borderline trial the other way must match one of the outcomes
+            # the oracle enumerates for such decisions
+            ref_in = ref.copy()
+            O.heatbath_sites(ref, gf.COULOMB, 1.45, 4, 0, sites)
+            border = heatbath_sites_check(dims, ref_in, got, ref, gf.COULOMB, 1.45, 4, 0, sites,
+                                          TOL[prec], 1e-5, "coulomb full size FP32 heatbath")
+            assert border <= 2, border
+            del ref_in
         else:
-            assert max(errs) <= tol, (kind, max(errs))
+            if kind == "hb":
+                O.heatbath_sites(ref, gf.COULOMB, 1.45, 4, 0, sites)
+            else:
+                O.update_sites(ref, gf.COULOMB, 1.7, sites)
+            r4 = ref.reshape(V, 4, 3, 3)
+            errs = [np.abs(got[s, mu] - r4[s, mu]).max() for s, mu in sites_links(dims, sites)]
+            assert max(errs) <= TOL[prec], (kind, max(errs))
         del ref, got
     if prec == gf.FP64:
         # per-timeslice F and theta of the input against the oracle on the whole field
