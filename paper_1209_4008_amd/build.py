@@ -13,6 +13,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgf.so")
+# the debug library: the site-update kernels with every link-element access
+# counted (checks of the RED/BLACK decomposition); not part of libgf
+DEBUG_LIB = os.path.join(HERE, "libgf_debug.so")
 OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GF_OFFLOAD_ARCH", "gfx950")
@@ -21,6 +24,10 @@ CSRC = os.path.join(HERE, "csrc")
 
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def debug_sources():
+    return sorted(glob.glob(os.path.join(CSRC, "debug", "*.hip")))
 
 
 def _flags(resource_usage=False):
@@ -37,30 +44,29 @@ def _flags(resource_usage=False):
 
 
 def _newest_input():
-    deps = glob.glob(os.path.join(CSRC, "*.hpp")) + [os.path.join(ROOT, "include", "gf.h")]
+    deps = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
     return max(os.path.getmtime(p) for p in deps)
 
 
 def build(verbose: bool = False, resource_usage: bool = False, incremental: bool = False,
           jobs: int = 0) -> str:
     """Compile every unit (incremental=True: only units older than their
-    source or a header) and link libgf.so."""
+    source or a header) and link libgf.so and the debug library."""
     os.makedirs(OBJ, exist_ok=True)
-    srcs = sources()
     hdr_time = _newest_input()
+    targets = [(LIB, sources(), []), (DEBUG_LIB, debug_sources(), ["-DGF_ACCESS_COUNT"])]
     todo = []
-    objs = []
-    for s in srcs:
-        o = os.path.join(OBJ, os.path.basename(s)[:-4] + ".o")
-        objs.append(o)
-        if (not incremental or not os.path.exists(o) or os.path.getmtime(o) < os.path.getmtime(s)
-                or os.path.getmtime(o) < hdr_time):
-            todo.append((s, o))
+    for lib, srcs, defs in targets:
+        for s in srcs:
+            o = os.path.join(OBJ, os.path.basename(s)[:-4] + ".o")
+            if (not incremental or not os.path.exists(o) or os.path.getmtime(o) < os.path.getmtime(s)
+                    or os.path.getmtime(o) < hdr_time):
+                todo.append((s, o, defs))
     flags = _flags(resource_usage)
 
-    def compile_one(so):
-        s, o = so
-        cmd = [HIPCC] + flags + ["-c", s, "-o", o + ".tmp"]
+    def compile_one(job):
+        s, o, defs = job
+        cmd = [HIPCC] + flags + defs + ["-c", s, "-o", o + ".tmp"]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -74,11 +80,13 @@ def build(verbose: bool = False, resource_usage: bool = False, incremental: bool
         for err in ex.map(compile_one, todo):
             if resource_usage and err:
                 print(err, flush=True)
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    for lib, srcs, _ in targets:
+        objs = [os.path.join(OBJ, os.path.basename(s)[:-4] + ".o") for s in srcs]
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", lib + ".tmp"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(lib + ".tmp", lib)
     return LIB
 
 

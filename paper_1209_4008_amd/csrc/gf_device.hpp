@@ -170,12 +170,43 @@ __host__ __device__ __forceinline__ size_t link_offset(uint32_t vp, int p, int m
 //   kNTStores  stores streamed, loads cached (fields the cache partly holds).
 constexpr int kNTNone = 0, kNTAll = 1, kNTStores = 2;
 
+#ifdef GF_ACCESS_COUNT
+// Access-count builds only (the debug library that checks the RED/BLACK
+// decomposition): every element a link load or store touches is counted in a
+// shadow array, at the element's offset from the start of its field; two
+// fields (the links and the gauge-transformation field).
+struct AccessCount {
+  const char* base[2];
+  size_t bytes[2];
+  unsigned* reads[2];
+  unsigned* writes[2];
+};
+static __device__ AccessCount gf_access_count;
+
+template <typename T>
+__device__ __forceinline__ void count_access(const v2<T>* p, bool write) {
+  const char* c = (const char*)p;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const char* b = gf_access_count.base[r];
+    if (b && c >= b && c < b + gf_access_count.bytes[r]) {
+      unsigned* cnt = write ? gf_access_count.writes[r] : gf_access_count.reads[r];
+      atomicAdd(cnt + (size_t)(c - b) / sizeof(v2<T>), 1u);
+    }
+  }
+}
+#define GF_COUNT_ACCESS(T, p, w) count_access<T>((p), (w))
+#else
+#define GF_COUNT_ACCESS(T, p, w) ((void)0)
+#endif
+
 // q points at component 0 of the link.
 template <typename T, int NC, int NT = kNTNone>
 __device__ __forceinline__ void load_link(const v2<T>* __restrict__ q, Su3<T>& A) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const v2<T>* p = q + c * kTile;
+    GF_COUNT_ACCESS(T, p, false);
     const v2<T> v = (NT == kNTAll) ? __builtin_nontemporal_load(p) : *p;
     A.e[c / 3][c % 3] = cx<T>(v.x, v.y);
   }
@@ -190,6 +221,7 @@ __device__ __forceinline__ void store_link(v2<T>* __restrict__ q, const Su3<T>& 
     v.x = A.e[c / 3][c % 3].re;
     v.y = A.e[c / 3][c % 3].im;
     v2<T>* p = q + c * kTile;
+    GF_COUNT_ACCESS(T, p, true);
     if (NT != kNTNone)
       __builtin_nontemporal_store(v, p);
     else
