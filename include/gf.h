@@ -157,6 +157,18 @@ gf_status gf_theta(gf_ctx* ctx, const void* U, const gf_geom* geom, int32_t gaug
 /* F and theta in one pass over the field (what the drivers use). */
 gf_status gf_measure(gf_ctx* ctx, const void* U, const gf_geom* geom, int32_t gauge,
                      double* F_dev, double* theta_dev);
+/* gf_measure for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, with the per-block partial sums in a fixed 4 MiB
+ * device array of the library (one per GPU, set up by gf_create, kept until
+ * the process ends) instead of context memory that gf_measure may allocate.
+ * Allocates nothing. Lattices needing more than 2^19 partial sums
+ * (2 * ceil(V / (2 nt 256)) * nt; about 2^27 sites) are rejected with
+ * GF_ERR_ARG. All calls on one GPU share the array: calls that overlap in time
+ * on one GPU (several streams or threads) race and must be serialised by the
+ * caller. */
+gf_status gf_measure_static(gf_ctx* ctx, const void* U, const gf_geom* geom, int32_t gauge,
+                            double* F_dev, double* theta_dev);
 /* Project every link onto SU(3) by Gram-Schmidt in FP64 (rows 0, 1
  * orthonormalised; row 2 = conj(row0 x row1) for R18). */
 gf_status gf_reunitarize(gf_ctx* ctx, void* U, const gf_geom* geom);

@@ -89,6 +89,7 @@ SIGNATURES = {
     "gf_functional": (C.c_int32, [_vp, _dp, _gp, C.c_int32, _dp]),
     "gf_theta": (C.c_int32, [_vp, _dp, _gp, C.c_int32, _dp]),
     "gf_measure": (C.c_int32, [_vp, _dp, _gp, C.c_int32, _dp, _dp]),
+    "gf_measure_static": (C.c_int32, [_vp, _dp, _gp, C.c_int32, _dp, _dp]),
     "gf_reunitarize": (C.c_int32, [_vp, _dp, _gp]),
     "gf_plaquette": (C.c_int32, [_vp, _dp, _gp, _dp]),
     "gf_heatbath_half": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.c_int32, C.c_double,
@@ -233,6 +234,10 @@ class Context:
     def measure(self, U, geom, gauge, F=None, theta=None):
         return self._check(lib().gf_measure(self.h, _ptr(U), C.byref(geom), int(gauge),
                                             _ptr(F), _ptr(theta)))
+
+    def measure_static(self, U, geom, gauge, F=None, theta=None):
+        return self._check(lib().gf_measure_static(self.h, _ptr(U), C.byref(geom), int(gauge),
+                                                   _ptr(F), _ptr(theta)))
 
     def functional(self, U, geom, gauge, F):
         return self._check(lib().gf_functional(self.h, _ptr(U), C.byref(geom), int(gauge),

@@ -2,6 +2,8 @@
 // bandwidth probes.
 #include "gf_host.hpp"
 
+#include <mutex>
+
 char g_create_err[512] = "no error";
 
 // ---------------------------------------------------------------------------
@@ -97,6 +99,8 @@ gf_status gf_selftest_host(void) {
 
 const char* gf_last_error(const gf_ctx* ctx) { return ctx ? ctx->err : g_create_err; }
 
+static gf_status scratch_setup(int device);  // the static measurement scratch, below
+
 gf_status gf_create(int device, void* hip_stream, gf_ctx** out) {
   if (!out) return fail(nullptr, GF_ERR_ARG, "gf_create: out is NULL");
   *out = nullptr;
@@ -107,6 +111,10 @@ gf_status gf_create(int device, void* hip_stream, gf_ctx** out) {
     return fail(nullptr, GF_ERR_ARG, "gf_create: device %d out of range (%d devices)", device, n);
   if (hipSetDevice(device) != hipSuccess)
     return fail(nullptr, GF_ERR_DEVICE, "gf_create: hipSetDevice(%d) failed", device);
+  {
+    const gf_status st = scratch_setup(device);
+    if (st != GF_OK) return st;
+  }
   gf_ctx* c = new gf_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
@@ -224,32 +232,44 @@ gf_status gf_reunitarize(gf_ctx* c, void* U, const gf_geom* g) {
   return launch_check(c, "gf_reunitarize");
 }
 
-gf_status measure_impl(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge,
-                              double* F, double* th) {
+// the measurement kernels with the per-block partial sums in `partial`
+// (2 * blocks_for(st) * nt doubles)
+static gf_status measure_launch(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge,
+                                double* F, double* th, double* partial) {
   const Lat L = make_lat(g);
   const uint32_t bpt = blocks_for(L.st);
-  gf_status st = ensure_partial(c, (size_t)2 * bpt * L.nt);
-  if (st != GF_OK) return st;
   const dim3 grid(bpt, L.nt);
   with_type(g, [&]<typename T, int NC>() {
     if (gauge == GF_LANDAU)
       hipLaunchKernelGGL((k_measure<T, NC, kLandau>), grid, dim3(kBlock), 0, c->stream,
-                         (const v2<T>*)U, L, c->partial);
+                         (const v2<T>*)U, L, partial);
     else if (gauge == GF_COULOMB)
       hipLaunchKernelGGL((k_measure<T, NC, kCoulomb>), grid, dim3(kBlock), 0, c->stream,
-                         (const v2<T>*)U, L, c->partial);
+                         (const v2<T>*)U, L, partial);
     else
       hipLaunchKernelGGL((k_measure_mag<T, NC>), grid, dim3(kBlock), 0, c->stream,
-                         (const v2<T>*)U, L, c->partial);
+                         (const v2<T>*)U, L, partial);
   });
   const double V = 2.0 * L.vh, Vs = V / L.nt;
   if (gauge != GF_COULOMB)
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial,
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, c->stream, (const double*)partial,
                        bpt * L.nt, 12.0 * V, 3.0 * V, F, th);
   else
     hipLaunchKernelGGL(k_finish, dim3(L.nt), dim3(kBlock), 0, c->stream,
-                       (const double*)c->partial, bpt, 9.0 * Vs, 3.0 * Vs, F, th);
+                       (const double*)partial, bpt, 9.0 * Vs, 3.0 * Vs, F, th);
   return launch_check(c, "gf_measure");
+}
+
+static size_t measure_partials(const gf_geom* g) {
+  const Lat L = make_lat(g);
+  return (size_t)2 * blocks_for(L.st) * L.nt;
+}
+
+gf_status measure_impl(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, double* F,
+                       double* th) {
+  gf_status st = ensure_partial(c, measure_partials(g));
+  if (st != GF_OK) return st;
+  return measure_launch(c, U, g, gauge, F, th, c->partial);
 }
 
 gf_status gf_measure(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, double* F,
@@ -260,6 +280,52 @@ gf_status gf_measure(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, 
     return fail(c, GF_ERR_ARG, "gf_measure: bad gauge");
   if (!U || (!F && !th)) return fail(c, GF_ERR_ARG, "gf_measure: NULL pointer");
   return measure_impl(c, U, g, gauge, F, th);
+}
+
+// ---------------------------------------------------------------------------
+// measurement without allocation: the partial sums go to a fixed device array
+// of this library, one per GPU, for callers that cannot allocate
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchDoubles = (size_t)1 << 19;  // 4 MiB per device
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// device address of `scratch` on each device, looked up once per device at
+// context creation with that device current (the array's name in host code is
+// a host-side stand-in, not a device address)
+constexpr int kScratchDevices = 64;
+static double* g_scratch_ptr[kScratchDevices];
+static std::mutex g_scratch_mu;
+
+static gf_status scratch_setup(int device) {
+  if (device < 0 || device >= kScratchDevices) return GF_OK;  // no static scratch there
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return GF_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(nullptr, GF_ERR_HIP, "gf_create: hipGetSymbolAddress(scratch) on device %d: %s",
+                device, hipGetErrorString(e));
+  g_scratch_ptr[device] = (double*)p;
+  return GF_OK;
+}
+
+gf_status gf_measure_static(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, double* F,
+                            double* th) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_measure_static");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB && gauge != GF_MAG)
+    return fail(c, GF_ERR_ARG, "gf_measure_static: bad gauge");
+  if (!U || (!F && !th)) return fail(c, GF_ERR_ARG, "gf_measure_static: NULL pointer");
+  const size_t need = measure_partials(g);
+  if (need > kScratchDoubles)
+    return fail(c, GF_ERR_ARG,
+                "gf_measure_static: the lattice needs %zu partial sums, the static scratch holds "
+                "%zu (about 2^27 sites); use gf_measure",
+                need, kScratchDoubles);
+  double* p = (c->device >= 0 && c->device < kScratchDevices) ? g_scratch_ptr[c->device] : nullptr;
+  if (!p) return fail(c, GF_ERR_UNSUPPORTED, "gf_measure_static: no static scratch on device %d",
+                      c->device);
+  return measure_launch(c, U, g, gauge, F, th, p);
 }
 
 gf_status gf_functional(gf_ctx* c, const void* U, const gf_geom* g, int32_t gauge, double* F) {
