@@ -17,8 +17,7 @@ struct gf_batch {
   void* arena32 = nullptr;  // FP32 working fields
   void* arenaG = nullptr;   // gauge-transformation fields
   std::vector<size_t> off32, offG;
-  int* d_active = nullptr;
-  int* h_active = nullptr;  // pinned
+  std::vector<int> active;  // lattices still in the current phase
   double* d_out = nullptr;  // F[n], theta[n]
   double* h_out = nullptr;  // pinned
   double* d_partial = nullptr;
@@ -29,15 +28,17 @@ struct gf_batch {
 
 namespace {
 
-// A batch sweeps all its fields in every launch, so with no variant set on
-// the context its built-in mode follows their total size (the 192-lattice
-// batch, 10.8 GB in FP64 12-real: streamed 5.25 against cached 4.73 TB/s).
+// A batch launch sweeps the fields of all the lattices still active, so with
+// no variant set on the context its built-in mode follows their total size
+// (the 192-lattice batch, 10.8 GB in FP64 12-real: streamed 5.25 against
+// cached 4.73 TB/s).
 int batch_nt(const gf_ctx* c, const gf_batch* b, bool lo) {
   const std::vector<gf_geom>& gs = lo ? b->g32 : b->g64;
   const int t = c->nt[gs[0].prec == GF_FP64][gs[0].storage == GF_R18];
   if (t >= 0) return t;
   size_t total = 0;
-  for (const gf_geom& g : gs) total += gf_field_bytes(&g);
+  for (int l = 0; l < b->n; ++l)
+    if (b->active[l]) total += gf_field_bytes(&gs[l]);
   return default_nt_bytes(total);
 }
 
@@ -47,12 +48,14 @@ struct TableSet {
   uint32_t blocks = 0;
 };
 
-// lattice table for one launch shape (threads per lattice = vh * tps)
+// table of the active lattices for one launch shape (threads per lattice =
+// vh * tps)
 template <typename T>
 TableSet<T> make_table(const gf_batch* b, bool lo, int tps) {
   TableSet<T> t;
   uint32_t blk = 0;
   for (int l = 0; l < b->n; ++l) {
+    if (!b->active[l]) continue;
     BatchEntry<T> e;
     e.L = b->lat[l];
     e.U = lo ? (v2<T>*)((char*)b->arena32 + b->off32[l]) : (v2<T>*)b->U64[l];
@@ -108,9 +111,8 @@ gf_status gf_batch_create(gf_ctx* c, int32_t n, const gf_geom* geoms, void* cons
   };
   if (hipMalloc(&b->arena32, s32) != hipSuccess) return cleanup(GF_ERR_NOMEM, "FP32 fields");
   if (hipMalloc(&b->arenaG, sG) != hipSuccess) return cleanup(GF_ERR_NOMEM, "g fields");
-  if (hipMalloc(&b->d_active, n * sizeof(int)) != hipSuccess ||
-      hipHostMalloc(&b->h_active, n * sizeof(int), hipHostMallocDefault) != hipSuccess ||
-      hipMalloc(&b->d_out, 2 * n * sizeof(double)) != hipSuccess ||
+  b->active.assign(n, 1);
+  if (hipMalloc(&b->d_out, 2 * n * sizeof(double)) != hipSuccess ||
       hipHostMalloc(&b->h_out, 2 * n * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return cleanup(GF_ERR_NOMEM, "control buffers");
   *out = b;
@@ -122,8 +124,6 @@ gf_status gf_batch_destroy(gf_batch* b) {
   if (b->c) (void)hipSetDevice(b->c->device);
   if (b->arena32) (void)hipFree(b->arena32);
   if (b->arenaG) (void)hipFree(b->arenaG);
-  if (b->d_active) (void)hipFree(b->d_active);
-  if (b->h_active) (void)hipHostFree(b->h_active);
   if (b->d_out) (void)hipFree(b->d_out);
   if (b->h_out) (void)hipHostFree(b->h_out);
   if (b->d_partial) (void)hipFree(b->d_partial);
@@ -157,10 +157,10 @@ gf_status upload_table(gf_batch* b, int k, const TableSet<T>& t, const BatchEntr
 
 template <typename T, int NC, class Upd, bool TRACK>
 void launch_batch_update(gf_ctx* c, int tps, int nt, const BatchEntry<T>* tab, int n, uint32_t blocks,
-                         const int* active, int parity, const Upd& upd) {
+                         int parity, const Upd& upd) {
   auto go = [&]<int TPS, int NT>() {
     hipLaunchKernelGGL((k_update_half_batch<T, NC, Upd, TPS, NT, TRACK>), dim3(blocks), dim3(kBlock),
-                       0, c->stream, tab, n, active, parity, upd);
+                       0, c->stream, tab, n, parity, upd);
   };
   auto go_tps = [&]<int NT>() {
     if (tps == 1) go.template operator()<1, NT>();
@@ -177,21 +177,46 @@ void launch_batch_update(gf_ctx* c, int tps, int nt, const BatchEntry<T>* tab, i
   }
 }
 
+// the launch tables of one phase over the active lattices: the sweep table
+// (tps lanes per site) and the measurement table (one thread per half index)
+template <typename T>
+struct PhaseTables {
+  TableSet<T> sweep, meas;
+  const BatchEntry<T>* d_sweep = nullptr;
+  const BatchEntry<T>* d_meas = nullptr;
+  int n = 0;   // entries (active lattices)
+  int nt = 0;  // nontemporal mode for their total size
+};
+
+template <typename T>
+gf_status build_tables(gf_batch* b, bool lo, int tps, PhaseTables<T>& pt) {
+  pt.sweep = make_table<T>(b, lo, tps);
+  pt.meas = make_table<T>(b, lo, 1);
+  pt.n = (int)pt.sweep.h.size();
+  pt.nt = batch_nt(b->c, b, lo);
+  gf_status st;
+  if (pt.n == 0) return GF_OK;
+  if ((st = upload_table(b, lo ? 0 : 2, pt.sweep, &pt.d_sweep)) != GF_OK) return st;
+  return upload_table(b, lo ? 1 : 3, pt.meas, &pt.d_meas);
+}
+
 // one batch phase (precision T, storage NC): checks and sweeps until every
-// lattice has theta < target or max_sweeps
+// lattice has theta < target or max_sweeps. A lattice leaves the phase at the
+// check that finds it converged (or out of sweeps); the tables are then
+// rebuilt over the lattices still active and the sweep block recaptured, so
+// that no launch covers a lattice that has left.
 template <typename T, int NC>
 gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double target, Timer& tm,
                       BatchPhase& ph) {
   gf_ctx* c = b->c;
   const int n = b->n;
   const gf_geom& gref = lo ? b->g32[0] : b->g64[0];
-  const int tps = ctx_tps(c, &gref), nt = batch_nt(c, b, lo);
-  const TableSet<T> ts = make_table<T>(b, lo, tps), tm1 = make_table<T>(b, lo, 1);
-  const BatchEntry<T>*d_sweep, *d_meas;
+  const int tps = ctx_tps(c, &gref);
+  b->active.assign(n, 1);
+  PhaseTables<T> pt;
   gf_status st;
-  if ((st = upload_table(b, lo ? 0 : 2, ts, &d_sweep)) != GF_OK) return st;
-  if ((st = upload_table(b, lo ? 1 : 3, tm1, &d_meas)) != GF_OK) return st;
-  const size_t need = 2 * (size_t)tm1.blocks;
+  if ((st = build_tables(b, lo, tps, pt)) != GF_OK) return st;
+  const size_t need = 2 * (size_t)pt.meas.blocks;
   if (need > b->partial_cap) {
     if (b->d_partial) HIP_OR_FAIL(c, hipFree(b->d_partial));
     b->d_partial = nullptr;
@@ -204,8 +229,6 @@ gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double targe
   ph.converged.assign(n, 0);
   ph.F.assign(n, 0.0);
   ph.theta.assign(n, 0.0);
-  for (int l = 0; l < n; ++l) b->h_active[l] = 1;
-  HIP_OR_FAIL(c, hipMemcpyAsync(b->d_active, b->h_active, n * sizeof(int), hipMemcpyHostToDevice, c->stream));
   UpdOR<T> upd;
   upd.omega = (T)p->omega;
   const bool sr = p->sr_prob > 0.0;
@@ -223,13 +246,13 @@ gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double targe
           us.k1 = (uint32_t)(p->seed >> 32);
           us.sweep = (uint32_t)(done + k);
           if (lo)
-            launch_batch_update<T, NC, UpdSR<T>, true>(c, tps, nt, d_sweep, n, ts.blocks, b->d_active, par, us);
+            launch_batch_update<T, NC, UpdSR<T>, true>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, us);
           else
-            launch_batch_update<T, NC, UpdSR<T>, false>(c, tps, nt, d_sweep, n, ts.blocks, b->d_active, par, us);
+            launch_batch_update<T, NC, UpdSR<T>, false>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, us);
         } else if (lo) {
-          launch_batch_update<T, NC, UpdOR<T>, true>(c, tps, nt, d_sweep, n, ts.blocks, b->d_active, par, upd);
+          launch_batch_update<T, NC, UpdOR<T>, true>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, upd);
         } else {
-          launch_batch_update<T, NC, UpdOR<T>, false>(c, tps, nt, d_sweep, n, ts.blocks, b->d_active, par, upd);
+          launch_batch_update<T, NC, UpdOR<T>, false>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, upd);
         }
       }
     return launch_check(c, "gf_batch_run: sweeps");
@@ -238,23 +261,24 @@ gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double targe
     // check: reunitarise (after the first), measure, copy back
     if (p->reunit_at_check && done > 0) {
       if ((st = tm.begin()) != GF_OK) return st;
-      hipLaunchKernelGGL((k_reunitarize_batch<T, NC>), dim3(tm1.blocks), dim3(kBlock), 0, c->stream,
-                         d_meas, n, (const int*)b->d_active);
+      hipLaunchKernelGGL((k_reunitarize_batch<T, NC>), dim3(pt.meas.blocks), dim3(kBlock), 0, c->stream,
+                         pt.d_meas, pt.n);
       if ((st = tm.end(3, 1)) != GF_OK) return st;
     }
     if ((st = tm.begin()) != GF_OK) return st;
-    hipLaunchKernelGGL((k_measure_batch<T, NC>), dim3(tm1.blocks), dim3(kBlock), 0, c->stream, d_meas, n,
-                       (const int*)b->d_active, b->d_partial);
-    hipLaunchKernelGGL((k_finish_batch<T>), dim3(n), dim3(kBlock), 0, c->stream, d_meas, n, tm1.blocks,
-                       (const int*)b->d_active, (const double*)b->d_partial, b->d_out, b->d_out + n);
+    hipLaunchKernelGGL((k_measure_batch<T, NC>), dim3(pt.meas.blocks), dim3(kBlock), 0, c->stream,
+                       pt.d_meas, pt.n, b->d_partial);
+    hipLaunchKernelGGL((k_finish_batch<T>), dim3(pt.n), dim3(kBlock), 0, c->stream, pt.d_meas, pt.n,
+                       pt.meas.blocks, (const double*)b->d_partial, b->d_out, b->d_out + n);
     if ((st = launch_check(c, "gf_batch_run: measure")) != GF_OK) return st;
     if ((st = tm.end(2, 2)) != GF_OK) return st;
     HIP_OR_FAIL(c, hipMemcpyAsync(b->h_out, b->d_out, 2 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     if ((st = tm.flush()) != GF_OK) return st;
     int remaining = 0;
+    bool retired = false;
     for (int l = 0; l < n; ++l) {
-      if (!b->h_active[l]) continue;
+      if (!b->active[l]) continue;
       const double F = b->h_out[l], th = b->h_out[n + l];
       if (!std::isfinite(F) || !std::isfinite(th))
         return fail(c, GF_ERR_NONFINITE, "gf_batch_run: lattice %d: non-finite F or theta", l);
@@ -264,15 +288,21 @@ gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double targe
       ph.sweeps[l] = done;
       if (th < target) {
         ph.converged[l] = 1;
-        b->h_active[l] = 0;
+        b->active[l] = 0;
+        retired = true;
       } else if (done >= p->max_sweeps) {
-        b->h_active[l] = 0;
+        b->active[l] = 0;
+        retired = true;
       } else {
         ++remaining;
       }
     }
     if (!remaining) return GF_OK;
-    HIP_OR_FAIL(c, hipMemcpyAsync(b->d_active, b->h_active, n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    if (retired) {
+      // the stream is idle (synchronised above): rewrite the tables in place
+      if ((st = build_tables(b, lo, tps, pt)) != GF_OK) return st;
+      sg.reset();
+    }
     const int32_t nsw = std::min(p->check_every, p->max_sweeps - done);
     if (use_graph && nsw == p->check_every && !sg.exec) {
       if (!c->capture) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
@@ -309,15 +339,11 @@ gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double targe
 template <int NC>
 gf_status batch_anneal(gf_batch* b, const gf_fix_params* p, Timer& tm) {
   gf_ctx* c = b->c;
-  const int n = b->n;
-  const int tps = ctx_tps(c, &b->g32[0]), nt = batch_nt(c, b, true);
-  const TableSet<float> ts = make_table<float>(b, true, tps), tm1 = make_table<float>(b, true, 1);
-  const BatchEntry<float>*d_sweep, *d_meas;
+  const int tps = ctx_tps(c, &b->g32[0]);
+  b->active.assign(b->n, 1);
+  PhaseTables<float> pt;
   gf_status st;
-  if ((st = upload_table(b, 0, ts, &d_sweep)) != GF_OK) return st;
-  if ((st = upload_table(b, 1, tm1, &d_meas)) != GF_OK) return st;
-  for (int l = 0; l < n; ++l) b->h_active[l] = 1;
-  HIP_OR_FAIL(c, hipMemcpyAsync(b->d_active, b->h_active, n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  if ((st = build_tables(b, true, tps, pt)) != GF_OK) return st;
   for (int32_t k = 0; k < p->sa_steps; ++k) {
     const double T = p->sa_steps > 1
                          ? p->sa_T0 + (p->sa_T1 - p->sa_T0) * (double)k / (double)(p->sa_steps - 1)
@@ -330,15 +356,15 @@ gf_status batch_anneal(gf_batch* b, const gf_fix_params* p, Timer& tm) {
     UpdMicro<float> mc;
     if ((st = tm.begin()) != GF_OK) return st;
     for (int par = 0; par < 2; ++par)
-      launch_batch_update<float, NC, UpdHB<float>, true>(c, tps, nt, d_sweep, n, ts.blocks, b->d_active, par, hb);
+      launch_batch_update<float, NC, UpdHB<float>, true>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, hb);
     for (int m = 0; m < p->sa_micro; ++m)
       for (int par = 0; par < 2; ++par)
-        launch_batch_update<float, NC, UpdMicro<float>, true>(c, tps, nt, d_sweep, n, ts.blocks, b->d_active, par, mc);
+        launch_batch_update<float, NC, UpdMicro<float>, true>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, mc);
     if ((st = launch_check(c, "gf_batch_run: annealing")) != GF_OK) return st;
     if ((st = tm.end(4, 2 + 2 * (int64_t)p->sa_micro)) != GF_OK) return st;
     if (p->sa_reunit_every > 0 && (k + 1) % p->sa_reunit_every == 0) {
-      hipLaunchKernelGGL((k_reunitarize_batch<float, NC>), dim3(tm1.blocks), dim3(kBlock), 0, c->stream,
-                         d_meas, n, (const int*)b->d_active);
+      hipLaunchKernelGGL((k_reunitarize_batch<float, NC>), dim3(pt.meas.blocks), dim3(kBlock), 0, c->stream,
+                         pt.d_meas, pt.n);
       if ((st = launch_check(c, "gf_batch_run: reunitarise")) != GF_OK) return st;
     }
   }

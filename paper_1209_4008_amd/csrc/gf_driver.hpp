@@ -89,10 +89,18 @@ struct SweepGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int32_t n = 0;
-  ~SweepGraph() {
+  SweepGraph() = default;
+  SweepGraph(const SweepGraph&) = delete;
+  SweepGraph& operator=(const SweepGraph&) = delete;
+  // drop the captured block (its launches name tables or shapes that changed)
+  void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    n = 0;
   }
+  ~SweepGraph() { reset(); }
 };
 
 inline void init_result(gf_fix_result* r) {

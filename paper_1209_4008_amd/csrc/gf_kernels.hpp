@@ -158,6 +158,46 @@ struct UpdMicro {
   }
 };
 
+// ---------------------------------------------------------------------------
+// lane exchange inside a quad (DPP quad_perm). The TPS lanes of a site are
+// consecutive and aligned, so a site's lanes always sit in one quad.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ int quad_perm_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+// value of lane (l ^ MASK): quad_perm selectors xor 1 -> [1,0,3,2] = 0xB1,
+// xor 2 -> [2,3,0,1] = 0x4E
+template <int MASK>
+__device__ __forceinline__ int quad_xor_i(int v) {
+  return quad_perm_i<(MASK == 1) ? 0xB1 : 0x4E>(v);
+}
+template <int MASK>
+__device__ __forceinline__ float quad_xor(float v) {
+  return __builtin_bit_cast(float, quad_xor_i<MASK>(__builtin_bit_cast(int, v)));
+}
+template <int MASK>
+__device__ __forceinline__ double quad_xor(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = quad_xor_i<MASK>((int)(uint32_t)b);
+  const int hi = quad_xor_i<MASK>((int)(uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+// value of lane SRC of the calling lane's own site (TPS lanes per site)
+template <int TPS, int SRC>
+__device__ __forceinline__ int site_bcast_i(int v) {
+  if constexpr (TPS == 1)
+    return v;
+  else if constexpr (TPS == 2)
+    return quad_perm_i<SRC | (SRC << 2) | ((2 + SRC) << 4) | ((2 + SRC) << 6)>(v);
+  else
+    return quad_perm_i<SRC * 0x55>(v);
+}
+template <int TPS, int SRC>
+__device__ __forceinline__ float site_bcast(float v) {
+  return __builtin_bit_cast(float, site_bcast_i<TPS, SRC>(__builtin_bit_cast(int, v)));
+}
+
 // Heatbath with weight exp(Re tr[g K]/T): with g = X what, Re tr = |w| X0, so
 // X0 is drawn with density ~ sqrt(1 - X0^2) exp(alpha X0), alpha = |w|/T, by
 // Kennedy & Pendleton (Phys. Lett. B 156 (1985) 393), and (X1, X2, X3) is
@@ -192,31 +232,32 @@ template <typename T>
 struct UpdHB {
   T temp;
   uint32_t k0, k1, sweep;
-  __device__ __forceinline__ HBDraws<T> draws(uint32_t site) const {
+  // subgroup sg's first trial and direction: out = (num, u3, cos theta,
+  // sin theta, cos phi, sin phi)
+  __device__ __forceinline__ void draw_one(uint32_t site, uint32_t sg, T out[6]) const {
     const T two_pi = (T)6.283185307179586476925286766559;
-    HBDraws<T> d;
-#pragma unroll
-    for (int sg = 0; sg < 3; ++sg) {
-      const U4 r = philox4x32_10(site, sweep, kTagKP | (uint32_t)sg, 0u, k0, k1);
-      const T u0 = unit_open<T>(r.v[0]), u1 = unit_open<T>(r.v[1]);
-      const T u2 = unit_open<T>(r.v[2]);
-      const T cs = hb_cos(two_pi * u1);
-      d.num[sg] = -(hb_log(u0) + cs * cs * hb_log(u2));
-      d.u3[sg] = unit_open<T>(r.v[3]);
-      const U4 q = philox4x32_10(site, sweep, kTagDir | (uint32_t)sg, 0u, k0, k1);
-      const T d0 = unit_open<T>(q.v[0]), d1 = unit_open<T>(q.v[1]);
-      d.cth[sg] = 2 * d0 - 1;
-      d.sth[sg] = sqrt_t(fmax(T(0), 1 - d.cth[sg] * d.cth[sg]));
-      const T phi = two_pi * d1;
-      d.cph[sg] = hb_cos(phi);
-      d.sph[sg] = hb_sin(phi);
-    }
-    return d;
+    const U4 r = philox4x32_10(site, sweep, kTagKP | sg, 0u, k0, k1);
+    const T u0 = unit_open<T>(r.v[0]), u1 = unit_open<T>(r.v[1]);
+    const T u2 = unit_open<T>(r.v[2]);
+    const T cs = hb_cos(two_pi * u1);
+    out[0] = -(hb_log(u0) + cs * cs * hb_log(u2));
+    out[1] = unit_open<T>(r.v[3]);
+    const U4 q = philox4x32_10(site, sweep, kTagDir | sg, 0u, k0, k1);
+    const T d0 = unit_open<T>(q.v[0]), d1 = unit_open<T>(q.v[1]);
+    out[2] = 2 * d0 - 1;
+    out[3] = sqrt_t(fmax(T(0), 1 - out[2] * out[2]));
+    const T phi = two_pi * d1;
+    out[4] = hb_cos(phi);
+    out[5] = hb_sin(phi);
   }
   // the step with the first trial and the direction taken from d (the same
-  // numbers operator() draws, combined in the same order)
+  // numbers operator() draws, combined in the same order). The further
+  // trials are shared by the site's TPS lanes: in each round lane r tries
+  // attempt att + r, and the site takes the first accepted attempt in order
+  // (every lane gets the owning lane's value bit for bit).
+  template <int TPS>
   __device__ __forceinline__ bool with_draws(const T w[4], uint32_t site, int sg, T s[4],
-                                             const HBDraws<T>& d) const {
+                                             const HBDraws<T>& d, int r) const {
     const T n2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
     if (!(n2 > Tiny<T>::value)) return false;
     const T n = sqrt_t(n2);
@@ -227,13 +268,41 @@ struct UpdHB {
       const T l2 = d.num[sg] / (2 * alpha);
       if (d.u3[sg] * d.u3[sg] <= 1 - l2) lam2 = l2;
     }
-    for (uint32_t att = 1; lam2 < 0 && att < kMaxAttempts; ++att) {
-      const U4 r = philox4x32_10(site, sweep, kTagKP | (uint32_t)sg, att, k0, k1);
-      const T u0 = unit_open<T>(r.v[0]), u1 = unit_open<T>(r.v[1]);
-      const T u2 = unit_open<T>(r.v[2]), u3 = unit_open<T>(r.v[3]);
-      const T cs = hb_cos(two_pi * u1);
-      const T l2 = -(hb_log(u0) + cs * cs * hb_log(u2)) / (2 * alpha);
-      if (u3 * u3 <= 1 - l2) lam2 = l2;
+    for (uint32_t att = 1; lam2 < 0 && att < kMaxAttempts; att += TPS) {
+      const uint32_t a = att + (uint32_t)r;
+      T l2 = 0;
+      int acc = 0;
+      if (a < kMaxAttempts) {
+        const U4 q = philox4x32_10(site, sweep, kTagKP | (uint32_t)sg, a, k0, k1);
+        const T u0 = unit_open<T>(q.v[0]), u1 = unit_open<T>(q.v[1]);
+        const T u2 = unit_open<T>(q.v[2]), u3 = unit_open<T>(q.v[3]);
+        const T cs = hb_cos(two_pi * u1);
+        l2 = -(hb_log(u0) + cs * cs * hb_log(u2)) / (2 * alpha);
+        acc = u3 * u3 <= 1 - l2;
+      }
+      if constexpr (TPS == 1) {
+        if (acc) lam2 = l2;
+      } else {
+#pragma unroll
+        for (int j = TPS - 1; j >= 0; --j) {  // the earliest accepted attempt wins
+          int acc_j;
+          T l2_j;
+          if (j == 0) {
+            acc_j = site_bcast_i<TPS, 0>(acc);
+            l2_j = site_bcast<TPS, 0>(l2);
+          } else if (j == 1) {
+            acc_j = site_bcast_i<TPS, 1>(acc);
+            l2_j = site_bcast<TPS, 1>(l2);
+          } else if (j == 2) {
+            acc_j = site_bcast_i<TPS, (TPS > 2 ? 2 : 0)>(acc);
+            l2_j = site_bcast<TPS, (TPS > 2 ? 2 : 0)>(l2);
+          } else {
+            acc_j = site_bcast_i<TPS, (TPS > 3 ? 3 : 0)>(acc);
+            l2_j = site_bcast<TPS, (TPS > 3 ? 3 : 0)>(l2);
+          }
+          if (acc_j) lam2 = l2_j;
+        }
+      }
     }
     if (lam2 < 0) return false;  // attempt cap: subgroup left unchanged
     const T rad = 2 * sqrt_t(lam2 * (1 - lam2));
@@ -286,6 +355,38 @@ struct UpdHB {
     return true;
   }
 };
+
+// The draws of a site before its links arrive, shared by its TPS lanes: lane
+// r draws subgroups r, r + TPS, ... (the lanes of a wave do this at the same
+// time), and the lanes then exchange them, so a lane makes ceil(3 / TPS)
+// subgroup draws instead of 3. A lane without a subgroup of its own repeats
+// subgroup 2 (kept uniform, unused).
+template <int TPS, int SG>
+__device__ __forceinline__ void take_draws(HBDraws<float>& d, const float own[6]) {
+  constexpr int o = SG % TPS;  // the lane that drew subgroup SG
+  d.num[SG] = site_bcast<TPS, o>(own[0]);
+  d.u3[SG] = site_bcast<TPS, o>(own[1]);
+  d.cth[SG] = site_bcast<TPS, o>(own[2]);
+  d.sth[SG] = site_bcast<TPS, o>(own[3]);
+  d.cph[SG] = site_bcast<TPS, o>(own[4]);
+  d.sph[SG] = site_bcast<TPS, o>(own[5]);
+}
+
+template <int TPS>
+__device__ __forceinline__ HBDraws<float> split_draws(const UpdHB<float>& u, uint32_t site, int r) {
+  constexpr int STEPS = (3 + TPS - 1) / TPS;
+  float own[STEPS][6];
+#pragma unroll
+  for (int k = 0; k < STEPS; ++k) {
+    const int sg = k * TPS + r;
+    u.draw_one(site, (uint32_t)(sg < 3 ? sg : 2), own[k]);
+  }
+  HBDraws<float> d;
+  take_draws<TPS, 0>(d, own[0]);
+  take_draws<TPS, 1>(d, own[1 / TPS]);
+  take_draws<TPS, 2>(d, own[2 / TPS]);
+  return d;
+}
 
 // Gram-Schmidt on rows 0 and 1 in the field's precision. A 12-real link
 // rebuilds row 2 = conj(row0 x row1), so a norm error of the stored rows
@@ -351,41 +452,44 @@ __device__ __forceinline__ void subgroup_step(Su3<T>& K, Su3<T>& G, uint32_t sit
   left_su2<T, I, J>(G, s);
 }
 
+// draws a site's update can take before its links arrive: the FP32 heatbath's
+// (see HBDraws, split_draws); none for the other updates
+struct NoDraws {};
+template <int TPS, class Upd>
+__device__ __forceinline__ NoDraws pre_draws(const Upd&, uint32_t, int) {
+  return {};
+}
+template <int TPS>
+__device__ __forceinline__ HBDraws<float> pre_draws(const UpdHB<float>& u, uint32_t site, int r) {
+  return split_draws<TPS>(u, site, r);
+}
+template <int TPS, typename T, class Upd>
+__device__ __forceinline__ bool call_upd(const Upd& u, const T w[4], uint32_t site, int sg, T s[4],
+                                         const NoDraws&, int) {
+  return u(w, site, sg, s);
+}
+template <int TPS>
+__device__ __forceinline__ bool call_upd(const UpdHB<float>& u, const float w[4], uint32_t site,
+                                         int sg, float s[4], const HBDraws<float>& d, int r) {
+  return u.template with_draws<TPS>(w, site, sg, s, d, r);
+}
+
 // The three subgroup steps with Gtot = G3 G2 G1 built directly: G1 is an
 // embedding in rows/cols (0,1), G2 G1 only mixes rows 0 and 2 of it, and
 // only the last step is a general row operation. (IEEE arithmetic cannot
 // drop the products with the zeros of a unit matrix, so the general form
 // would do that work.) A declined step (degenerate subgroup) uses s = 1,
-// whose row operation is exact.
-// draws a site's update can take before its links arrive: the FP32 heatbath's
-// (see HBDraws); none for the other updates
-struct NoDraws {};
-template <class Upd>
-__device__ __forceinline__ NoDraws pre_draws(const Upd&, uint32_t) {
-  return {};
-}
-__device__ __forceinline__ HBDraws<float> pre_draws(const UpdHB<float>& u, uint32_t site) {
-  return u.draws(site);
-}
-template <typename T, class Upd>
-__device__ __forceinline__ bool call_upd(const Upd& u, const T w[4], uint32_t site, int sg, T s[4],
-                                         const NoDraws&) {
-  return u(w, site, sg, s);
-}
-__device__ __forceinline__ bool call_upd(const UpdHB<float>& u, const float w[4], uint32_t site,
-                                         int sg, float s[4], const HBDraws<float>& d) {
-  return u.with_draws(w, site, sg, s, d);
-}
-
-template <typename T, class Upd, class D = NoDraws>
+// whose row operation is exact. r is the calling lane's place among its
+// site's TPS lanes.
+template <typename T, class Upd, int TPS = 1, class D = NoDraws>
 __device__ __forceinline__ void build_G(Su3<T>& K, Su3<T>& G, uint32_t site, const Upd& upd,
-                                        const D& dr = D()) {
+                                        const D& dr = D(), int r = 0) {
   T w[4], s[4], t[4];
   subgroup_w<T, 0, 1>(K, w);
-  if (!call_upd(upd, w, site, 0, s, dr)) s[0] = 1, s[1] = s[2] = s[3] = 0;
+  if (!call_upd<TPS>(upd, w, site, 0, s, dr, r)) s[0] = 1, s[1] = s[2] = s[3] = 0;
   left_su2<T, 0, 1>(K, s);
   subgroup_w<T, 0, 2>(K, w);
-  if (!call_upd(upd, w, site, 1, t, dr)) t[0] = 1, t[1] = t[2] = t[3] = 0;
+  if (!call_upd<TPS>(upd, w, site, 1, t, dr, r)) t[0] = 1, t[1] = t[2] = t[3] = 0;
   left_su2<T, 0, 2>(K, t);
   // G2 G1: rows of G1 = (g00, g01, 0), (g10, g11, 0), (0, 0, 1)
   const Cx<T> g00 = cx(s[0], s[3]), g01 = cx(s[2], s[1]);
@@ -402,28 +506,7 @@ __device__ __forceinline__ void build_G(Su3<T>& K, Su3<T>& G, uint32_t site, con
   G.e[2][1] = cmul(t20, g01);
   G.e[2][2] = t22;
   subgroup_w<T, 1, 2>(K, w);
-  if (call_upd(upd, w, site, 2, s, dr)) left_su2<T, 1, 2>(G, s);
-}
-
-// ---------------------------------------------------------------------------
-// lane exchange inside a quad (DPP quad_perm): value of lane (l ^ MASK)
-// ---------------------------------------------------------------------------
-template <int MASK>
-__device__ __forceinline__ int quad_xor_i(int v) {
-  // quad_perm selectors: xor 1 -> [1,0,3,2] = 0xB1, xor 2 -> [2,3,0,1] = 0x4E
-  constexpr int ctrl = (MASK == 1) ? 0xB1 : 0x4E;
-  return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, false);
-}
-template <int MASK>
-__device__ __forceinline__ float quad_xor(float v) {
-  return __builtin_bit_cast(float, quad_xor_i<MASK>(__builtin_bit_cast(int, v)));
-}
-template <int MASK>
-__device__ __forceinline__ double quad_xor(double v) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const int lo = quad_xor_i<MASK>((int)(uint32_t)b);
-  const int hi = quad_xor_i<MASK>((int)(uint32_t)(b >> 32));
-  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+  if (call_upd<TPS>(upd, w, site, 2, s, dr, r)) left_su2<T, 1, 2>(G, s);
 }
 
 // sum of K over the TPS lanes of one site; every lane ends with the same bits
@@ -488,7 +571,7 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
     load_link<T, NC, NT>(U + link_offset<NC>(L.vp, 1 - parity, mu, hb[d]), Ub[d]);
   }
   const uint32_t site = 2 * h + S.xodd;
-  const auto dr = pre_draws(upd, site);  // while the loads are in flight
+  const auto dr = pre_draws<TPS>(upd, site, r);  // while the loads are in flight
   Su3<T> K;
   set_zero(K);
 #pragma unroll
@@ -509,7 +592,7 @@ __device__ __forceinline__ void site_half_update(v2<T>* __restrict__ U, const La
   }
   lane_sum<T, TPS>(K);
   Su3<T> G;
-  build_G<T, Upd>(K, G, site, upd, dr);
+  build_G<T, Upd, TPS>(K, G, site, upd, dr, r);
   if (TRACK && r == 0) {
     v2<T>* gp = Gx + link_offset<6, 1>(L.vp, parity, 0, h);
     Su3<T> gx, A;
@@ -808,8 +891,9 @@ __global__ __launch_bounds__(kBlock) void k_mag_half(v2<T>* __restrict__ U, cons
 
 // ---------------------------------------------------------------------------
 // batches of independent lattices (Gribov copies, uneven extents): one launch
-// covers every active lattice; lattice l owns the blocks
-// [first_block[l], first_block[l+1]).
+// covers the lattices of a table, entry k owning the blocks
+// [first_block[k], first_block[k+1]); the host rebuilds the table without the
+// lattices that have left the phase, so a launch covers active lattices only.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct BatchEntry {
@@ -861,13 +945,10 @@ __device__ __forceinline__ UpdSR<T> for_lattice(const UpdSR<T>& u, uint32_t l) {
 
 template <typename T, int NC, class Upd, int TPS, int NT, bool TRACK>
 __global__ __launch_bounds__(kBlock) void k_update_half_batch(const BatchEntry<T>* __restrict__ tab,
-                                                              const int n,
-                                                              const int* __restrict__ active,
-                                                              const int parity, const Upd upd) {
+                                                              const int n, const int parity,
+                                                              const Upd upd) {
   const uint32_t blk = sweep_block(parity);
-  const int l = batch_lattice(tab, n, blk);
-  if (!active[l]) return;
-  const BatchEntry<T> e = tab[l];
+  const BatchEntry<T> e = tab[batch_lattice(tab, n, blk)];
   site_half_update<T, NC, kLandau, Upd, TPS, NT, TRACK>(
       e.U, e.L, parity, for_lattice(upd, e.index), e.Gx,
       (blk - e.first_block) * kBlock + threadIdx.x, nullptr);
@@ -1009,12 +1090,9 @@ __global__ __launch_bounds__(kBlock) void k_measure_mag(const v2<T>* __restrict_
 template <typename T, int NC>
 __global__ __launch_bounds__(kBlock) void k_measure_batch(const BatchEntry<T>* __restrict__ tab,
                                                           const int n,
-                                                          const int* __restrict__ active,
                                                           double* __restrict__ partial) {
   __shared__ double lds[kBlock / 64];
-  const int l = batch_lattice(tab, n, blockIdx.x);
-  if (!active[l]) return;  // uniform per block
-  const BatchEntry<T> e = tab[l];
+  const BatchEntry<T> e = tab[batch_lattice(tab, n, blockIdx.x)];
   const Lat& L = e.L;
   const uint32_t h = (blockIdx.x - e.first_block) * kBlock + threadIdx.x;
   double f = 0, th = 0;
@@ -1058,20 +1136,18 @@ __global__ __launch_bounds__(kBlock) void k_measure_batch(const BatchEntry<T>* _
   }
 }
 
-// one block per lattice: F[l] = sum / (12 V_l), theta[l] = sum / (3 V_l) over
-// the lattice's blocks (active lattices only)
+// one block per table entry k: F[l] = sum / (12 V_l), theta[l] = sum / (3 V_l)
+// over the entry's blocks, l = its lattice number
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_finish_batch(const BatchEntry<T>* __restrict__ tab,
                                                          const int n, const uint32_t total_blocks,
-                                                         const int* __restrict__ active,
                                                          const double* __restrict__ partial,
                                                          double* __restrict__ F,
                                                          double* __restrict__ th) {
   __shared__ double lds[kBlock / 64];
-  const int l = blockIdx.x;
-  if (!active[l]) return;
-  const uint32_t b0 = tab[l].first_block;
-  const uint32_t b1 = (l + 1 < n) ? tab[l + 1].first_block : total_blocks;
+  const int k = blockIdx.x;
+  const uint32_t b0 = tab[k].first_block;
+  const uint32_t b1 = (k + 1 < n) ? tab[k + 1].first_block : total_blocks;
   double a = 0, b = 0;
   for (uint32_t k = b0 + threadIdx.x; k < b1; k += kBlock) {
     a += partial[2 * (size_t)k];
@@ -1080,9 +1156,9 @@ __global__ __launch_bounds__(kBlock) void k_finish_batch(const BatchEntry<T>* __
   a = block_sum(a, lds);
   b = block_sum(b, lds);
   if (threadIdx.x == 0) {
-    const double V = 2.0 * tab[l].L.vh;
-    F[l] = a / (12.0 * V);
-    th[l] = b / (3.0 * V);
+    const double V = 2.0 * tab[k].L.vh;
+    F[tab[k].index] = a / (12.0 * V);
+    th[tab[k].index] = b / (3.0 * V);
   }
 }
 
@@ -1292,15 +1368,11 @@ __global__ __launch_bounds__(kBlock) void k_fill_unit(v2<T>* __restrict__ U, con
   }
 }
 
-// bandwidth probes: 16-byte elements, one per thread
-// batched in-place reunitarisation of the active lattices (8 link blocks each)
+// batched in-place reunitarisation of the lattices of a table (8 link blocks each)
 template <typename T, int NC>
 __global__ __launch_bounds__(kBlock) void k_reunitarize_batch(const BatchEntry<T>* __restrict__ tab,
-                                                              const int n,
-                                                              const int* __restrict__ active) {
-  const int l = batch_lattice(tab, n, blockIdx.x);
-  if (!active[l]) return;
-  const BatchEntry<T> e = tab[l];
+                                                              const int n) {
+  const BatchEntry<T> e = tab[batch_lattice(tab, n, blockIdx.x)];
   const uint32_t h = (blockIdx.x - e.first_block) * kBlock + threadIdx.x;
   if (h >= e.L.vh) return;
 #pragma unroll 1
@@ -1355,6 +1427,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_gauge(v2<T>* __restrict__ U,
   }
 }
 
+// bandwidth probes: 16-byte elements, one per thread
 static __global__ __launch_bounds__(kBlock) void k_probe_copy(const double2* __restrict__ a,
                                                        double2* __restrict__ b, const size_t n) {
   const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
