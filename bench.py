@@ -166,6 +166,10 @@ def coulomb_main(args):
     for g, f in ((glo, U_lo), (ghi, U_hi)):
         ctx.pack(g, canon, f)
         ctx.autotune(g, gf.COULOMB, U_like=f)
+    # the annealing updates run in FP32 with g tracked; tuned at a mid-schedule T
+    ctx.pack(glo, canon, U_lo)
+    anneal_tuned = ctx.autotune_anneal(glo, gf.COULOMB, U_like=U_lo, T=0.7)
+    log("annealing variant", anneal_tuned)
 
     def run(extra_flags):
         ctx.pack(ghi, canon, U_hi)

@@ -206,6 +206,9 @@ gf_status gf_philox(gf_ctx* ctx, const uint32_t* ctr_dev, uint64_t seed, uint32_
 size_t gf_gauge_bytes(const gf_geom* geom);
 /* G <- 1 at every site (the padding sites included). */
 gf_status gf_gauge_unit(gf_ctx* ctx, const gf_geom* geom, void* G);
+/* Canonical complex128 g[s][a][b] in device memory (9 complex per site, an
+ * SU(3) matrix each) -> G (rows 0 and 1 rounded to FP32; row 2 is implied). */
+gf_status gf_gauge_pack(gf_ctx* ctx, const gf_geom* geom, const double* g_canon_dev, void* G);
 /* G -> canonical complex128 g[s][a][b] (9 complex per site, row 2 rebuilt in
  * FP64) in device memory. */
 gf_status gf_gauge_unpack(gf_ctx* ctx, const gf_geom* geom, const void* G, double* g_canon_dev);
@@ -233,31 +236,57 @@ gf_status gf_micro_half_tracked(gf_ctx* ctx, void* U, void* G, const gf_geom* ge
  * loads and stores as streaming, 2 to stream the stores only (loads cached;
  * pays when the cache holds part of the field between half-sweeps; the
  * overrelaxation and stochastic-relaxation sweeps, the annealing updates run
- * 2 as 1).
- * tps = 0 / nontemporal = -1 restore the built-in defaults: 4 lanes (FP64) or
- * 2 (FP32); nontemporal 0 for fields of at most 2 GiB (the Infinity Cache
- * then serves part of every half-sweep), 1 for larger ones. */
+ * 2 as 1). The context keeps two tables: the overrelaxation sweeps (every
+ * form, stochastic relaxation, GF_MAG; gf_set_sweep_variant) and the
+ * annealing updates (heatbath and microcanonical; gf_set_anneal_variant),
+ * each per (precision, storage) and per size class (fields of at most 2 GiB,
+ * larger ones). These calls set both size classes; the autotuners set the
+ * class of the field they time.
+ * tps = 0 / nontemporal = -1 restore the built-in defaults: 4 lanes for FP64;
+ * for FP32 2 lanes (sweeps) and 1 lane (annealing); nontemporal 0 for fields
+ * of at most 2 GiB (the Infinity Cache then serves part of every half-sweep),
+ * 1 for larger ones. */
 gf_status gf_set_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t tps,
                                int32_t nontemporal);
-/* The variant set for (prec, storage), or the built-in one for a field of at
- * most 2 GiB. */
+gf_status gf_set_anneal_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t tps,
+                                int32_t nontemporal);
+/* The sweep variant for (prec, storage) and a field of at most 2 GiB. */
 gf_status gf_get_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t* tps,
                                int32_t* nontemporal);
-/* The variant the sweeps of `geom`'s field use on this context (the set one,
- * else the built-in one for the field's size). */
+/* The variant the sweeps (resp. the annealing updates) of `geom`'s field use
+ * on this context: the set or tuned one of its size class, else the built-in
+ * one. */
 gf_status gf_sweep_variant_for(gf_ctx* ctx, const gf_geom* geom, int32_t* tps,
                                int32_t* nontemporal);
-/* Autotuner: times the overrelaxation half-sweep for geom (its extents,
- * precision and storage) for the nine variants (tps 1, 2, 4) x (nontemporal 0,
- * 1, 2) on a scratch field (allocated and freed inside the call) that starts as
- * a copy of U_like (a device field of geom; NULL: the unit field), keeps the
- * fastest on this context and returns it (the built-in variant when it is
- * within 5% of the fastest, so that repeated tunings agree). The caller's fields are not
- * modified. ms_out (NULL or 9 floats, index 3*nontemporal + log2(tps))
- * receives the mean time per half-sweep of each. Synchronises the context
- * stream. */
+gf_status gf_anneal_variant_for(gf_ctx* ctx, const gf_geom* geom, int32_t* tps,
+                                int32_t* nontemporal);
+/* Autotuner of the overrelaxation sweep for geom (its extents, precision and
+ * storage): on a scratch field (allocated and freed inside the call) that
+ * starts as a copy of U_like (a device field of geom; NULL: the unit field),
+ * each of the nine variants (tps 1, 2, 4) x (nontemporal 0, 1, 2) runs a
+ * block of RED/BLACK sweep pairs (omega 1.7) captured as a hipGraph, as the
+ * drivers replay theirs (about 2 ms of work per block); the nine blocks are
+ * replayed in turn for five rounds and each variant's time is the median of
+ * its rounds. The fastest is kept on this context for geom's precision,
+ * storage and size class, and returned. The caller's fields are not modified.
+ * ms_out (NULL or 9 floats, index 3*nontemporal + log2(tps)) receives the
+ * time per half-sweep of each. Synchronises the context stream. */
 gf_status gf_autotune(gf_ctx* ctx, const gf_geom* geom, int32_t gauge, const void* U_like,
                       int32_t* tps_out, int32_t* nt_out, float* ms_out);
+/* The same for the annealing updates (GF_LANDAU or GF_COULOMB): the unit of
+ * work is one annealing step at temperature T (heatbath RED and BLACK, one
+ * microcanonical sweep, the same draws in every replay); ms_out per
+ * half-sweep. */
+gf_status gf_autotune_anneal(gf_ctx* ctx, const gf_geom* geom, int32_t gauge, const void* U_like,
+                             double T, int32_t* tps_out, int32_t* nt_out, float* ms_out);
+/* Storage axis: packs the canonical FP64 field U_canon (device) into scratch
+ * fields of geom's extents and precision in 12 and 18 reals, tunes the sweep
+ * variants of each (gf_autotune, which keeps each one's best on the context)
+ * and returns in *storage_out the storage whose best variant sweeps the
+ * lattice fastest (GF_R12 or GF_R18); ms_out (NULL or 2 floats): the best
+ * time per half-sweep of each. geom->storage is ignored. */
+gf_status gf_autotune_storage(gf_ctx* ctx, const gf_geom* geom, int32_t gauge,
+                              const double* U_canon, int32_t* storage_out, float* ms_out);
 
 /* Bandwidth probe (measurement support): streams `bytes` (a multiple of 16)
  * with 16-byte accesses, one per thread. kind 0: copy src -> dst; kind 1:

@@ -43,6 +43,7 @@ def lib():
             "or_mag_local_max": (C.c_int, [d, i32p, C.c_int64, C.c_int, d]),
             "or_mag_sweep": (C.c_int, [d, i32p, C.c_int, C.c_double, C.c_int]),
             "or_mag_functional": (C.c_double, [d, i32p]),
+            "or_mag_site_gaps": (C.c_int, [d, i32p, C.c_int64, C.c_double, C.c_int, d]),
             "or_mag_theta": (C.c_double, [d, i32p]),
             "or_fix_coulomb_frozen": (C.c_int, [d, i32p, C.c_double, C.c_double, C.c_int32,
                                                 C.c_int32, C.c_int32, i32p, d, d, i32p]),
@@ -164,6 +165,15 @@ def mag_sweep(U, parity, omega, form=0):
     rc = lib().or_mag_sweep(_field(U), _dims(dims_of(U)), int(parity), float(omega), int(form))
     if rc != 0:
         raise ValueError("or_mag_sweep: bad arguments")
+
+
+def mag_site_gaps(U, s, omega, form=0):
+    gaps = np.zeros(3)
+    rc = lib().or_mag_site_gaps(_field(U), _dims(dims_of(U)), int(s), float(omega), int(form),
+                                _dptr(gaps))
+    if rc != 0:
+        raise ValueError("or_mag_site_gaps: bad arguments")
+    return gaps
 
 
 def mag_functional(U):

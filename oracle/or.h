@@ -129,6 +129,12 @@ int    or_mag_local_max(const double* U, const int32_t dims[4], int64_t s, int s
 /* One checkerboard half-sweep of MAG overrelaxation (maximiser raised to
  * omega in the given form, or_overrelax_form). */
 int    or_mag_sweep(double* U, const int32_t dims[4], int parity, double omega, int form);
+/* Relative gaps (l1 - l2)/|l1| between the two largest eigenvalues of the
+ * 3x3 block of M met at each of the three subgroup steps of the update of
+ * site s (as in or_mag_sweep with omega, form), on a copy of the field; 0 for
+ * a skipped step. A small gap: the maximiser is (nearly) not unique. */
+int    or_mag_site_gaps(const double* U, const int32_t dims[4], int64_t s, double omega,
+                        int form, double gaps[3]);
 /* F_MAG = R / (3 * 4 V) (1 when all links are diagonal). */
 double or_mag_functional(const double* U, const int32_t dims[4]);
 /* theta_MAG = (1/(3V)) sum_x sum_sg (M_01^2 + M_02^2): the squared gradient of

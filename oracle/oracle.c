@@ -1124,7 +1124,18 @@ void or_mag_matrix(const double* U, const int32_t dims[4], int64_t s, int sg, do
  * cyclic Jacobi rotations (Golub & Van Loan, Matrix Computations, Sec. 8.5):
  * each rotation zeroes one off-diagonal entry; sweeps repeat until the
  * off-diagonal part vanishes to rounding. */
+static void sym3_jacobi(const double A_in[3][3], double vals[3], double Qout[3][3]);
 static void sym3_top_eigvec(const double A_in[3][3], double v[3]) {
+  double vals[3], Q[3][3];
+  sym3_jacobi(A_in, vals, Q);
+  int best = 0;
+  for (int k = 1; k < 3; ++k)
+    if (vals[k] > vals[best]) best = k;
+  for (int k = 0; k < 3; ++k) v[k] = Q[k][best];
+}
+
+/* all eigenvalues (vals) and eigenvectors (columns of Qout) */
+static void sym3_jacobi(const double A_in[3][3], double vals[3], double Qout[3][3]) {
   double A[3][3], Q[3][3];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) {
@@ -1159,10 +1170,10 @@ static void sym3_top_eigvec(const double A_in[3][3], double v[3]) {
         }
       }
   }
-  int best = 0;
-  for (int k = 1; k < 3; ++k)
-    if (A[k][k] > A[best][best]) best = k;
-  for (int k = 0; k < 3; ++k) v[k] = Q[k][best];
+  for (int k = 0; k < 3; ++k) {
+    vals[k] = A[k][k];
+    for (int c = 0; c < 3; ++c) Qout[k][c] = Q[k][c];
+  }
 }
 
 /* The maximiser of R over the subgroup: a^T M a is invariant under left
@@ -1230,6 +1241,50 @@ int or_mag_sweep(double* U, const int32_t dims[4], int parity, double omega, int
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < L.V; ++s)
     if (site_parity(&L, s) == parity) mag_site_update(U, &L, s, omega, form);
+  return 0;
+}
+
+/* Relative gaps (l1 - l2) / |l1| between the two largest eigenvalues of the
+ * 3x3 block of M that the update of site s (as in or_mag_sweep with omega,
+ * form) meets at each of its three subgroup steps, on a copy of the field (0
+ * where a step is skipped). A small gap means the maximiser is (nearly) not
+ * unique, so that another choice is as good a maximiser. */
+int or_mag_site_gaps(const double* U, const int32_t dims[4], int64_t s, double omega, int form,
+                     double gaps[3]) {
+  if (!U || !gaps || or_check_dims(dims) != 0) return -1;
+  lat_t L = make_lat(dims);
+  if (s < 0 || s >= L.V) return -1;
+  size_t n = (size_t)L.V * 4 * 18;
+  double* W = (double*)malloc(n * sizeof(double));
+  if (!W) return -1;
+  memcpy(W, U, n * sizeof(double));
+  for (int sg = 0; sg < 3; ++sg) {
+    int i = SG_I[sg], j = SG_J[sg];
+    double M[4][4], a[4], g[4], B[3][3], vals[3], Q[3][3];
+    gaps[sg] = 0.0;
+    mag_matrix(W, &L, s, sg, M);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) B[r][c] = M[r][c];
+    sym3_jacobi(B, vals, Q);
+    double l1 = fmax(vals[0], fmax(vals[1], vals[2]));
+    double l3 = fmin(vals[0], fmin(vals[1], vals[2]));
+    double l2 = vals[0] + vals[1] + vals[2] - l1 - l3;
+    if (mag_local_max(M, a) < 0) continue;
+    gaps[sg] = fabs(l1) > 0 ? (l1 - l2) / fabs(l1) : 0.0;
+    if (or_overrelax_form(a, omega, form, g) < 0) continue;
+    mat3 G = embed_su2(g, i, j);
+    mat3 Gd = mat_dag(&G);
+    for (int mu = 0; mu < 4; ++mu) {
+      int64_t sb = neighbour(&L, s, mu, -1);
+      mat3 Uf = get_link(W, s, mu);
+      mat3 Ub = get_link(W, sb, mu);
+      mat3 A = mat_mul(&G, &Uf);
+      mat3 Bm = mat_mul(&Ub, &Gd);
+      put_link(W, s, mu, &A);
+      put_link(W, sb, mu, &Bm);
+    }
+  }
+  free(W);
   return 0;
 }
 

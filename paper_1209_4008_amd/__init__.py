@@ -100,6 +100,7 @@ SIGNATURES = {
     "gf_philox": (C.c_int32, [_vp, _dp, C.c_uint64, _dp, C.c_int64]),
     "gf_gauge_bytes": (C.c_size_t, [_gp]),
     "gf_gauge_unit": (C.c_int32, [_vp, _gp, _dp]),
+    "gf_gauge_pack": (C.c_int32, [_vp, _gp, _dp, _dp]),
     "gf_gauge_unpack": (C.c_int32, [_vp, _gp, _dp, _dp]),
     "gf_sweep_tracked": (C.c_int32, [_vp, _dp, _dp, _gp, C.c_int32, C.c_int32, C.c_double]),
     "gf_heatbath_half_tracked": (C.c_int32, [_vp, _dp, _dp, _gp, C.c_int32, C.c_int32,
@@ -109,8 +110,14 @@ SIGNATURES = {
     "gf_get_sweep_variant": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int32)]),
     "gf_sweep_variant_for": (C.c_int32, [_vp, _gp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "gf_set_anneal_variant": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "gf_anneal_variant_for": (C.c_int32, [_vp, _gp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "gf_autotune": (C.c_int32, [_vp, _gp, C.c_int32, _dp, C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "gf_autotune_anneal": (C.c_int32, [_vp, _gp, C.c_int32, _dp, C.c_double, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "gf_autotune_storage": (C.c_int32, [_vp, _gp, C.c_int32, _dp, C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_float)]),
     "gf_stream_probe": (C.c_int32, [_vp, _dp, _dp, C.c_size_t, C.c_int32]),
     "gf_fix": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.POINTER(FixParams),
                            C.POINTER(FixResult)]),
@@ -267,6 +274,9 @@ class Context:
     def gauge_unit(self, geom, G):
         return self._check(lib().gf_gauge_unit(self.h, C.byref(geom), _ptr(G)))
 
+    def gauge_pack(self, geom, g_canon, G):
+        return self._check(lib().gf_gauge_pack(self.h, C.byref(geom), _ptr(g_canon), _ptr(G)))
+
     def gauge_unpack(self, geom, G, g_canon):
         return self._check(lib().gf_gauge_unpack(self.h, C.byref(geom), _ptr(G), _ptr(g_canon)))
 
@@ -312,6 +322,33 @@ class Context:
                                       C.byref(t), C.byref(n), ms))
         table = {(1 << (k % 3), k // 3): ms[k] for k in range(9)}
         return (t.value, n.value), table
+
+    def autotune_anneal(self, geom, gauge, U_like=None, T=1.0):
+        """The same for the annealing updates at temperature T."""
+        t, n = C.c_int32(0), C.c_int32(0)
+        ms = (C.c_float * 9)()
+        self._check(lib().gf_autotune_anneal(self.h, C.byref(geom), int(gauge), _ptr(U_like),
+                                             float(T), C.byref(t), C.byref(n), ms))
+        table = {(1 << (k % 3), k // 3): ms[k] for k in range(9)}
+        return (t.value, n.value), table
+
+    def autotune_storage(self, geom, gauge, U_canon):
+        """Storage axis: (GF_R12 or GF_R18, {R12: ms, R18: ms}) per half-sweep of
+        each storage's best variant for geom's extents and precision."""
+        st = C.c_int32(0)
+        ms = (C.c_float * 2)()
+        self._check(lib().gf_autotune_storage(self.h, C.byref(geom), int(gauge), _ptr(U_canon),
+                                              C.byref(st), ms))
+        return st.value, {R12: ms[0], R18: ms[1]}
+
+    def set_anneal_variant(self, prec, storage, tps=0, nontemporal=-1):
+        return self._check(lib().gf_set_anneal_variant(self.h, int(prec), int(storage), int(tps),
+                                                       int(nontemporal)))
+
+    def anneal_variant_for(self, geom):
+        t, n = C.c_int32(0), C.c_int32(0)
+        self._check(lib().gf_anneal_variant_for(self.h, C.byref(geom), C.byref(t), C.byref(n)))
+        return t.value, n.value
 
     def stream_probe(self, src, dst, nbytes, kind):
         return self._check(lib().gf_stream_probe(self.h, _ptr(src), _ptr(dst), int(nbytes),

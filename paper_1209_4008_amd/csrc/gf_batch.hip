@@ -24,6 +24,8 @@ struct gf_batch {
   size_t partial_cap = 0;
   void* d_tab = nullptr;  // scratch for the lattice tables (4 tables)
   size_t tab_cap = 0;
+  uint32_t* d_map[4] = {nullptr, nullptr, nullptr, nullptr};  // their block maps
+  size_t map_cap[4] = {0, 0, 0, 0};                           // entries
 };
 
 namespace {
@@ -32,19 +34,26 @@ namespace {
 // no variant set on the context its built-in mode follows their total size
 // (the 192-lattice batch, 10.8 GB in FP64 12-real: streamed 5.25 against
 // cached 4.73 TB/s).
-int batch_nt(const gf_ctx* c, const gf_batch* b, bool lo) {
+size_t active_bytes(const gf_batch* b, bool lo) {
   const std::vector<gf_geom>& gs = lo ? b->g32 : b->g64;
-  const int t = c->nt[gs[0].prec == GF_FP64][gs[0].storage == GF_R18];
-  if (t >= 0) return t;
   size_t total = 0;
   for (int l = 0; l < b->n; ++l)
     if (b->active[l]) total += gf_field_bytes(&gs[l]);
-  return default_nt_bytes(total);
+  return total;
+}
+int batch_nt(const gf_ctx* c, const gf_batch* b, bool lo, int kind) {
+  const gf_geom& g = lo ? b->g32[0] : b->g64[0];
+  return ctx_nt_bytes(c, &g, kind, active_bytes(b, lo));
+}
+int batch_tps(const gf_ctx* c, const gf_batch* b, bool lo, int kind) {
+  const gf_geom& g = lo ? b->g32[0] : b->g64[0];
+  return ctx_tps_bytes(c, &g, kind, active_bytes(b, lo));
 }
 
 template <typename T>
 struct TableSet {
   std::vector<BatchEntry<T>> h;
+  std::vector<uint32_t> map;  // table entry of each block
   uint32_t blocks = 0;
 };
 
@@ -62,7 +71,9 @@ TableSet<T> make_table(const gf_batch* b, bool lo, int tps) {
     e.Gx = lo ? (v2<T>*)((char*)b->arenaG + b->offG[l]) : nullptr;
     e.first_block = blk;
     e.index = (uint32_t)l;
-    blk += blocks_for((uint64_t)e.L.vh * (uint64_t)tps);
+    const uint32_t nb = blocks_for((uint64_t)e.L.vh * (uint64_t)tps);
+    t.map.insert(t.map.end(), nb, (uint32_t)t.h.size());
+    blk += nb;
     t.h.push_back(e);
   }
   t.blocks = blk;
@@ -128,15 +139,19 @@ gf_status gf_batch_destroy(gf_batch* b) {
   if (b->h_out) (void)hipHostFree(b->h_out);
   if (b->d_partial) (void)hipFree(b->d_partial);
   if (b->d_tab) (void)hipFree(b->d_tab);
+  for (int k = 0; k < 4; ++k)
+    if (b->d_map[k]) (void)hipFree(b->d_map[k]);
   delete b;
   return GF_OK;
 }
 
 namespace {
 
-// upload a table into slot k of the batch's table scratch; returns its device address
+// upload a table and its block map into slot k of the batch's scratch;
+// returns their device addresses
 template <typename T>
-gf_status upload_table(gf_batch* b, int k, const TableSet<T>& t, const BatchEntry<T>** dev) {
+gf_status upload_table(gf_batch* b, int k, const TableSet<T>& t, const BatchEntry<T>** dev,
+                       const uint32_t** dev_map) {
   gf_ctx* c = b->c;
   const size_t one = ((size_t)b->n * sizeof(BatchEntry<T>) + 255) / 256 * 256;
   if (b->tab_cap < 4 * one) {
@@ -152,15 +167,25 @@ gf_status upload_table(gf_batch* b, int k, const TableSet<T>& t, const BatchEntr
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   HIP_OR_FAIL(c, hipMemcpy(p, t.h.data(), t.h.size() * sizeof(BatchEntry<T>), hipMemcpyHostToDevice));
   *dev = (const BatchEntry<T>*)p;
+  if (t.map.size() > b->map_cap[k]) {
+    if (b->d_map[k]) HIP_OR_FAIL(c, hipFree(b->d_map[k]));
+    b->d_map[k] = nullptr;
+    b->map_cap[k] = 0;
+    HIP_OR_FAIL(c, hipMalloc(&b->d_map[k], t.map.size() * sizeof(uint32_t)));
+    b->map_cap[k] = t.map.size();
+  }
+  HIP_OR_FAIL(c, hipMemcpy(b->d_map[k], t.map.data(), t.map.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice));
+  *dev_map = b->d_map[k];
   return GF_OK;
 }
 
 template <typename T, int NC, class Upd, bool TRACK>
-void launch_batch_update(gf_ctx* c, int tps, int nt, const BatchEntry<T>* tab, int n, uint32_t blocks,
-                         int parity, const Upd& upd) {
+void launch_batch_update(gf_ctx* c, int tps, int nt, const BatchEntry<T>* tab,
+                         const uint32_t* map, uint32_t blocks, int parity, const Upd& upd) {
   auto go = [&]<int TPS, int NT>() {
     hipLaunchKernelGGL((k_update_half_batch<T, NC, Upd, TPS, NT, TRACK>), dim3(blocks), dim3(kBlock),
-                       0, c->stream, tab, n, parity, upd);
+                       0, c->stream, tab, map, parity, upd);
   };
   auto go_tps = [&]<int NT>() {
     if (tps == 1) go.template operator()<1, NT>();
@@ -184,20 +209,24 @@ struct PhaseTables {
   TableSet<T> sweep, meas;
   const BatchEntry<T>* d_sweep = nullptr;
   const BatchEntry<T>* d_meas = nullptr;
-  int n = 0;   // entries (active lattices)
-  int nt = 0;  // nontemporal mode for their total size
+  const uint32_t* d_sweep_map = nullptr;
+  const uint32_t* d_meas_map = nullptr;
+  int n = 0;    // entries (active lattices)
+  int tps = 1;  // lanes per site and nontemporal mode for their total size
+  int nt = 0;
 };
 
 template <typename T>
-gf_status build_tables(gf_batch* b, bool lo, int tps, PhaseTables<T>& pt) {
-  pt.sweep = make_table<T>(b, lo, tps);
+gf_status build_tables(gf_batch* b, bool lo, int kind, PhaseTables<T>& pt) {
+  pt.tps = batch_tps(b->c, b, lo, kind);
+  pt.nt = batch_nt(b->c, b, lo, kind);
+  pt.sweep = make_table<T>(b, lo, pt.tps);
   pt.meas = make_table<T>(b, lo, 1);
   pt.n = (int)pt.sweep.h.size();
-  pt.nt = batch_nt(b->c, b, lo);
   gf_status st;
   if (pt.n == 0) return GF_OK;
-  if ((st = upload_table(b, lo ? 0 : 2, pt.sweep, &pt.d_sweep)) != GF_OK) return st;
-  return upload_table(b, lo ? 1 : 3, pt.meas, &pt.d_meas);
+  if ((st = upload_table(b, lo ? 0 : 2, pt.sweep, &pt.d_sweep, &pt.d_sweep_map)) != GF_OK) return st;
+  return upload_table(b, lo ? 1 : 3, pt.meas, &pt.d_meas, &pt.d_meas_map);
 }
 
 // one batch phase (precision T, storage NC): checks and sweeps until every
@@ -210,12 +239,10 @@ gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double targe
                       BatchPhase& ph) {
   gf_ctx* c = b->c;
   const int n = b->n;
-  const gf_geom& gref = lo ? b->g32[0] : b->g64[0];
-  const int tps = ctx_tps(c, &gref);
   b->active.assign(n, 1);
   PhaseTables<T> pt;
   gf_status st;
-  if ((st = build_tables(b, lo, tps, pt)) != GF_OK) return st;
+  if ((st = build_tables(b, lo, kSweepKind, pt)) != GF_OK) return st;
   const size_t need = 2 * (size_t)pt.meas.blocks;
   if (need > b->partial_cap) {
     if (b->d_partial) HIP_OR_FAIL(c, hipFree(b->d_partial));
@@ -246,13 +273,13 @@ gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double targe
           us.k1 = (uint32_t)(p->seed >> 32);
           us.sweep = (uint32_t)(done + k);
           if (lo)
-            launch_batch_update<T, NC, UpdSR<T>, true>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, us);
+            launch_batch_update<T, NC, UpdSR<T>, true>(c, pt.tps, pt.nt, pt.d_sweep, pt.d_sweep_map, pt.sweep.blocks, par, us);
           else
-            launch_batch_update<T, NC, UpdSR<T>, false>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, us);
+            launch_batch_update<T, NC, UpdSR<T>, false>(c, pt.tps, pt.nt, pt.d_sweep, pt.d_sweep_map, pt.sweep.blocks, par, us);
         } else if (lo) {
-          launch_batch_update<T, NC, UpdOR<T>, true>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, upd);
+          launch_batch_update<T, NC, UpdOR<T>, true>(c, pt.tps, pt.nt, pt.d_sweep, pt.d_sweep_map, pt.sweep.blocks, par, upd);
         } else {
-          launch_batch_update<T, NC, UpdOR<T>, false>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, upd);
+          launch_batch_update<T, NC, UpdOR<T>, false>(c, pt.tps, pt.nt, pt.d_sweep, pt.d_sweep_map, pt.sweep.blocks, par, upd);
         }
       }
     return launch_check(c, "gf_batch_run: sweeps");
@@ -262,12 +289,12 @@ gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double targe
     if (p->reunit_at_check && done > 0) {
       if ((st = tm.begin()) != GF_OK) return st;
       hipLaunchKernelGGL((k_reunitarize_batch<T, NC>), dim3(pt.meas.blocks), dim3(kBlock), 0, c->stream,
-                         pt.d_meas, pt.n);
+                         pt.d_meas, pt.d_meas_map);
       if ((st = tm.end(3, 1)) != GF_OK) return st;
     }
     if ((st = tm.begin()) != GF_OK) return st;
     hipLaunchKernelGGL((k_measure_batch<T, NC>), dim3(pt.meas.blocks), dim3(kBlock), 0, c->stream,
-                       pt.d_meas, pt.n, b->d_partial);
+                       pt.d_meas, pt.d_meas_map, b->d_partial);
     hipLaunchKernelGGL((k_finish_batch<T>), dim3(pt.n), dim3(kBlock), 0, c->stream, pt.d_meas, pt.n,
                        pt.meas.blocks, (const double*)b->d_partial, b->d_out, b->d_out + n);
     if ((st = launch_check(c, "gf_batch_run: measure")) != GF_OK) return st;
@@ -300,7 +327,7 @@ gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double targe
     if (!remaining) return GF_OK;
     if (retired) {
       // the stream is idle (synchronised above): rewrite the tables in place
-      if ((st = build_tables(b, lo, tps, pt)) != GF_OK) return st;
+      if ((st = build_tables(b, lo, kSweepKind, pt)) != GF_OK) return st;
       sg.reset();
     }
     const int32_t nsw = std::min(p->check_every, p->max_sweeps - done);
@@ -339,11 +366,10 @@ gf_status batch_phase(gf_batch* b, const gf_fix_params* p, bool lo, double targe
 template <int NC>
 gf_status batch_anneal(gf_batch* b, const gf_fix_params* p, Timer& tm) {
   gf_ctx* c = b->c;
-  const int tps = ctx_tps(c, &b->g32[0]);
   b->active.assign(b->n, 1);
   PhaseTables<float> pt;
   gf_status st;
-  if ((st = build_tables(b, true, tps, pt)) != GF_OK) return st;
+  if ((st = build_tables(b, true, kAnnealKind, pt)) != GF_OK) return st;
   for (int32_t k = 0; k < p->sa_steps; ++k) {
     const double T = p->sa_steps > 1
                          ? p->sa_T0 + (p->sa_T1 - p->sa_T0) * (double)k / (double)(p->sa_steps - 1)
@@ -356,15 +382,15 @@ gf_status batch_anneal(gf_batch* b, const gf_fix_params* p, Timer& tm) {
     UpdMicro<float> mc;
     if ((st = tm.begin()) != GF_OK) return st;
     for (int par = 0; par < 2; ++par)
-      launch_batch_update<float, NC, UpdHB<float>, true>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, hb);
+      launch_batch_update<float, NC, UpdHB<float>, true>(c, pt.tps, pt.nt, pt.d_sweep, pt.d_sweep_map, pt.sweep.blocks, par, hb);
     for (int m = 0; m < p->sa_micro; ++m)
       for (int par = 0; par < 2; ++par)
-        launch_batch_update<float, NC, UpdMicro<float>, true>(c, tps, pt.nt, pt.d_sweep, pt.n, pt.sweep.blocks, par, mc);
+        launch_batch_update<float, NC, UpdMicro<float>, true>(c, pt.tps, pt.nt, pt.d_sweep, pt.d_sweep_map, pt.sweep.blocks, par, mc);
     if ((st = launch_check(c, "gf_batch_run: annealing")) != GF_OK) return st;
     if ((st = tm.end(4, 2 + 2 * (int64_t)p->sa_micro)) != GF_OK) return st;
     if (p->sa_reunit_every > 0 && (k + 1) % p->sa_reunit_every == 0) {
       hipLaunchKernelGGL((k_reunitarize_batch<float, NC>), dim3(pt.meas.blocks), dim3(kBlock), 0, c->stream,
-                         pt.d_meas, pt.n);
+                         pt.d_meas, pt.d_meas_map);
       if ((st = launch_check(c, "gf_batch_run: reunitarise")) != GF_OK) return st;
     }
   }

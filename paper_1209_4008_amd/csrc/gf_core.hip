@@ -210,6 +210,16 @@ gf_status gf_gauge_unit(gf_ctx* c, const gf_geom* g, void* G) {
   return launch_check(c, "gf_gauge_unit");
 }
 
+gf_status gf_gauge_pack(gf_ctx* c, const gf_geom* g, const double* src, void* G) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_gauge_pack");
+  if (!src || !G) return fail(c, GF_ERR_ARG, "gf_gauge_pack: NULL pointer");
+  const Lat L = make_lat(g);
+  hipLaunchKernelGGL((k_pack_gauge<float>), dim3(blocks_for(2ull * L.vh)), dim3(kBlock), 0,
+                     c->stream, src, (v2<float>*)G, L);
+  return launch_check(c, "gf_gauge_pack");
+}
+
 gf_status gf_gauge_unpack(gf_ctx* c, const gf_geom* g, const void* G, double* dst) {
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_gauge_unpack");
@@ -372,16 +382,28 @@ static int ps_ok(int32_t prec, int32_t storage) {
   return (prec == GF_FP32 || prec == GF_FP64) && (storage == GF_R12 || storage == GF_R18);
 }
 
+static gf_status set_variant(gf_ctx* c, int kind, int32_t prec, int32_t storage, int32_t tps,
+                             int32_t nontemporal, const char* what) {
+  if (!c) return GF_ERR_ARG;
+  if (!ps_ok(prec, storage)) return fail(c, GF_ERR_ARG, "%s: bad precision or storage", what);
+  if (tps != 0 && !tps_ok(tps)) return fail(c, GF_ERR_ARG, "%s: tps must be 0, 1, 2 or 4", what);
+  if (nontemporal < -1 || nontemporal > 2)
+    return fail(c, GF_ERR_ARG, "%s: nontemporal must be -1, 0, 1 or 2", what);
+  for (int cls = 0; cls < 2; ++cls) {
+    ctx_var(c, kind, prec, storage, cls).tps = tps;
+    ctx_var(c, kind, prec, storage, cls).nt = nontemporal;
+  }
+  return GF_OK;
+}
+
 gf_status gf_set_sweep_variant(gf_ctx* c, int32_t prec, int32_t storage, int32_t tps,
                                int32_t nontemporal) {
-  if (!c) return GF_ERR_ARG;
-  if (!ps_ok(prec, storage)) return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: bad precision or storage");
-  if (tps != 0 && !tps_ok(tps)) return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: tps must be 0, 1, 2 or 4");
-  if (nontemporal < -1 || nontemporal > 2)
-    return fail(c, GF_ERR_ARG, "gf_set_sweep_variant: nontemporal must be -1, 0, 1 or 2");
-  c->tps[prec == GF_FP64][storage == GF_R18] = tps;
-  c->nt[prec == GF_FP64][storage == GF_R18] = nontemporal;
-  return GF_OK;
+  return set_variant(c, kSweepKind, prec, storage, tps, nontemporal, "gf_set_sweep_variant");
+}
+
+gf_status gf_set_anneal_variant(gf_ctx* c, int32_t prec, int32_t storage, int32_t tps,
+                                int32_t nontemporal) {
+  return set_variant(c, kAnnealKind, prec, storage, tps, nontemporal, "gf_set_anneal_variant");
 }
 
 gf_status gf_sweep_variant_for(gf_ctx* c, const gf_geom* g, int32_t* tps, int32_t* nontemporal) {
@@ -390,6 +412,15 @@ gf_status gf_sweep_variant_for(gf_ctx* c, const gf_geom* g, int32_t* tps, int32_
   if (!tps || !nontemporal) return fail(c, GF_ERR_ARG, "gf_sweep_variant_for: NULL pointer");
   *tps = ctx_tps(c, g);
   *nontemporal = ctx_nt(c, g);
+  return GF_OK;
+}
+
+gf_status gf_anneal_variant_for(gf_ctx* c, const gf_geom* g, int32_t* tps, int32_t* nontemporal) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_anneal_variant_for");
+  if (!tps || !nontemporal) return fail(c, GF_ERR_ARG, "gf_anneal_variant_for: NULL pointer");
+  *tps = ctx_tps(c, g, kAnnealKind);
+  *nontemporal = ctx_nt(c, g, kAnnealKind);
   return GF_OK;
 }
 
@@ -403,78 +434,210 @@ gf_status gf_get_sweep_variant(gf_ctx* c, int32_t prec, int32_t storage, int32_t
   return GF_OK;
 }
 
+namespace {
+
+// One captured block of timing work per variant, replayed from a hipGraph as
+// the drivers replay their sweep blocks.
+struct TuneGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~TuneGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+// capture `enqueue` (which launches on c->stream) into g on the context's
+// capture stream
+template <class F>
+gf_status capture_block(gf_ctx* c, F&& enqueue, TuneGraph& g) {
+  if (!c->capture) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+  hipStream_t saved = c->stream;
+  c->stream = c->capture;
+  hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    c->stream = saved;
+    return fail(c, GF_ERR_HIP, "autotune: hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  gf_status st = enqueue();
+  e = hipStreamEndCapture(c->capture, &g.graph);
+  c->stream = saved;
+  if (st != GF_OK) return st;
+  if (e != hipSuccess) return fail(c, GF_ERR_HIP, "autotune: hipStreamEndCapture: %s", hipGetErrorString(e));
+  HIP_OR_FAIL(c, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+  return GF_OK;
+}
+
+// time one replay of g on the context stream (ms)
+gf_status time_replay(gf_ctx* c, const TuneGraph& g, float* ms) {
+  HIP_OR_FAIL(c, hipEventRecord(c->ev[0], c->stream));
+  HIP_OR_FAIL(c, hipGraphLaunch(g.exec, c->stream));
+  HIP_OR_FAIL(c, hipEventRecord(c->ev[1], c->stream));
+  HIP_OR_FAIL(c, hipEventSynchronize(c->ev[1]));
+  HIP_OR_FAIL(c, hipEventElapsedTime(ms, c->ev[0], c->ev[1]));
+  return GF_OK;
+}
+
+// The autotuner's timing, done the way the drivers run the kernels: for each
+// of the nine variants (lanes per site 1, 2, 4 x nontemporal mode 0, 1, 2) a
+// block of `reps` units of work (`unit` enqueues one: a RED/BLACK sweep pair,
+// or an annealing step) is captured as a hipGraph on the scratch field; the
+// nine graphs are then replayed in turn, round after round, and each variant
+// is timed by the median of its rounds, so that slow drifts and the order of
+// the variants weigh on all of them alike. Returns the median ms per unit in
+// times[9] (index 3 * mode + log2(lanes)).
+template <class Unit>
+gf_status tune_variants(gf_ctx* c, int kind, const gf_geom* g, Unit&& unit, int half_sweeps_per_unit,
+                        float times[kVariants]) {
+  const int i64 = g->prec == GF_FP64, i18 = g->storage == GF_R18;
+  const int cls = size_class(gf_field_bytes(g));
+  gf_ctx::Variant saved = c->var[kind][i64][i18][cls];
+  gf_status st = GF_OK;
+  // size of a block: about 2 ms of work, from one timed unit of the built-in variant
+  float ms1 = 0;
+  if ((st = unit()) != GF_OK) return st;
+  HIP_OR_FAIL(c, hipEventRecord(c->ev[0], c->stream));
+  if ((st = unit()) != GF_OK) return st;
+  HIP_OR_FAIL(c, hipEventRecord(c->ev[1], c->stream));
+  HIP_OR_FAIL(c, hipEventSynchronize(c->ev[1]));
+  HIP_OR_FAIL(c, hipEventElapsedTime(&ms1, c->ev[0], c->ev[1]));
+  const int reps = std::max(2, std::min(400, (int)std::ceil(2.0 / std::max(ms1, 1e-3f))));
+  TuneGraph graphs[kVariants];
+  for (int k = 0; k < kVariants && st == GF_OK; ++k) {
+    c->var[kind][i64][i18][cls].tps = 1 << (k % 3);
+    c->var[kind][i64][i18][cls].nt = k / 3;
+    st = capture_block(c, [&]() -> gf_status {
+      for (int r = 0; r < reps; ++r) {
+        gf_status s2 = unit();
+        if (s2 != GF_OK) return s2;
+      }
+      return GF_OK;
+    }, graphs[k]);
+  }
+  c->var[kind][i64][i18][cls] = saved;
+  if (st != GF_OK) return st;
+  constexpr int kRounds = 5;
+  float t[kVariants][kRounds];
+  for (int k = 0; k < kVariants; ++k) HIP_OR_FAIL(c, hipGraphLaunch(graphs[k].exec, c->stream));  // warm-up
+  for (int r = 0; r < kRounds; ++r)
+    for (int k = 0; k < kVariants; ++k)
+      if ((st = time_replay(c, graphs[k], &t[k][r])) != GF_OK) return st;
+  for (int k = 0; k < kVariants; ++k) {
+    std::sort(t[k], t[k] + kRounds);
+    times[k] = t[k][kRounds / 2] / (float)(reps * half_sweeps_per_unit);
+  }
+  return GF_OK;
+}
+
+// scratch copy of U_like (or the unit field) for the tuner
+gf_status tune_scratch(gf_ctx* c, const gf_geom* g, const void* U_like, void** out) {
+  const size_t bytes = gf_field_bytes(g);
+  HIP_OR_FAIL(c, hipMalloc(out, bytes));
+  const Lat L = make_lat(g);
+  if (U_like) {
+    if (hipMemcpyAsync(*out, U_like, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+      (void)hipFree(*out);
+      *out = nullptr;
+      return fail(c, GF_ERR_HIP, "autotune: copy of the sample field failed");
+    }
+  } else {
+    with_type(g, [&]<typename T, int NC>() {
+      hipLaunchKernelGGL((k_fill_unit<T, NC, 4>), dim3(blocks_for(L.vp), 8), dim3(kBlock), 0,
+                         c->stream, (v2<T>*)*out, L.vp);
+    });
+  }
+  return GF_OK;
+}
+
+// keep the fastest variant for g's precision, storage and size class
+void keep_fastest(gf_ctx* c, int kind, const gf_geom* g, const float times[kVariants],
+                  int32_t* tps_out, int32_t* nt_out, float* ms_out) {
+  int best = 0;
+  for (int k = 1; k < kVariants; ++k)
+    if (times[k] < times[best]) best = k;
+  const int cls = size_class(gf_field_bytes(g));
+  ctx_var(c, kind, g->prec, g->storage, cls).tps = 1 << (best % 3);
+  ctx_var(c, kind, g->prec, g->storage, cls).nt = best / 3;
+  if (tps_out) *tps_out = 1 << (best % 3);
+  if (nt_out) *nt_out = best / 3;
+  if (ms_out)
+    for (int k = 0; k < kVariants; ++k) ms_out[k] = times[k];
+}
+
+}  // namespace
+
 gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, const void* U_like,
                       int32_t* tps_out, int32_t* nt_out, float* ms_out) {
   CHECK_CTX(c);
   CHECK_GEOM(c, g, "gf_autotune");
   if (gauge != GF_LANDAU && gauge != GF_COULOMB && gauge != GF_MAG)
     return fail(c, GF_ERR_ARG, "gf_autotune: bad gauge");
-  const size_t bytes = gf_field_bytes(g);
   void* scratch = nullptr;
-  HIP_OR_FAIL(c, hipMalloc(&scratch, bytes));
-  const Lat L = make_lat(g);
-  if (U_like) {
-    if (hipMemcpyAsync(scratch, U_like, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
-      (void)hipFree(scratch);
-      return fail(c, GF_ERR_HIP, "gf_autotune: copy of the sample field failed");
-    }
-  } else {
-    with_type(g, [&]<typename T, int NC>() {
-      hipLaunchKernelGGL((k_fill_unit<T, NC, 4>), dim3(blocks_for(L.vp), 8), dim3(kBlock), 0,
-                         c->stream, (v2<T>*)scratch, L.vp);
-    });
-  }
-  const int reps = 20;
+  gf_status st = tune_scratch(c, g, U_like, &scratch);
+  if (st != GF_OK) return st;
   float times[kVariants] = {};
-  float best = 1e30f;
-  int best_tps = default_tps(g), best_nt = default_nt(g);
-  const int i64 = g->prec == GF_FP64, i18 = g->storage == GF_R18;
-  const int saved_tps = c->tps[i64][i18], saved_nt = c->nt[i64][i18];
-  gf_status st = GF_OK;
-  for (int k = 0; k < kVariants && st == GF_OK; ++k) {
-    c->tps[i64][i18] = 1 << (k % 3);
-    c->nt[i64][i18] = k / 3;
-    for (int w = 0; w < 2 && st == GF_OK; ++w) st = gf_sweep(c, scratch, g, gauge, w & 1, 1.5);
-    if (st != GF_OK) break;
-    if (hipEventRecord(c->ev[0], c->stream) != hipSuccess) st = GF_ERR_HIP;
-    for (int w = 0; w < 2 * reps && st == GF_OK; ++w) st = gf_sweep(c, scratch, g, gauge, w & 1, 1.5);
-    if (st != GF_OK) break;
-    float ms = 0;
-    if (hipEventRecord(c->ev[1], c->stream) != hipSuccess || hipEventSynchronize(c->ev[1]) != hipSuccess ||
-        hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) != hipSuccess) {
-      st = fail(c, GF_ERR_HIP, "gf_autotune: event timing failed");
-      break;
-    }
-    ms /= (float)(2 * reps);
-    times[k] = ms;
-    if (ms_out) ms_out[k] = ms;
-    if (ms < best) {
-      best = ms;
-      best_tps = 1 << (k % 3);
-      best_nt = k / 3;
-    }
-  }
+  st = tune_variants(c, kSweepKind, g, [&]() -> gf_status {
+    gf_status s2 = gf_sweep(c, scratch, g, gauge, 0, 1.7);
+    return s2 != GF_OK ? s2 : gf_sweep(c, scratch, g, gauge, 1, 1.7);
+  }, 2, times);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(scratch);
-  if (st != GF_OK) {
-    c->tps[i64][i18] = saved_tps;
-    c->nt[i64][i18] = saved_nt;
-    return st;
+  if (st != GF_OK) return st;
+  keep_fastest(c, kSweepKind, g, times, tps_out, nt_out, ms_out);
+  return GF_OK;
+}
+
+gf_status gf_autotune_anneal(gf_ctx* c, const gf_geom* g, int32_t gauge, const void* U_like,
+                             double T, int32_t* tps_out, int32_t* nt_out, float* ms_out) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_autotune_anneal");
+  if (gauge != GF_LANDAU && gauge != GF_COULOMB)
+    return fail(c, GF_ERR_ARG, "gf_autotune_anneal: gauge must be GF_LANDAU or GF_COULOMB");
+  if (!(T > 0.0) || !std::isfinite(T)) return fail(c, GF_ERR_ARG, "gf_autotune_anneal: T must be > 0");
+  void* scratch = nullptr;
+  gf_status st = tune_scratch(c, g, U_like, &scratch);
+  if (st != GF_OK) return st;
+  float times[kVariants] = {};
+  // one step: heatbath RED and BLACK at T, one microcanonical sweep; the
+  // step index is fixed, so every replay draws the same numbers
+  st = tune_variants(c, kAnnealKind, g, [&]() -> gf_status {
+    gf_status s2 = GF_OK;
+    for (int p = 0; p < 2 && s2 == GF_OK; ++p) s2 = gf_heatbath_half(c, scratch, g, gauge, p, T, 1, 0);
+    for (int p = 0; p < 2 && s2 == GF_OK; ++p) s2 = gf_micro_half(c, scratch, g, gauge, p);
+    return s2;
+  }, 4, times);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(scratch);
+  if (st != GF_OK) return st;
+  keep_fastest(c, kAnnealKind, g, times, tps_out, nt_out, ms_out);
+  return GF_OK;
+}
+
+gf_status gf_autotune_storage(gf_ctx* c, const gf_geom* g, int32_t gauge, const double* U_canon,
+                              int32_t* storage_out, float* ms_out) {
+  CHECK_CTX(c);
+  CHECK_GEOM(c, g, "gf_autotune_storage");
+  if (!U_canon || !storage_out) return fail(c, GF_ERR_ARG, "gf_autotune_storage: NULL pointer");
+  float best[2] = {0, 0};
+  const int32_t storages[2] = {GF_R12, GF_R18};
+  for (int k = 0; k < 2; ++k) {
+    gf_geom gs = *g;
+    gs.storage = storages[k];
+    void* f = nullptr;
+    HIP_OR_FAIL(c, hipMalloc(&f, gf_field_bytes(&gs)));
+    gf_status st = gf_pack(c, &gs, U_canon, f);
+    float ms[kVariants] = {};
+    if (st == GF_OK) st = gf_autotune(c, &gs, gauge, f, nullptr, nullptr, ms);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(f);
+    if (st != GF_OK) return st;
+    best[k] = *std::min_element(ms, ms + kVariants);
   }
-  // variants within 5% of the fastest: keep the built-in one, so that
-  // repeated tunings settle on the same kernel (the scratch field's timings
-  // can differ from the caller's field's by a few percent)
-  {
-    const int kd = 3 * default_nt(g) + (default_tps(g) == 4 ? 2 : default_tps(g) == 2 ? 1 : 0);
-    if (times[kd] <= 1.05f * best) {
-      best_tps = default_tps(g);
-      best_nt = default_nt(g);
-    }
+  *storage_out = best[1] < best[0] ? GF_R18 : GF_R12;
+  if (ms_out) {
+    ms_out[0] = best[0];
+    ms_out[1] = best[1];
   }
-  c->tps[i64][i18] = best_tps;
-  c->nt[i64][i18] = best_nt;
-  if (tps_out) *tps_out = best_tps;
-  if (nt_out) *nt_out = best_nt;
   return GF_OK;
 }
 

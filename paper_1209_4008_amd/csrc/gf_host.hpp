@@ -31,8 +31,15 @@ struct gf_ctx {
   double* host_out = nullptr; // pinned copy of dev_out
   size_t out_cap = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
-  int tps[2][2] = {{0, 0}, {0, 0}};  // lanes per site [fp64][r18]; 0 = default
-  int nt[2][2] = {{-1, -1}, {-1, -1}};  // nontemporal accesses [fp64][r18]; -1 = default
+  // sweep-kernel variants set or tuned on this context, [kind][fp64][r18][size
+  // class]: kind 0 the overrelaxation sweeps (every form, stochastic
+  // relaxation, MAG), 1 the annealing updates (heatbath, microcanonical); size
+  // class 0 fields of at most 2 GiB, 1 larger ones. tps = lanes per site (0:
+  // built-in), nt = nontemporal mode (-1: built-in).
+  struct Variant {
+    int tps = 0;
+    int nt = -1;
+  } var[2][2][2][2];
   void* gbuf = nullptr;  // gauge-transformation field of the mixed driver
   size_t gbuf_cap = 0;   // bytes
   hipStream_t capture = nullptr;  // private stream for hipGraph capture
@@ -192,9 +199,17 @@ static inline gf_status ensure_out(gf_ctx* c, size_t n) {
 
 #define CHECK_GEOM(c, g, what) \
   if (!geom_ok(g)) return fail((c), GF_ERR_ARG, "%s: invalid geometry", what)
-// lanes per site and nontemporal accesses of the sweep kernels, per
-// (precision, storage); the autotuner overwrites these per context
-static inline int default_tps(const gf_geom* g) { return g->prec == GF_FP64 ? 4 : 2; }
+// Built-in lanes per site: FP64 4 (one lane cannot hold 8 FP64 links in
+// registers), FP32 overrelaxation 2. The FP32 annealing updates run 1 lane: the
+// heatbath's draws and trials then cost a lane no more than with 2 lanes,
+// and at 32^3 x 64 (tracked, 12 reals) 1 lane took 143.4 / 145.6 / 171.8 us
+// per half-sweep at T = 0.05 / 0.5 / 1.45 against 155.4 / 157.3 / 169.4 with 2
+// (microcanonical 143.7 against 144.8).
+constexpr int kSweepKind = 0, kAnnealKind = 1;
+static inline int default_tps(const gf_geom* g, int kind = kSweepKind) {
+  if (g->prec == GF_FP64) return 4;
+  return kind == kAnnealKind ? 1 : 2;
+}
 // variants timed by the autotuner: lanes per site 1, 2, 4 x nontemporal mode
 // kNTNone, kNTAll, kNTStores, index 3 * mode + log2(lanes)
 constexpr int kVariants = 9;
@@ -339,14 +354,43 @@ static inline void launch_tracked_v(gf_ctx* c, int tps, void* U, void* Gx, const
   }
 }
 
-static inline int ctx_tps(const gf_ctx* c, const gf_geom* g) {
-  const int t = c->tps[g->prec == GF_FP64][g->storage == GF_R18];
-  return t > 0 ? t : default_tps(g);
+static inline int size_class(size_t bytes) { return bytes > kStreamBytes ? 1 : 0; }
+static inline gf_ctx::Variant& ctx_var(gf_ctx* c, int kind, int prec, int storage, int cls) {
+  return c->var[kind][prec == GF_FP64][storage == GF_R18][cls];
 }
-static inline int ctx_nt(const gf_ctx* c, const gf_geom* g) {
-  const int t = c->nt[g->prec == GF_FP64][g->storage == GF_R18];
-  return t >= 0 ? t : default_nt(g);
+static inline const gf_ctx::Variant& ctx_var(const gf_ctx* c, int kind, const gf_geom* g,
+                                             size_t bytes) {
+  return c->var[kind][g->prec == GF_FP64][g->storage == GF_R18][size_class(bytes)];
 }
+// the variant of a launch over fields of `bytes` in all (batches: the active
+// lattices' fields), of geometry g's precision and storage
+static inline int ctx_tps_bytes(const gf_ctx* c, const gf_geom* g, int kind, size_t bytes) {
+  const int t = ctx_var(c, kind, g, bytes).tps;
+  return t > 0 ? t : default_tps(g, kind);
+}
+static inline int ctx_nt_bytes(const gf_ctx* c, const gf_geom* g, int kind, size_t bytes) {
+  const int t = ctx_var(c, kind, g, bytes).nt;
+  return t >= 0 ? t : default_nt_bytes(bytes);
+}
+static inline int ctx_tps(const gf_ctx* c, const gf_geom* g, int kind = kSweepKind) {
+  return ctx_tps_bytes(c, g, kind, gf_field_bytes(g));
+}
+static inline int ctx_nt(const gf_ctx* c, const gf_geom* g, int kind = kSweepKind) {
+  return ctx_nt_bytes(c, g, kind, gf_field_bytes(g));
+}
+// which variant table an update policy uses
+template <class Upd>
+struct UpdKind {
+  static constexpr int value = kSweepKind;
+};
+template <typename T>
+struct UpdKind<UpdHB<T>> {
+  static constexpr int value = kAnnealKind;
+};
+template <typename T>
+struct UpdKind<UpdMicro<T>> {
+  static constexpr int value = kAnnealKind;
+};
 
 template <class UpdF>
 static inline gf_status launch_update(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge,
@@ -355,7 +399,8 @@ static inline gf_status launch_update(gf_ctx* c, void* U, const gf_geom* g, int3
   if (gauge == GF_MAG && !MagCapable<UpdD>::value)
     return fail(c, GF_ERR_UNSUPPORTED, "%s: not available for GF_MAG", what);
   const Lat L = make_lat(g);
-  const int tps = ctx_tps(c, g), nt = ctx_nt(c, g);
+  const int kind = UpdKind<UpdD>::value;
+  const int tps = ctx_tps(c, g, kind), nt = ctx_nt(c, g, kind);
   with_type(g, [&]<typename T, int NC>() {
     auto upd = make_upd.template operator()<T>();
     if (gauge == GF_LANDAU)
@@ -383,7 +428,8 @@ static inline gf_status update_tracked(gf_ctx* c, void* U, void* Gx, const gf_ge
   if (gauge == GF_MAG && !MagCapable<Upd>::value)
     return fail(c, GF_ERR_UNSUPPORTED, "%s: not available for GF_MAG", what);
   const Lat L = make_lat(g);
-  const int tps = ctx_tps(c, g), nt = ctx_nt(c, g);
+  const int kind = UpdKind<Upd>::value;
+  const int tps = ctx_tps(c, g, kind), nt = ctx_nt(c, g, kind);
   const int mode = nt_mode<Upd>(nt);
   auto go_gauge = [&]<int NC, int GAUGE>() {
     if (mode == kNTAll) {

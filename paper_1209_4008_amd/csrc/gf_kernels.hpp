@@ -892,8 +892,10 @@ __global__ __launch_bounds__(kBlock) void k_mag_half(v2<T>* __restrict__ U, cons
 // ---------------------------------------------------------------------------
 // batches of independent lattices (Gribov copies, uneven extents): one launch
 // covers the lattices of a table, entry k owning the blocks
-// [first_block[k], first_block[k+1]); the host rebuilds the table without the
-// lattices that have left the phase, so a launch covers active lattices only.
+// [first_block[k], first_block[k+1]), and map[b] names the entry of block b
+// (one load per block instead of a search of the table); the host rebuilds
+// table and map without the lattices that have left the phase, so a launch
+// covers active lattices only.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct BatchEntry {
@@ -903,21 +905,6 @@ struct BatchEntry {
   uint32_t first_block;
   uint32_t index;  // lattice number (keys the annealing draws)
 };
-
-// lattice owning block b: the last l with first_block[l] <= b (n >= 1)
-template <typename T>
-__device__ __forceinline__ int batch_lattice(const BatchEntry<T>* __restrict__ tab, int n,
-                                             uint32_t b) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tab[mid].first_block <= b)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
 
 // per-lattice update policy: the annealing draws of lattice l use the key
 // seed + l, so that a batched lattice draws what a run of it alone with that
@@ -945,10 +932,10 @@ __device__ __forceinline__ UpdSR<T> for_lattice(const UpdSR<T>& u, uint32_t l) {
 
 template <typename T, int NC, class Upd, int TPS, int NT, bool TRACK>
 __global__ __launch_bounds__(kBlock) void k_update_half_batch(const BatchEntry<T>* __restrict__ tab,
-                                                              const int n, const int parity,
-                                                              const Upd upd) {
+                                                              const uint32_t* __restrict__ map,
+                                                              const int parity, const Upd upd) {
   const uint32_t blk = sweep_block(parity);
-  const BatchEntry<T> e = tab[batch_lattice(tab, n, blk)];
+  const BatchEntry<T> e = tab[map[blk]];
   site_half_update<T, NC, kLandau, Upd, TPS, NT, TRACK>(
       e.U, e.L, parity, for_lattice(upd, e.index), e.Gx,
       (blk - e.first_block) * kBlock + threadIdx.x, nullptr);
@@ -1089,10 +1076,10 @@ __global__ __launch_bounds__(kBlock) void k_measure_mag(const v2<T>* __restrict_
 // partial[2*block + {0: F, 1: theta}]
 template <typename T, int NC>
 __global__ __launch_bounds__(kBlock) void k_measure_batch(const BatchEntry<T>* __restrict__ tab,
-                                                          const int n,
+                                                          const uint32_t* __restrict__ map,
                                                           double* __restrict__ partial) {
   __shared__ double lds[kBlock / 64];
-  const BatchEntry<T> e = tab[batch_lattice(tab, n, blockIdx.x)];
+  const BatchEntry<T> e = tab[map[blockIdx.x]];
   const Lat& L = e.L;
   const uint32_t h = (blockIdx.x - e.first_block) * kBlock + threadIdx.x;
   double f = 0, th = 0;
@@ -1331,6 +1318,27 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const v2<T>* __restrict__ src
   }
 }
 
+// canonical complex128 g[s][3][3] -> gauge-transformation field (rows 0 and
+// 1, rounded to Tg); grid ceil(V/kBlock)
+template <typename Tg>
+__global__ __launch_bounds__(kBlock) void k_pack_gauge(const double* __restrict__ src,
+                                                       v2<Tg>* __restrict__ G, const Lat L) {
+  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= 2 * L.vh) return;
+  const uint32_t h = s >> 1;
+  const Site S = site_of(L, h, 0);
+  const int p = (int)((S.t + S.z + S.y + (s & 1u)) & 1u);
+  const double* q = src + (size_t)s * 18;
+  v2<Tg>* d = G + link_offset<6, 1>(L.vp, p, 0, h);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    v2<Tg> v;
+    v.x = (Tg)q[2 * c];
+    v.y = (Tg)q[2 * c + 1];
+    d[c * kTile] = v;
+  }
+}
+
 // gauge-transformation field (rows 0 and 1 of g, ND = 1) -> canonical
 // complex128 g[s][3][3], row 2 rebuilt in FP64; grid ceil(V/kBlock)
 template <typename Tg>
@@ -1371,8 +1379,8 @@ __global__ __launch_bounds__(kBlock) void k_fill_unit(v2<T>* __restrict__ U, con
 // batched in-place reunitarisation of the lattices of a table (8 link blocks each)
 template <typename T, int NC>
 __global__ __launch_bounds__(kBlock) void k_reunitarize_batch(const BatchEntry<T>* __restrict__ tab,
-                                                              const int n) {
-  const BatchEntry<T> e = tab[batch_lattice(tab, n, blockIdx.x)];
+                                                              const uint32_t* __restrict__ map) {
+  const BatchEntry<T> e = tab[map[blockIdx.x]];
   const uint32_t h = (blockIdx.x - e.first_block) * kBlock + threadIdx.x;
   if (h >= e.L.vh) return;
 #pragma unroll 1

@@ -54,14 +54,14 @@ def test_fp32_12real_hot_annealing_stays_unitary(ctx, tps):
     40 steps without any reunitarisation stay at the FP32 rounding level."""
     dims = (4, 4, 4, 8)
     U = inputs.config0(dims, 0.3, 40)
-    ctx.set_sweep_variant(gf.FP32, gf.R12, tps, 0)
+    ctx.set_anneal_variant(gf.FP32, gf.R12, tps, 0)
     try:
         f, g = upload(ctx, U, gf.FP32, gf.R12)
         for k in range(40):
             ctx.anneal_sweep(f, g, gf.LANDAU, 1.2, 17, k, 2)
         W = download(ctx, f, g).reshape(-1, 3, 3)
     finally:
-        ctx.set_sweep_variant(gf.FP32, gf.R12, 0, -1)
+        ctx.set_anneal_variant(gf.FP32, gf.R12, 0, -1)
     dev = np.abs(W @ W.conj().transpose(0, 2, 1) - np.eye(3)).max()
     assert dev < 2e-6, dev
 

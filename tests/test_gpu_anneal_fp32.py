@@ -62,7 +62,7 @@ VARIANTS = [(tps, nt) for tps in (1, 2, 4) for nt in (0, 1, 2)]
 def test_fp32_micro_half_per_element(ctx, storage, gauge, tps, nt):
     U = inputs.config0(DIMS, 0.5, 61)
     ref0 = oracle_input(U, gf.FP32, storage)
-    ctx.set_sweep_variant(gf.FP32, storage, tps, nt)
+    ctx.set_anneal_variant(gf.FP32, storage, tps, nt)
     try:
         for parity in (0, 1):
             f, g = upload(ctx, U, gf.FP32, storage)
@@ -73,7 +73,7 @@ def test_fp32_micro_half_per_element(ctx, storage, gauge, tps, nt):
             err = np.abs(got - ref).max()
             assert err <= BAR, (parity, err)
     finally:
-        ctx.set_sweep_variant(gf.FP32, storage, 0, -1)
+        ctx.set_anneal_variant(gf.FP32, storage, 0, -1)
 
 
 @pytest.mark.parametrize("tps,nt", VARIANTS)
@@ -82,7 +82,7 @@ def test_fp32_micro_half_per_element(ctx, storage, gauge, tps, nt):
 def test_fp32_heatbath_half_per_element(ctx, storage, gauge, tps, nt):
     U = inputs.config0(DIMS, 0.5, 62)
     ref0 = oracle_input(U, gf.FP32, storage)
-    ctx.set_sweep_variant(gf.FP32, storage, tps, nt)
+    ctx.set_anneal_variant(gf.FP32, storage, tps, nt)
     border = total = 0
     try:
         for k, T in enumerate([1.45, 0.5, 0.05, 0.01]):
@@ -97,7 +97,7 @@ def test_fp32_heatbath_half_per_element(ctx, storage, gauge, tps, nt):
                 border += nb
                 total += ns
     finally:
-        ctx.set_sweep_variant(gf.FP32, storage, 0, -1)
+        ctx.set_anneal_variant(gf.FP32, storage, 0, -1)
     assert border <= max(2, total // 500), (border, total)
 
 
@@ -119,6 +119,7 @@ def test_fp32_tracked_micro_and_overrelaxation(ctx, storage, gauge, tps):
     U = inputs.config0(DIMS, 0.5, 63)
     ref0 = oracle_input(U, gf.FP32, storage)
     ctx.set_sweep_variant(gf.FP32, storage, tps, 0)
+    ctx.set_anneal_variant(gf.FP32, storage, tps, 0)
     try:
         for kind, parity in ((O.MICRO, 0), (O.OR, 1)):
             f, geom = upload(ctx, U, gf.FP32, storage)
@@ -137,6 +138,7 @@ def test_fp32_tracked_micro_and_overrelaxation(ctx, storage, gauge, tps):
             assert errU <= BAR and errg <= BAR, (kind, errU, errg)
     finally:
         ctx.set_sweep_variant(gf.FP32, storage, 0, -1)
+        ctx.set_anneal_variant(gf.FP32, storage, 0, -1)
 
 
 @pytest.mark.parametrize("tps", [1, 2, 4])
@@ -149,7 +151,7 @@ def test_fp32_tracked_heatbath(ctx, storage, gauge, tps):
     input transformed by the GPU's own g (eq. (4))."""
     U = inputs.config0(DIMS, 0.5, 64)
     ref0 = oracle_input(U, gf.FP32, storage)
-    ctx.set_sweep_variant(gf.FP32, storage, tps, 0)
+    ctx.set_anneal_variant(gf.FP32, storage, tps, 0)
     try:
         for parity, T in ((0, 1.2), (1, 0.02)):
             f, geom = upload(ctx, U, gf.FP32, storage)
@@ -169,7 +171,7 @@ def test_fp32_tracked_heatbath(ctx, storage, gauge, tps):
             O.gauge_transform(W, ggpu)
             assert np.abs(W - got).max() <= BAR
     finally:
-        ctx.set_sweep_variant(gf.FP32, storage, 0, -1)
+        ctx.set_anneal_variant(gf.FP32, storage, 0, -1)
 
 
 def test_fp32_heatbath_larger_lattice_borderline_rate(ctx):
@@ -192,3 +194,49 @@ def test_fp32_heatbath_larger_lattice_borderline_rate(ctx):
             total += ns
     say("borderline sites", border, "of", total)
     assert border <= max(2, total // 1000), (border, total)
+
+
+@pytest.mark.parametrize("tps", [1, 2, 4])
+@pytest.mark.parametrize("storage", [gf.R12, gf.R18])
+def test_fp32_tracked_accumulates_onto_g(ctx, storage, tps):
+    """g(x) <- Gtot g(x) onto a g that is not 1: G starts as a Haar-random
+    field from the generator (rounded to FP32 rows), one tracked half-sweep of
+    each kind; g after = the oracle's site transformation times g before."""
+    import torch
+    U = inputs.config0(DIMS, 0.5, 66)
+    h = inputs.haar_sites(DIMS, 91)
+    ref0 = oracle_input(U, gf.FP32, storage)
+    # what the FP32 rows of h hold, with row 2 rebuilt (the kernels' g)
+    h32 = h.astype(np.complex64).astype(np.complex128)
+    h32[..., 2, :] = np.conj(np.cross(h32[..., 0, :], h32[..., 1, :]))
+    hc = torch.from_numpy(np.ascontiguousarray(h).view(np.float64).reshape(-1).copy()).to("cuda")
+    ctx.set_sweep_variant(gf.FP32, storage, tps, 0)
+    ctx.set_anneal_variant(gf.FP32, storage, tps, 0)
+    try:
+        for kind, parity in ((O.MICRO, 1), (O.OR, 0), (O.HEATBATH, 1)):
+            f, geom = upload(ctx, U, gf.FP32, storage)
+            G = ctx.empty_gauge(geom)
+            ctx.gauge_pack(geom, hc, G)
+            if kind == O.MICRO:
+                ctx.micro_half_tracked(f, G, geom, gf.COULOMB, parity)
+            elif kind == O.OR:
+                ctx.sweep_tracked(f, G, geom, gf.COULOMB, parity, 1.7)
+            else:
+                ctx.heatbath_half_tracked(f, G, geom, gf.COULOMB, parity, 0.05, 3, 9)
+            ref = ref0.copy()
+            gh = O.half_sweep_g(ref, gf.COULOMB, parity, kind, omega=1.7, param=0.05, seed=3,
+                                sweep=9)
+            got_g = gauge_field(ctx, geom, G)
+            want = gh @ h32
+            if kind == O.HEATBATH:
+                sites, err = site_errors(DIMS, download(ctx, f, geom), ref, parity)
+                sel = np.ones(int(np.prod(DIMS)), dtype=bool)
+                sel[sites[err > BAR]] = False  # borderline sites are checked elsewhere
+                errg = np.abs(got_g.reshape(-1, 3, 3)[sel] - want.reshape(-1, 3, 3)[sel]).max()
+            else:
+                errg = np.abs(got_g - want).max()
+            say("tracked accumulation", kind, storage, tps, f"g {errg:.2e}")
+            assert errg <= BAR, (kind, errg)
+    finally:
+        ctx.set_sweep_variant(gf.FP32, storage, 0, -1)
+        ctx.set_anneal_variant(gf.FP32, storage, 0, -1)

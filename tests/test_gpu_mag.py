@@ -52,35 +52,89 @@ def test_mag_half_sweep_parity(ctx, dims, prec, storage, form, eps):
     _check(ctx, U, prec, storage, 1.7, form)
 
 
+def _embed(a, i, j):
+    G = np.eye(3, dtype=np.complex128)
+    G[i, i], G[i, j] = a[0] + 1j * a[3], a[2] + 1j * a[1]
+    G[j, i], G[j, j] = -a[2] + 1j * a[1], a[0] - 1j * a[3]
+    return G
+
+
+def _site_R(links, G=None):
+    """R of a site's 8 links (forward 0..3, backward 4..7) after G"""
+    if G is None:
+        G = np.eye(3)
+    f = G @ links[:4]
+    b = links[4:] @ G.conj().T
+    return float((np.abs(np.diagonal(f, axis1=1, axis2=2)) ** 2).sum()
+                 + (np.abs(np.diagonal(b, axis1=1, axis2=2)) ** 2).sum())
+
+
+def _last_step_excess(links):
+    """lambda_max of the (a0, a1, a2) block of the subgroup-(1,2) quadratic form
+    at these links minus its value at the identity (>= 0; 0 when the identity
+    is a maximiser), relative to lambda_max; the form by polarisation of R"""
+    C = _site_R(links, _embed(np.zeros(4), 1, 2))
+    E = np.eye(4)
+    Rk = [_site_R(links, _embed(E[k], 1, 2)) for k in range(4)]
+    M = np.zeros((4, 4))
+    for k in range(4):
+        M[k, k] = Rk[k] - C
+        for l in range(k + 1, 4):
+            M[k, l] = M[l, k] = 0.5 * (_site_R(links, _embed(E[k] + E[l], 1, 2)) - Rk[k] - Rk[l] + C)
+    lmax = np.linalg.eigvalsh(M[:3, :3])[-1]
+    return (lmax - M[0, 0]) / abs(lmax)
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.7])
 @pytest.mark.parametrize("prec,storage", [(gf.FP64, gf.R12), (gf.FP32, gf.R12)])
-def test_mag_rough_field_validity(ctx, prec, storage):
-    """Haar-scrambled rough field (small eigen-gaps at some sites): each GPU
-    half-sweep keeps the links unitary and the plaquette, never lowers F_MAG,
-    and agrees with the oracle on the bulk of the links."""
+def test_mag_rough_field_validity(ctx, prec, storage, omega):
+    """Haar-scrambled rough field, where some sites meet (nearly) degenerate
+    top eigenvalues of M, one half-sweep of each parity from the generator's
+    field. Every site either matches the oracle to the precision's bar, or
+    (a) the oracle meets a small relative eigen-gap at one of the site's
+    subgroup steps -- below |dM| / bar, the gap under which the rounding of M
+    (|dM| ~ 1e-14 relative in FP64, 1e-6 in FP32) can move the maximiser by
+    more than the bar (Davis-Kahan): 1e-2 in FP64, 5e-2 in FP32 -- so that the
+    maximiser there is not determined to the bar, and (b) at omega = 1 the GPU's
+    result is valid on its own terms: the site's R did not decrease and the
+    last subgroup step ended at a maximiser (the identity reaches the top
+    eigenvalue of the last subgroup's form at the GPU's links to rounding).
+    The field stays unitary and the plaquette is unchanged."""
+    from gpu_helpers import back_index, eight_links, site_errors
     dims = (4, 6, 8, 10)
     U = inputs.config0(dims, 0.6, 95)
-    ref = oracle_input(U, prec, storage)
-    f, g = upload(ctx, ref, prec, storage)
-    F, P = ctx.empty_out(1), ctx.empty_out(1)
-    ctx.functional(f, g, gf.MAG, F)
-    ctx.plaquette(f, g, P)
-    F0, P0 = F.item(), P.item()
-    for par in (0, 1, 0, 1):
-        ctx.sweep(f, g, gf.MAG, par, 1.7)
-        O.mag_sweep(ref, par, 1.7, 0)
-        ctx.functional(f, g, gf.MAG, F)
-        assert F.item() >= F0 - (1e-14 if prec == gf.FP64 else 1e-6)
-        F0 = F.item()
+    ref0 = oracle_input(U, prec, storage)
+    gap_res = 1e-2 if prec == gf.FP64 else 5e-2
+    rtol = 1e-12 if prec == gf.FP64 else 2e-5
+    b = back_index(dims)
+    total_diff = 0
+    for par in (0, 1):
+        f, g = upload(ctx, U, prec, storage)
+        P0, P1 = ctx.empty_out(1), ctx.empty_out(1)
+        ctx.plaquette(f, g, P0)
+        ctx.sweep(f, g, gf.MAG, par, omega)
+        ctx.plaquette(f, g, P1)
+        assert P1.item() == pytest.approx(P0.item(), abs=1e-13 if prec == gf.FP64 else 1e-5)
         got = download(ctx, f, g)
-        close = np.abs(got - ref).reshape(-1, 9).max(axis=1) <= TOL[prec]
-        say("  rough field: links within the bar %.4f" % close.mean())
-        assert close.mean() > 0.9
-        ref = got  # continue both from the GPU state
-    ctx.plaquette(f, g, P)
-    assert P.item() == pytest.approx(P0, abs=1e-13 if prec == gf.FP64 else 1e-5)
-    M = download(ctx, f, g).reshape(-1, 3, 3)
-    assert np.abs(M @ M.conj().transpose(0, 2, 1) - np.eye(3)).max() < (
-        1e-13 if prec == gf.FP64 else 1e-5)
+        ref = ref0.copy()
+        O.mag_sweep(ref, par, omega, 0)
+        sites, err = site_errors(dims, got, ref, par)
+        diff = sites[err > TOL[prec]]
+        total_diff += diff.size
+        for s in diff:
+            gaps = O.mag_site_gaps(ref0, int(s), omega, 0)
+            assert gaps.min() < gap_res, (int(s), gaps, float(err[sites == s][0]))
+            if omega == 1.0:
+                new = eight_links(got, dims, int(s), b)
+                old = eight_links(ref0, dims, int(s), b)
+                assert _site_R(new) >= _site_R(old) * (1 - rtol), int(s)
+                assert _last_step_excess(new) <= 10 * rtol, (int(s), _last_step_excess(new))
+        say(f"  rough field omega {omega} parity {par}: {diff.size} of {sites.size} sites "
+            f"differ beyond the bar, each at a near-degenerate step")
+        M = got.reshape(-1, 3, 3)
+        assert np.abs(M @ M.conj().transpose(0, 2, 1) - np.eye(3)).max() < (
+            1e-13 if prec == gf.FP64 else 1e-5)
+    say(f"  rough field: {total_diff} differing sites in all")
 
 
 @pytest.mark.parametrize("nt", [0, 1, 2])

@@ -232,28 +232,56 @@ def test_argument_errors_on_gpu(ctx):
 
 @pytest.mark.parametrize("prec,storage", [(gf.FP64, gf.R12), (gf.FP32, gf.R12)])
 def test_autotune_choice_and_parity_after(ctx, prec, storage):
-    """The autotuner times six variants on a copy of the caller's field, leaves
-    that field untouched, keeps a variant within 5% of the fastest (the
-    built-in one when it qualifies), and the tuned sweep still matches the
-    oracle."""
+    """The autotuner times the nine variants on a copy of the caller's field
+    (graph-replayed blocks, median of interleaved rounds), leaves that field
+    untouched, keeps the fastest for the field's size class only, and the
+    tuned sweep still matches the oracle."""
     dims = (6, 4, 8, 10)
     U = inputs.config0(dims, 0.6, 18)
     f, g = upload(ctx, U, prec, storage)
     before = download(ctx, f, g)
+    big = gf.Geom.make((72, 72, 72, 72), prec, storage)  # above 2 GiB: the other class
+    big_before = ctx.sweep_variant_for(big)
     say("autotune", prec, storage)
     try:
         (tps, nt), table = ctx.autotune(g, gf.LANDAU, U_like=f)
         assert set(table) == {(t, n) for t in (1, 2, 4) for n in (0, 1, 2)}
         assert all(v > 0 for v in table.values())
-        assert table[(tps, nt)] <= 1.05 * min(table.values())
-        default = (4, 0) if prec == gf.FP64 else (2, 0)
-        if table[default] <= 1.05 * min(table.values()):
-            assert (tps, nt) == default
+        assert table[(tps, nt)] == min(table.values())
+        assert ctx.sweep_variant_for(g) == (tps, nt)
         assert ctx.get_sweep_variant(prec, storage) == (tps, nt)
+        assert ctx.sweep_variant_for(big) == big_before
         assert np.array_equal(download(ctx, f, g), before)
         _half_sweep_check(ctx, U, prec, storage, gf.LANDAU)
     finally:
         ctx.set_sweep_variant(prec, storage, 0, -1)
+
+
+@pytest.mark.parametrize("gauge", [gf.LANDAU, gf.COULOMB])
+def test_autotune_anneal_and_storage(ctx, gauge):
+    """The annealing autotuner fills its own table (the sweep variant is left
+    as it was); the storage axis returns the storage whose best variant is
+    faster and tunes both; the caller's fields are untouched."""
+    import torch
+    dims = (6, 4, 8, 10)
+    U = inputs.config0(dims, 0.6, 28)
+    f, g = upload(ctx, U, gf.FP32, gf.R12)
+    before = download(ctx, f, g)
+    sweep_before = ctx.sweep_variant_for(g)
+    try:
+        (tps, nt), table = ctx.autotune_anneal(g, gauge, U_like=f, T=0.7)
+        assert table[(tps, nt)] == min(table.values()) and all(v > 0 for v in table.values())
+        assert ctx.anneal_variant_for(g) == (tps, nt)
+        assert ctx.sweep_variant_for(g) == sweep_before
+        assert np.array_equal(download(ctx, f, g), before)
+        canon = torch.from_numpy(U.view(np.float64).reshape(-1).copy()).to("cuda")
+        st, best = ctx.autotune_storage(g, gauge, canon)
+        assert st in (gf.R12, gf.R18) and best[st] == min(best.values()) > 0
+        say("storage axis", gauge, best)
+    finally:
+        for s_ in (gf.R12, gf.R18):
+            ctx.set_sweep_variant(gf.FP32, s_, 0, -1)
+        ctx.set_anneal_variant(gf.FP32, gf.R12, 0, -1)
 
 
 @pytest.mark.parametrize("prec,storage", COMBOS)
@@ -325,6 +353,9 @@ def test_built_in_variant_follows_field_size(ctx):
     assert ctx.sweep_variant_for(small) == (4, 0)
     assert ctx.sweep_variant_for(big) == (4, 1)
     assert ctx.sweep_variant_for(big32) == (2, 1)
+    # the annealing updates: FP32 one lane per site, FP64 four
+    assert ctx.anneal_variant_for(big32) == (1, 1)
+    assert ctx.anneal_variant_for(small) == (4, 0)
     assert ctx.get_sweep_variant(gf.FP64, gf.R12) == (4, 0)
     ctx.set_sweep_variant(gf.FP64, gf.R12, 2, 2)
     try:

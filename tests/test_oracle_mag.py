@@ -158,3 +158,18 @@ def test_mag_argument_errors():
     for bad in [(2, 1.7, 0), (0, 2.0, 0), (0, 1.7, 4)]:
         with pytest.raises(ValueError):
             O.mag_sweep(U, *bad)
+
+
+def test_mag_site_gaps_first_step_against_eigh():
+    """The gap of the first subgroup step is that of the 3x3 block of M at the
+    input (numpy eigh); later steps are taken on the updated links."""
+    dims = (4, 4, 2, 6)
+    U = inputs.config0(dims, 0.6, 77)
+    for s in (0, 5, 17, 40):
+        g = O.mag_site_gaps(U, s, 1.0)
+        ev = np.linalg.eigvalsh(O.mag_matrix(U, s, 0)[:3, :3])
+        assert g[0] == pytest.approx((ev[2] - ev[1]) / abs(ev[2]), rel=1e-9, abs=1e-14)
+        assert np.all(g >= 0) and np.all(g <= 2)
+    # the field is not changed
+    V = inputs.config0(dims, 0.6, 77)
+    assert np.array_equal(U, V)
