@@ -74,6 +74,9 @@ def parse():
                          "each of 16^4, 24^4, 12^3x24 with 2000 annealing steps then the mixed fix; "
                          "scan: 32^4 sweeps and time against the precision switch, omega and the "
                          "stochastic-relaxation probability; mag: 32^4 maximally Abelian gauge")
+    ap.add_argument("--variant", type=str, default="",
+                    help="probe: lanes,nontemporal of the FP64 12-real sweep (the benchmark's "
+                         "tuned variant), e.g. 4,2")
     ap.add_argument("--probe", action="store_true",
                     help="kernel probe for profilers: bandwidth probes of known size, then "
                          "20 sweeps of each storage variant on a generated input")
@@ -493,6 +496,9 @@ def probe_main(args):
             ctx.pack(g, canon, f)
             ctx.autotune(g, gf.LANDAU, U_like=f)
             del f
+    if args.variant:
+        tps, nt = (int(v) for v in args.variant.split(","))
+        ctx.set_sweep_variant(gf.FP64, gf.R12, tps, nt)
     log("probe: 20 sweeps per storage variant on", dims)
     res["variants"] = variant_rates(ctx, torch, gf, canon, dims, args.omega, n=20)
     ctx.close()

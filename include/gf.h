@@ -265,7 +265,8 @@ gf_status gf_anneal_variant_for(gf_ctx* ctx, const gf_geom* geom, int32_t* tps,
  * starts as a copy of U_like (a device field of geom; NULL: the unit field),
  * each of the nine variants (tps 1, 2, 4) x (nontemporal 0, 1, 2) runs a
  * block of RED/BLACK sweep pairs (omega 1.7) captured as a hipGraph, as the
- * drivers replay theirs (about 2 ms of work per block); the nine blocks are
+ * drivers replay theirs (100 sweeps, the drivers' check interval, or about
+ * 100 ms of work for large fields); the nine blocks are
  * replayed in turn for five rounds and each variant's time is the median of
  * its rounds. The fastest is kept on this context for geom's precision,
  * storage and size class, and returned. The caller's fields are not modified.

@@ -481,19 +481,23 @@ gf_status time_replay(gf_ctx* c, const TuneGraph& g, float* ms) {
 // The autotuner's timing, done the way the drivers run the kernels: for each
 // of the nine variants (lanes per site 1, 2, 4 x nontemporal mode 0, 1, 2) a
 // block of `reps` units of work (`unit` enqueues one: a RED/BLACK sweep pair,
-// or an annealing step) is captured as a hipGraph on the scratch field; the
+// or an annealing step) followed by `tail` (the drivers' check between
+// blocks) is captured as a hipGraph on the scratch field; the
 // nine graphs are then replayed in turn, round after round, and each variant
 // is timed by the median of its rounds, so that slow drifts and the order of
 // the variants weigh on all of them alike. Returns the median ms per unit in
 // times[9] (index 3 * mode + log2(lanes)).
-template <class Unit>
-gf_status tune_variants(gf_ctx* c, int kind, const gf_geom* g, Unit&& unit, int half_sweeps_per_unit,
-                        float times[kVariants]) {
+template <class Unit, class Tail>
+gf_status tune_variants(gf_ctx* c, int kind, const gf_geom* g, Unit&& unit, Tail&& tail,
+                        int half_sweeps_per_unit, float times[kVariants]) {
   const int i64 = g->prec == GF_FP64, i18 = g->storage == GF_R18;
   const int cls = size_class(gf_field_bytes(g));
   gf_ctx::Variant saved = c->var[kind][i64][i18][cls];
   gf_status st = GF_OK;
-  // size of a block: about 2 ms of work, from one timed unit of the built-in variant
+  // size of a block: 100 units, the drivers' check interval, capped at about
+  // 100 ms of work (one timed unit of the built-in variant sets the cap); with
+  // blocks of a few ms the stores-streamed variants timed up to 2% faster
+  // than they then ran between the checks of a fix at 32^4
   float ms1 = 0;
   if ((st = unit()) != GF_OK) return st;
   HIP_OR_FAIL(c, hipEventRecord(c->ev[0], c->stream));
@@ -501,7 +505,7 @@ gf_status tune_variants(gf_ctx* c, int kind, const gf_geom* g, Unit&& unit, int 
   HIP_OR_FAIL(c, hipEventRecord(c->ev[1], c->stream));
   HIP_OR_FAIL(c, hipEventSynchronize(c->ev[1]));
   HIP_OR_FAIL(c, hipEventElapsedTime(&ms1, c->ev[0], c->ev[1]));
-  const int reps = std::max(2, std::min(400, (int)std::ceil(2.0 / std::max(ms1, 1e-3f))));
+  const int reps = std::max(2, std::min(100, (int)std::ceil(100.0 / std::max(ms1, 1e-3f))));
   TuneGraph graphs[kVariants];
   for (int k = 0; k < kVariants && st == GF_OK; ++k) {
     c->var[kind][i64][i18][cls].tps = 1 << (k % 3);
@@ -511,7 +515,7 @@ gf_status tune_variants(gf_ctx* c, int kind, const gf_geom* g, Unit&& unit, int 
         gf_status s2 = unit();
         if (s2 != GF_OK) return s2;
       }
-      return GF_OK;
+      return tail();
     }, graphs[k]);
   }
   c->var[kind][i64][i18][cls] = saved;
@@ -576,10 +580,24 @@ gf_status gf_autotune(gf_ctx* c, const gf_geom* g, int32_t gauge, const void* U_
   gf_status st = tune_scratch(c, g, U_like, &scratch);
   if (st != GF_OK) return st;
   float times[kVariants] = {};
-  st = tune_variants(c, kSweepKind, g, [&]() -> gf_status {
-    gf_status s2 = gf_sweep(c, scratch, g, gauge, 0, 1.7);
-    return s2 != GF_OK ? s2 : gf_sweep(c, scratch, g, gauge, 1, 1.7);
-  }, 2, times);
+  // the drivers' check after each block: reunitarisation, F and theta (the
+  // partial sums and outputs allocated before the capture)
+  const int nout = gauge == GF_COULOMB ? g->nt : 1;
+  if ((st = ensure_partial(c, measure_partials(g))) == GF_OK) st = ensure_out(c, nout);
+  if (st == GF_OK)
+    st = tune_variants(
+        c, kSweepKind, g,
+        [&]() -> gf_status {
+          gf_status s2 = gf_sweep(c, scratch, g, gauge, 0, 1.7);
+          return s2 != GF_OK ? s2 : gf_sweep(c, scratch, g, gauge, 1, 1.7);
+        },
+        [&]() -> gf_status {
+          gf_status s2 = gf_reunitarize(c, scratch, g);
+          return s2 != GF_OK ? s2
+                             : measure_launch(c, scratch, g, gauge, c->dev_out, c->dev_out + c->out_cap,
+                                              c->partial);
+        },
+        2, times);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(scratch);
   if (st != GF_OK) return st;
@@ -600,12 +618,15 @@ gf_status gf_autotune_anneal(gf_ctx* c, const gf_geom* g, int32_t gauge, const v
   float times[kVariants] = {};
   // one step: heatbath RED and BLACK at T, one microcanonical sweep; the
   // step index is fixed, so every replay draws the same numbers
-  st = tune_variants(c, kAnnealKind, g, [&]() -> gf_status {
-    gf_status s2 = GF_OK;
-    for (int p = 0; p < 2 && s2 == GF_OK; ++p) s2 = gf_heatbath_half(c, scratch, g, gauge, p, T, 1, 0);
-    for (int p = 0; p < 2 && s2 == GF_OK; ++p) s2 = gf_micro_half(c, scratch, g, gauge, p);
-    return s2;
-  }, 4, times);
+  st = tune_variants(
+      c, kAnnealKind, g,
+      [&]() -> gf_status {
+        gf_status s2 = GF_OK;
+        for (int p = 0; p < 2 && s2 == GF_OK; ++p) s2 = gf_heatbath_half(c, scratch, g, gauge, p, T, 1, 0);
+        for (int p = 0; p < 2 && s2 == GF_OK; ++p) s2 = gf_micro_half(c, scratch, g, gauge, p);
+        return s2;
+      },
+      []() -> gf_status { return GF_OK; }, 4, times);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(scratch);
   if (st != GF_OK) return st;
