@@ -505,6 +505,43 @@ def probe_main(args):
     print(json.dumps(res), flush=True)
 
 
+def probe_batch_main(args):
+    """Short batch run for rocprofv3 counter runs: the stream probes, then the
+    192 lattices of the Gribov-copy batch (64 each of 16^4, 24^4, 12^3 x 24;
+    random fields, which move the same bytes as heatbath ones) through 2
+    annealing steps and 20 FP32 and 20 FP64 overrelaxation sweeps, every
+    lattice active in every launch."""
+    import torch
+
+    import inputs
+    import paper_1209_4008_amd as gf
+
+    ctx = gf.Context(0)
+    log("probe: stream probes (2 GiB, 10 reps each)")
+    res = {"probe": stream_probes(ctx, torch)}
+    geoms, fields = [], []
+    for k, dims in enumerate(((16, 16, 16, 16), (24, 24, 24, 24), (24, 12, 12, 12))):
+        g = gf.Geom.make(dims, gf.FP64, gf.R12)
+        for cp in range(64):
+            canon = inputs.gpu_config0(dims, 0.3, 100 * k + cp)
+            f = ctx.empty_field(g)
+            ctx.pack(g, canon, f)
+            geoms.append(g)
+            fields.append(f)
+    torch.cuda.synchronize()
+    sites = sum(g.volume for g in geoms)
+    log("probe: batch of", len(geoms), "lattices,", sites, "sites")
+    b = gf.Batch(ctx, geoms, fields)
+    p = gf.fix_params(omega=args.omega, theta_target=1e-300, theta_switch=1e-300, max_sweeps=20,
+                      check_every=10, sa_steps=2, sa_micro=1, sa_T0=1.0, sa_T1=0.5, seed=11)
+    r = b.run(p)
+    torch.cuda.synchronize()
+    b.close()
+    res["batch"] = {"lattices": len(geoms), "sites": sites, "sweeps": r[0].sweeps}
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
 def timed_fix(ctx, torch, fn):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -713,7 +750,10 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.probe:
-        probe_main(args)
+        if args.workload == "batch":
+            probe_batch_main(args)
+        else:
+            probe_main(args)
         return
     if args.workload == "coulomb":
         coulomb_main(args)

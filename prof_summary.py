@@ -2,6 +2,7 @@
 
   python prof_summary.py kernels STATS_CSV --command CMD
   python prof_summary.py counters FETCH_CSV WRITE_CSV --command CMD
+  python prof_summary.py busy TRACE_CSV --match REGEX --command CMD
 
 Measurement support for bench.py and profiles/, not part of the library.
 `kernels` turns a --kernel-trace --stats kernel_stats.csv into a table of
@@ -10,7 +11,11 @@ WRITE_SIZE, in KiB per dispatch) of `bench.py --probe` into HBM bytes per
 dispatch, each counter scaled by what it reads for the copy probe of known
 size (2 GiB read + 2 GiB written per dispatch), and compares the sweep kernels
 with their algorithmic bytes. Both embed the hash of the kernel sources so that
-a reader (bench.py) can tell whether the kernels changed since.
+a reader (bench.py) can tell whether the kernels changed since. `busy` splits a
+--kernel-trace kernel_trace.csv into stretches of GPU work separated by idle
+gaps longer than --split-ms (host-side set-up between runs) and reports, for
+each stretch that holds a kernel matching REGEX, how much of its wall time had
+a kernel running: the idle share a driver's host-side checks and launches cost.
 """
 import argparse
 import collections
@@ -47,9 +52,12 @@ def short_name(name):
 
 
 def sweep_bytes(name, V):
-    """Algorithmic bytes per launch of an overrelaxation half-sweep: V/2 sites,
-    each reading and writing 8 links of R reals of b bytes."""
-    m = re.match(r"k_update_half<(float|double),(\d+),\d+,UpdOR,\d+,\w+(?:,(\w+))?>", name)
+    """Algorithmic bytes per launch of a half-sweep (overrelaxation, heatbath or
+    microcanonical; one lattice or a batch of lattices of V sites in all): V/2
+    sites, each reading and writing 8 links of R reals of b bytes, and g (12
+    reals) read and written where it is tracked."""
+    m = (re.match(r"k_update_half<(float|double),(\d+),\d+,Upd(?:OR|HB|Micro),\d+,\w+,(\w+)>", name)
+         or re.match(r"k_update_half_batch<(float|double),(\d+),Upd(?:OR|HB|Micro),\d+,\w+,(\w+)>", name))
     if not m:
         return None
     b = 4 if m.group(1) == "float" else 8
@@ -88,11 +96,14 @@ def cmd_counters(args):
     V = 1
     for d in args.dims.split(","):
         V *= int(d)
-    out = {"kernel_source_hash": kernel_source_hash(), "lattice": args.dims,
+    if args.sites:
+        V = args.sites
+    out = {"kernel_source_hash": kernel_source_hash(), "lattice": args.dims, "sites": V,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
     print(f"# {args.title}\n")
     print(f"Commands:\n\n```\n{args.command}\n```\n")
-    print(f"Kernel sources hash: `{out['kernel_source_hash']}`. Lattice {args.dims}.\n")
+    print(f"Kernel sources hash: `{out['kernel_source_hash']}`. "
+          + (f"{V} sites in all.\n" if args.sites else f"Lattice {args.dims}.\n"))
     print(f"Calibration: the copy probe moves 2 GiB in and 2 GiB out per dispatch; FETCH_SIZE "
           f"reads {fetch[copy]:.0f} KiB and WRITE_SIZE {write[copy]:.0f} KiB for it, so the "
           f"counters are scaled by {f_scale:.4f} and {w_scale:.4f}.\n")
@@ -110,6 +121,62 @@ def cmd_counters(args):
         out["kernels"][k] = {"traffic_bytes": tot, "algorithmic_bytes": alg}
     print("\n```json")
     print(json.dumps(out, indent=1))
+    print("```")
+
+
+def cmd_busy(args):
+    rows = []
+    with open(args.csv) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"])))
+    rows.sort()
+    pat = re.compile(args.match)
+    split = args.split_ms * 1e6
+    # stretches: maximal runs of kernels whose idle gaps are all below split
+    stretches, cur, end = [], [], 0
+    for a, b, n in rows:
+        if cur and a - end > split:
+            stretches.append(cur)
+            cur = []
+        end = b if not cur else max(end, b)
+        cur.append((a, b, n))
+    if cur:
+        stretches.append(cur)
+    print(f"# {args.title}\n")
+    print(f"Command: `{args.command}`\n")
+    print(f"Kernel sources hash: `{kernel_source_hash()}`\n")
+    print(f"Stretches of GPU work split at idle gaps over {args.split_ms} ms; listed: those with a "
+          f"kernel matching `{args.match}`. Busy: the union of kernel intervals.\n")
+    print("| stretch | wall ms | kernels | matching | busy ms | busy % | gaps > 5 us | idle in them ms | "
+          "largest gap us |")
+    print("|---:|---:|---:|---:|---:|---:|---:|---:|---:|")
+    out = []
+    for i, st in enumerate(stretches):
+        m = sum(1 for _, _, n in st if pat.search(n))
+        if not m:
+            continue
+        busy, gaps, idle, big, hi = 0, 0, 0, 0, None
+        for a, b, _ in st:
+            if hi is None:
+                busy, hi = b - a, b
+                continue
+            if a > hi:
+                g = a - hi
+                if g > 5000:
+                    gaps += 1
+                    idle += g
+                big = max(big, g)
+                busy += b - a
+                hi = b
+            elif b > hi:
+                busy += b - hi
+                hi = b
+        wall = hi - st[0][0]
+        out.append({"wall_ms": wall / 1e6, "busy_frac": busy / wall})
+        print(f"| {i} | {wall / 1e6:.1f} | {len(st)} | {m} | {busy / 1e6:.1f} | {100 * busy / wall:.2f} | "
+              f"{gaps} | {idle / 1e6:.2f} | {big / 1e3:.1f} |")
+    print("\n```json")
+    print(json.dumps({"stretches": out}, indent=1))
     print("```")
 
 
@@ -135,12 +202,16 @@ def main(argv=None):
     c.add_argument("write")
     c.add_argument("--command", required=True)
     c.add_argument("--dims", default="32,32,32,32")
+    c.add_argument("--sites", type=int, default=0, help="sites in all (a batch), instead of --dims")
     c.add_argument("--title", default="HBM counters")
+    b = sub.add_parser("busy")
+    b.add_argument("csv")
+    b.add_argument("--match", required=True)
+    b.add_argument("--split-ms", type=float, default=20.0)
+    b.add_argument("--command", required=True)
+    b.add_argument("--title", default="GPU busy time")
     args = ap.parse_args(argv)
-    if args.cmd == "kernels":
-        cmd_kernels(args)
-    else:
-        cmd_counters(args)
+    {"kernels": cmd_kernels, "counters": cmd_counters, "busy": cmd_busy}[args.cmd](args)
 
 
 if __name__ == "__main__":
