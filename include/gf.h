@@ -17,12 +17,12 @@
  *   is split into a RED and a BLACK block and the site index runs fastest):
  *   complex elements of the precision `prec` (float2 or double2),
  *     elem(p, mu, c, h) at offset
- *       p*4*NC*Vp + (h/128)*128*4*NC + (mu*NC + c)*128 + h%128,
+ *       p*4*NC*Vp + (h/2048)*2048*4*NC + (mu*NC + c)*2048 + h%2048,
  *   p = parity, h = s >> 1 (the half index), c = 3a + b < NC,
  *   NC = storage/2: 9 complex (18 reals) or 6 complex (12 reals: rows 0 and 1;
  *   row 2 is rebuilt as conj(row0 x row1), Sec. 4.1), Vp = V/2 rounded up to
- *   a multiple of 128. That is, the sites of each parity are cut into tiles
- *   of 128 consecutive half indices; a tile holds its links direction after
+ *   a multiple of 2048. That is, the sites of each parity are cut into tiles
+ *   of 2048 consecutive half indices; a tile holds its links direction after
  *   direction and component after component, the site index running fastest.
  *   Elements of the padding sites h >= V/2 are never read. Size:
  *   gf_field_bytes() = 8 Vp storage prec bytes.
@@ -97,7 +97,7 @@ const char* gf_last_error(const gf_ctx* ctx);
 /* Host-only: GF_OK if geom is valid, GF_ERR_ARG otherwise. */
 gf_status gf_check_geom(const gf_geom* geom);
 /* Host-only: bytes of a device field, 8 Vp storage prec (Vp = V/2 rounded up
- * to a multiple of 128); 0 if geom invalid. */
+ * to a multiple of 2048); 0 if geom invalid. */
 size_t gf_field_bytes(const gf_geom* geom);
 /* Host-only: runs the library's host-side self checks (index arithmetic);
  * GF_OK when they pass. */
@@ -201,7 +201,7 @@ gf_status gf_philox(gf_ctx* ctx, const uint32_t* ctr_dev, uint64_t seed, uint32_
  * accumulates (Sec. 1, eq. (4): the result of a gauge fixing is the input
  * transformed by one g(x) per site): FP32, rows 0 and 1 of g(x) (row 2 =
  * conj(row0 x row1)), tiled like a 12-real device field with one direction:
- *   elem(p, c, h) at offset p*6*Vp + (h/128)*128*6 + c*128 + h%128, c = 3a + b.
+ *   elem(p, c, h) at offset p*6*Vp + (h/2048)*2048*6 + c*2048 + h%2048, c = 3a + b.
  * Host-only: its size in bytes, 96 Vp; 0 if geom is invalid. */
 size_t gf_gauge_bytes(const gf_geom* geom);
 /* G <- 1 at every site (the padding sites included). */

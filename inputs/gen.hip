@@ -371,11 +371,13 @@ __global__ void k_haar_copy(double* U, Lat L, uint64_t seed, uint32_t copy) {
 // config-0 links written straight into the gauge-fixing library's device
 // layout (its public header documents it), for lattices whose canonical FP64
 // form would not fit in device memory: complex element (p, mu, c, h) at
-//   p*4*nc*vp + (h/128)*128*4*nc + (mu*nc + c)*128 + h%128,
+//   p*4*nc*vp + (h/W)*W*4*nc + (mu*nc + c)*W + h%W,   W = kLayoutTile,
 // p = parity of the site, h = s >> 1, c = 3a + b < nc (nc = 6: rows 0 and 1;
-// nc = 9: all rows), vp = V/2 rounded up to a multiple of 128; T = float or
+// nc = 9: all rows), vp = V/2 rounded up to a multiple of W; T = float or
 // double, re and im interleaved. The link values are those of k_config0,
 // rounded to T.
+constexpr int64_t kLayoutTile = 2048;  // sites per tile of the documented layout
+
 template <typename T>
 __device__ void config0_packed_link(T* F, const Lat& L, int nc, int64_t vp, double eps,
                                     uint64_t seed, int64_t l) {
@@ -386,9 +388,10 @@ __device__ void config0_packed_link(T* F, const Lat& L, int nc, int64_t vp, doub
   coords(L, s, c4);
   const int64_t p = (c4[0] + c4[1] + c4[2] + c4[3]) & 1;
   const int64_t h = s >> 1;
-  const int64_t base = p * 4 * nc * vp + (h / 128) * 128 * 4 * nc + (int64_t)mu * nc * 128 + h % 128;
+  const int64_t W = kLayoutTile;
+  const int64_t base = p * 4 * nc * vp + (h / W) * W * 4 * nc + (int64_t)mu * nc * W + h % W;
   for (int c = 0; c < nc; ++c) {
-    T* q = F + 2 * (base + (int64_t)c * 128);
+    T* q = F + 2 * (base + (int64_t)c * W);
     q[0] = (T)A.e[c / 3][c % 3].re;
     q[1] = (T)A.e[c / 3][c % 3].im;
   }
@@ -529,7 +532,7 @@ int gen_gpu_config0_packed(void* F, const int32_t dims[4], int32_t prec_bytes, i
     return -1;
   const Lat L = make_lat(dims);
   if (L.V > ((int64_t)1 << 30)) return -1;
-  const int64_t vp = (L.V / 2 + 127) / 128 * 128;
+  const int64_t vp = (L.V / 2 + kLayoutTile - 1) / kLayoutTile * kLayoutTile;
   const int64_t n = 4 * L.V;
   const int64_t want = (n + 255) / 256;
   const unsigned blocks = (unsigned)(want < (1 << 20) ? want : (1 << 20));

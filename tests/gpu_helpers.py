@@ -8,6 +8,8 @@ import numpy as np
 import paper_1209_4008_amd as gf
 
 TOL = {gf.FP64: 1e-12, gf.FP32: 2e-5}
+# sites per tile of the device layout that gf.h documents
+LAYOUT_TILE = 2048
 
 
 def say(*a):
@@ -118,30 +120,94 @@ def eight_links(U, dims, s, b):
     return np.concatenate([U4[s], U4[b[s], np.arange(4)]])
 
 
+def site_transform_residual(in8, out8):
+    """How far out8 is from in8 transformed by one SU(3) matrix G at the site
+    (U_mu(x) -> G U_mu(x), U_mu(x - mu) -> U_mu(x - mu) G^dag, eq. (4)), with
+    G read off the first link; includes the unitarity of G."""
+    G = out8[0] @ in8[0].conj().T
+    r = np.abs(G @ G.conj().T - np.eye(3)).max()
+    for mu in range(4):
+        r = max(r, np.abs(out8[mu] - G @ in8[mu]).max(),
+                np.abs(out8[4 + mu] - in8[4 + mu] @ G.conj().T).max())
+    return r
+
+
+def heatbath_spread(U_in, dims, gauge, T, seed, sweep, s, b, n=16, rng_seed=0):
+    """How far the oracle's update of site s moves when each real component of
+    its 8 input links is perturbed by a relative N(0, 1) * 2^-23 (the unit
+    roundoff of FP32): the largest change of the site's 8 output links over n
+    perturbations. An FP32 computation of the same update, rounding at every
+    step, can differ from the FP64 result by a multiple of this without any
+    mistake."""
+    import oracle as O
+    V = int(np.prod(dims))
+    W = U_in.copy()
+    W4 = W.reshape(V, 4, 3, 3)
+    pos = [(s, mu) for mu in range(4)] + [(int(b[s, mu]), mu) for mu in range(4)]
+    orig = [W4[i, mu].copy() for i, mu in pos]
+    ref = W.copy()
+    O.heatbath_sites(ref, gauge, T, seed, sweep, [s])
+    e0 = eight_links(ref, dims, s, b)
+    rng = np.random.default_rng(rng_seed)
+    spread = 0.0
+    for _ in range(n):
+        for (i, mu), o in zip(pos, orig):
+            d = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+            W4[i, mu] = o.real * (1 + 2.0 ** -23 * d.real) + 1j * o.imag * (1 + 2.0 ** -23 * d.imag)
+        O.heatbath_sites(W, gauge, T, seed, sweep, [s])
+        spread = max(spread, np.abs(eight_links(W, dims, s, b) - e0).max())
+        for (i, mu), o in zip(pos, orig):
+            W4[i, mu] = o
+    return spread
+
+
 def heatbath_sites_check(dims, U_in, got, ref, gauge, T, seed, sweep, sites, bar, tau, what):
     """Heatbath half-sweep result `got` (GPU) against `ref` (oracle, from U_in)
-    at the given sites of one parity. A site within `bar` passes; a site
-    beyond it must have a borderline Kennedy-Pendleton trial (margin < tau,
-    oracle.heatbath_site_outcomes) and match one of the outcomes that deciding
-    such trials either way gives. Returns the number of borderline sites."""
+    at the given sites of one parity. A site within `bar` passes. A site
+    beyond it must either
+      - have a borderline Kennedy-Pendleton trial (margin < tau,
+        oracle.heatbath_site_outcomes) and match one of the outcomes that
+        deciding such trials either way gives, or
+      - be ill-conditioned: its update moves by spread(s) under FP32-level
+        perturbations of its inputs (heatbath_spread), and the bar scales
+        with that: |got - ref| <= bar * spread(s) / spread0, spread0 the
+        median spread of 8 sites that passed; such a site's result must also
+        be a transformation of its input by one SU(3) matrix (to 1e-5).
+    Returns the number of sites that needed either (each kind bounded by the
+    caller)."""
     import oracle as O
     b = back_index(dims)
-    border = 0
+    border = ill = 0
     worst = 0.0
+    passed = []
+    spread0 = None
     for s in sites:
         s = int(s)
         g8 = eight_links(got, dims, s, b)
         e = np.abs(g8 - eight_links(ref, dims, s, b)).max()
         if e <= bar:
             worst = max(worst, e)
+            passed.append(s)
             continue
         outs, mm = O.heatbath_site_outcomes(U_in, gauge, T, seed, sweep, s, tau)
-        assert len(outs) > 1, (what, "site", s, "has no borderline trial (smallest margin",
-                               mm, ") yet differs by", e)
-        best = min(np.abs(g8 - o).max() for o in outs)
-        assert best <= bar, (what, "site", s, "matches none of", len(outs),
-                             "outcomes; closest", best)
-        border += 1
+        if len(outs) > 1:
+            best = min(np.abs(g8 - o).max() for o in outs)
+            assert best <= bar, (what, "site", s, "matches none of", len(outs),
+                                 "outcomes; closest", best)
+            border += 1
+            continue
+        if spread0 is None:
+            others = [q for q in passed[:8]] or [int(q) for q in sites[:8] if int(q) != s]
+            spread0 = float(np.median([heatbath_spread(U_in, dims, gauge, T, seed, sweep, q, b)
+                                       for q in others]))
+        sp = heatbath_spread(U_in, dims, gauge, T, seed, sweep, s, b)
+        allowed = bar * max(1.0, sp / spread0)
+        res = site_transform_residual(eight_links(U_in, dims, s, b), g8)
+        say(what, "site", s, "no borderline trial (smallest margin", mm, "); differs by", e,
+            "spread", sp, "typical", spread0, "allowed", allowed, "SU(3) residual", res)
+        assert e <= allowed and res <= 1e-5, (what, "site", s, "differs by", e, "allowed", allowed,
+                                              "residual", res)
+        ill += 1
     say(what, f"max err at exactly decided sites {worst:.2e};",
-        f"borderline sites {border} of {len(sites)}")
-    return border
+        f"borderline sites {border}, ill-conditioned sites {ill} of {len(sites)}")
+    return border + ill

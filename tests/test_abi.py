@@ -39,9 +39,11 @@ def test_geometry_validation_and_sizes():
     assert gf.field_bytes(g) == 4 * 8 ** 4 * 18 * 8
     assert gf.field_bytes(gf.Geom.make((32, 32, 32, 32), gf.FP32, gf.R12)) == 4 * 32 ** 4 * 12 * 4
     assert gf.field_bytes(gf.Geom.make((48,) * 4, gf.FP64, gf.R12)) == 4 * 48 ** 4 * 12 * 8
-    # V/2 is padded to whole tiles of 128 sites: 6x4x2x10 has 240 sites per parity
-    assert gf.field_bytes(gf.Geom.make((6, 4, 2, 10), gf.FP32, gf.R18)) == 8 * 256 * 18 * 4
-    assert gf.field_bytes(gf.Geom.make((2, 2, 2, 2), gf.FP64, gf.R12)) == 8 * 128 * 12 * 8
+    # V/2 is padded to whole tiles of 2048 sites: 6x4x2x10 has 240 sites per
+    # parity, 10x8x10x14 5600 (two tiles and a ragged third)
+    assert gf.field_bytes(gf.Geom.make((6, 4, 2, 10), gf.FP32, gf.R18)) == 8 * 2048 * 18 * 4
+    assert gf.field_bytes(gf.Geom.make((2, 2, 2, 2), gf.FP64, gf.R12)) == 8 * 2048 * 12 * 8
+    assert gf.field_bytes(gf.Geom.make((10, 8, 10, 14), gf.FP64, gf.R12)) == 8 * 6144 * 12 * 8
     # the largest accepted volume, 2^30 sites: sizes computed without overflow
     big = gf.Geom.make((256, 256, 128, 128), gf.FP64, gf.R18)
     assert gf.check_geom(big) == gf.OK
@@ -54,7 +56,7 @@ def test_geometry_validation_and_sizes():
         assert gf.field_bytes(bad) == 0
     assert gf.lib().gf_check_geom(None) == gf.ERR_ARG
     # gauge-transformation field: FP32 rows 0 and 1 (6 complex) per padded site
-    assert gf.gauge_bytes(gf.Geom.make((6, 4, 2, 10), gf.FP32, gf.R12)) == 2 * 256 * 6 * 8
+    assert gf.gauge_bytes(gf.Geom.make((6, 4, 2, 10), gf.FP32, gf.R12)) == 2 * 2048 * 6 * 8
     assert gf.gauge_bytes(gf.Geom.make((32,) * 4, gf.FP32, gf.R18)) == 32 ** 4 * 6 * 8
     assert gf.gauge_bytes(gf.Geom.make((7, 8, 8, 8))) == 0
 

@@ -16,12 +16,12 @@ import pytest
 
 import inputs
 import paper_1209_4008_amd as gf
-from gpu_helpers import say, upload
+from gpu_helpers import LAYOUT_TILE, say, upload
 
 pytestmark = pytest.mark.gpu
 
 DEBUG_LIB = os.path.join(os.path.dirname(gf.__file__), "libgf_debug.so")
-DIMS = (6, 4, 6, 10)  # 720 sites per parity: five 128-site tiles and a ragged sixth
+DIMS = (10, 8, 10, 14)  # 5600 sites per parity: two 2048-site tiles and a ragged third
 
 
 @pytest.fixture(scope="module")
@@ -45,26 +45,28 @@ def expected_link_counts(geom):
     the padding of the last tile"""
     nc = geom.storage // 2
     vh = geom.volume // 2
-    vp = (vh + 127) // 128 * 128
+    W = LAYOUT_TILE
+    vp = (vh + W - 1) // W * W
     h = np.arange(vp)
     real = (h < vh).astype(np.uint32)
-    # element (p, mu, c, h) at p*4*NC*vp + (h//128)*128*4*NC + (mu*NC + c)*128 + h%128
+    # element (p, mu, c, h) at p*4*NC*vp + (h//W)*W*4*NC + (mu*NC + c)*W + h%W
     out = np.zeros(8 * nc * vp, dtype=np.uint32)
     for p in range(2):
         for mu in range(4):
             for c in range(nc):
-                off = p * 4 * nc * vp + (h // 128) * 128 * 4 * nc + (mu * nc + c) * 128 + h % 128
+                off = p * 4 * nc * vp + (h // W) * W * 4 * nc + (mu * nc + c) * W + h % W
                 out[off] = real
     return out
 
 
 def expected_gauge_counts(geom, parity):
     vh = geom.volume // 2
-    vp = (vh + 127) // 128 * 128
+    W = LAYOUT_TILE
+    vp = (vh + W - 1) // W * W
     h = np.arange(vp)
     out = np.zeros(2 * 6 * vp, dtype=np.uint32)
     for c in range(6):
-        off = parity * 6 * vp + (h // 128) * 128 * 6 + c * 128 + h % 128
+        off = parity * 6 * vp + (h // W) * W * 6 + c * W + h % W
         out[off] = (h < vh).astype(np.uint32)
     return out
 

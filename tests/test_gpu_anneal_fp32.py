@@ -32,7 +32,9 @@ pytestmark = pytest.mark.gpu
 
 BAR = 2e-5
 TAU = 1e-5
-DIMS = (6, 4, 6, 10)  # 720 sites per parity: five 128-site tiles and a ragged sixth
+DIMS = (6, 4, 6, 10)  # 720 sites per parity: one ragged 2048-site tile
+# 5120 sites per parity: two tiles and a ragged third
+DIMS_TILES = (8, 8, 10, 16)
 
 
 @pytest.fixture(scope="module")
@@ -74,6 +76,22 @@ def test_fp32_micro_half_per_element(ctx, storage, gauge, tps, nt):
             assert err <= BAR, (parity, err)
     finally:
         ctx.set_anneal_variant(gf.FP32, storage, 0, -1)
+
+
+@pytest.mark.parametrize("gauge", [gf.LANDAU, gf.COULOMB])
+@pytest.mark.parametrize("storage", [gf.R12, gf.R18])
+def test_fp32_micro_half_several_tiles(ctx, storage, gauge):
+    """the built-in variant on a lattice of several tiles and a ragged one"""
+    U = inputs.config0(DIMS_TILES, 0.5, 67)
+    ref0 = oracle_input(U, gf.FP32, storage)
+    for parity in (0, 1):
+        f, g = upload(ctx, U, gf.FP32, storage)
+        ctx.micro_half(f, g, gauge, parity)
+        got = download(ctx, f, g)
+        ref = ref0.copy()
+        O.micro_half(ref, gauge, parity)
+        err = np.abs(got - ref).max()
+        assert err <= BAR, (parity, err)
 
 
 @pytest.mark.parametrize("tps,nt", VARIANTS)
@@ -175,9 +193,10 @@ def test_fp32_tracked_heatbath(ctx, storage, gauge, tps):
 
 
 def test_fp32_heatbath_larger_lattice_borderline_rate(ctx):
-    """8x8x8x16 at the temperatures of the annealing schedules, built-in
-    variant: the per-site check and the rate of borderline sites."""
-    dims = (8, 8, 8, 16)
+    """8x8x10x16 (several tiles and a ragged one) at the temperatures of the
+    annealing schedules, built-in variant: the per-site check and the rate of
+    borderline sites."""
+    dims = DIMS_TILES
     U = inputs.config0(dims, 0.4, 65)
     ref0 = oracle_input(U, gf.FP32, gf.R12)
     border = total = 0
@@ -189,7 +208,7 @@ def test_fp32_heatbath_larger_lattice_borderline_rate(ctx):
             ref = ref0.copy()
             O.heatbath_half(ref, gf.COULOMB, parity, T, 5, k)
             nb, ns = check_heatbath(dims, ref0, got, ref, gf.COULOMB, parity, T, 5, k,
-                                    f"8x8x8x16 T={T} p={parity}")
+                                    f"8x8x10x16 T={T} p={parity}")
             border += nb
             total += ns
     say("borderline sites", border, "of", total)

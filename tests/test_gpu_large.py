@@ -12,7 +12,7 @@ import pytest
 import inputs
 import oracle as O
 import paper_1209_4008_amd as gf
-from gpu_helpers import TOL, rebuild_row2, say, site_parity, sites_links
+from gpu_helpers import LAYOUT_TILE, TOL, rebuild_row2, say, site_parity, sites_links
 
 @pytest.fixture(scope="module")
 def ctx():
@@ -28,11 +28,12 @@ def packed_index(dims, nc, s, mu):
     """complex-element indices of link (s, mu) in the tiled device layout
     (rows 0.. of the link, c = 3a + b < nc)"""
     V = int(np.prod(dims))
-    vp = (V // 2 + 127) // 128 * 128
+    W = LAYOUT_TILE
+    vp = (V // 2 + W - 1) // W * W
     p = site_parity(dims, s)
     h = s >> 1
-    base = p * 4 * nc * vp + (h // 128) * 128 * 4 * nc + mu * nc * 128 + h % 128
-    return [base + c * 128 for c in range(nc)]
+    base = p * 4 * nc * vp + (h // W) * W * 4 * nc + mu * nc * W + h % W
+    return [base + c * W for c in range(nc)]
 
 
 def gather(F, dims, prec, nc, links):
@@ -92,10 +93,11 @@ def test_mini_lattice_update_is_the_site_update():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("dims,prec", [((6, 4, 10, 12), gf.FP32), ((6, 4, 10, 12), gf.FP64)])
+@pytest.mark.parametrize("dims,prec", [((10, 8, 10, 14), gf.FP32), ((10, 8, 10, 14), gf.FP64)])
 @pytest.mark.parametrize("nc", [6, 9])
 def test_packed_generator_matches_canonical(ctx, dims, prec, nc):
-    """the packed-layout generator writes gpu_config0's links (ragged tail: V/2 = 1440)"""
+    """the packed-layout generator writes gpu_config0's links (V/2 = 5600: two
+    tiles and a ragged third)"""
     import torch
     storage = gf.R12 if nc == 6 else gf.R18
     geom = gf.Geom.make(dims, prec, storage)

@@ -16,7 +16,8 @@ from gpu_helpers import (TOL, download, oracle_input, say, site_parity, sites_li
 pytestmark = pytest.mark.gpu
 
 COMBOS = [(gf.FP64, gf.R18), (gf.FP64, gf.R12), (gf.FP32, gf.R18), (gf.FP32, gf.R12)]
-DIMS = [(8, 8, 8, 8), (6, 4, 2, 10), (2, 2, 2, 2), (4, 6, 8, 10)]
+# (10, 8, 10, 14): 5600 sites per parity, two 2048-site tiles and a ragged third
+DIMS = [(8, 8, 8, 8), (6, 4, 2, 10), (2, 2, 2, 2), (4, 6, 8, 10), (10, 8, 10, 14)]
 
 
 @pytest.fixture(scope="module")
@@ -75,7 +76,7 @@ def test_half_sweep_parity(ctx, dims, prec, storage, gauge):
 @pytest.mark.parametrize("tps", [1, 2, 4])
 @pytest.mark.parametrize("gauge", [gf.LANDAU, gf.COULOMB])
 @pytest.mark.parametrize("prec,storage", COMBOS)
-@pytest.mark.parametrize("dims", [(6, 4, 2, 10), (4, 6, 8, 10)])
+@pytest.mark.parametrize("dims", [(6, 4, 2, 10), (10, 8, 10, 14)])
 def test_half_sweep_parity_variants(ctx, dims, prec, storage, gauge, tps, nt):
     """Every variant of the sweep kernel (lanes per site x nontemporal) against the oracle."""
     U = inputs.config0(dims, 0.6, 17)
