@@ -242,10 +242,11 @@ gf_status gf_micro_half_tracked(gf_ctx* ctx, void* U, void* G, const gf_geom* ge
  * each per (precision, storage) and per size class (fields of at most 2 GiB,
  * larger ones). These calls set both size classes; the autotuners set the
  * class of the field they time.
- * tps = 0 / nontemporal = -1 restore the built-in defaults: 4 lanes for FP64;
- * for FP32 2 lanes (sweeps) and 1 lane (annealing); nontemporal 0 for fields
- * of at most 2 GiB (the Infinity Cache then serves part of every half-sweep),
- * 1 for larger ones. */
+ * tps = 0 / nontemporal = -1 restore the built-in defaults: for FP64 4 lanes,
+ * except 1 lane for the sweeps over more than 2 GiB of fields; for FP32 2
+ * lanes (sweeps) and 1 lane (annealing); nontemporal 0 for fields of at most
+ * 2 GiB (the Infinity Cache then serves part of every half-sweep), 1 for
+ * larger ones. */
 gf_status gf_set_sweep_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t tps,
                                int32_t nontemporal);
 gf_status gf_set_anneal_variant(gf_ctx* ctx, int32_t prec, int32_t storage, int32_t tps,

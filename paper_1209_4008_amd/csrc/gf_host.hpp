@@ -199,17 +199,7 @@ static inline gf_status ensure_out(gf_ctx* c, size_t n) {
 
 #define CHECK_GEOM(c, g, what) \
   if (!geom_ok(g)) return fail((c), GF_ERR_ARG, "%s: invalid geometry", what)
-// Built-in lanes per site: FP64 4 (one lane cannot hold 8 FP64 links in
-// registers), FP32 overrelaxation 2. The FP32 annealing updates run 1 lane: the
-// heatbath's draws and trials then cost a lane no more than with 2 lanes,
-// and at 32^3 x 64 (tracked, 12 reals) 1 lane took 143.4 / 145.6 / 171.8 us
-// per half-sweep at T = 0.05 / 0.5 / 1.45 against 155.4 / 157.3 / 169.4 with 2
-// (microcanonical 143.7 against 144.8).
 constexpr int kSweepKind = 0, kAnnealKind = 1;
-static inline int default_tps(const gf_geom* g, int kind = kSweepKind) {
-  if (g->prec == GF_FP64) return 4;
-  return kind == kAnnealKind ? 1 : 2;
-}
 // variants timed by the autotuner: lanes per site 1, 2, 4 x nontemporal mode
 // kNTNone, kNTAll, kNTStores, index 3 * mode + log2(lanes)
 constexpr int kVariants = 9;
@@ -223,6 +213,20 @@ constexpr int kVariants = 9;
 constexpr size_t kStreamBytes = (size_t)2 << 30;
 static inline int default_nt_bytes(size_t bytes) { return bytes > kStreamBytes ? kNTAll : kNTNone; }
 static inline int default_nt(const gf_geom* g) { return default_nt_bytes(gf_field_bytes(g)); }
+// Built-in lanes per site, for launches over `bytes` of fields. FP64: 4 lanes
+// (three waves per SIMD) with the cached accesses of fields up to 2 GiB; one
+// lane (all 8 links of a site in its registers, one wave per SIMD) with the
+// streamed accesses above, where it sweeps fastest: the 192-lattice batch
+// (10.8 GB) FP64 half-sweep 3.55 ms with 1 lane against 3.86 ms with 4 and
+// 4.08 ms with 2. FP32 overrelaxation 2. The FP32 annealing updates run 1
+// lane: the heatbath's draws and trials then cost a lane no more than with
+// 2 lanes, and at 32^3 x 64 (tracked, 12 reals) 1 lane took 143.4 / 145.6 /
+// 171.8 us per half-sweep at T = 0.05 / 0.5 / 1.45 against 155.4 / 157.3 /
+// 169.4 with 2 (microcanonical 143.7 against 144.8).
+static inline int default_tps_bytes(const gf_geom* g, int kind, size_t bytes) {
+  if (g->prec == GF_FP64) return (kind == kSweepKind && bytes > kStreamBytes) ? 1 : 4;
+  return kind == kAnnealKind ? 1 : 2;
+}
 
 // the stores-only nontemporal mode is instantiated for the overrelaxation
 // sweeps (all forms of g^omega and stochastic relaxation: the same
@@ -366,7 +370,7 @@ static inline const gf_ctx::Variant& ctx_var(const gf_ctx* c, int kind, const gf
 // lattices' fields), of geometry g's precision and storage
 static inline int ctx_tps_bytes(const gf_ctx* c, const gf_geom* g, int kind, size_t bytes) {
   const int t = ctx_var(c, kind, g, bytes).tps;
-  return t > 0 ? t : default_tps(g, kind);
+  return t > 0 ? t : default_tps_bytes(g, kind, bytes);
 }
 static inline int ctx_nt_bytes(const gf_ctx* c, const gf_geom* g, int kind, size_t bytes) {
   const int t = ctx_var(c, kind, g, bytes).nt;

@@ -346,13 +346,14 @@ def test_nontemporal_modes_change_no_bit(ctx, tps):
 
 
 def test_built_in_variant_follows_field_size(ctx):
-    """Cached link accesses up to 2 GiB fields, streamed above (no memory is
-    touched: only the choice is queried); a set variant applies to every size."""
+    """Cached link accesses up to 2 GiB fields, streamed above, and FP64 one lane
+    per site with the streamed accesses (no memory is touched: only the choice
+    is queried); a set variant applies to every size."""
     small = gf.Geom.make((32, 32, 32, 32), gf.FP64, gf.R12)   # 0.4 GB
     big = gf.Geom.make((72, 72, 72, 72), gf.FP64, gf.R12)     # 10.3 GB
     big32 = gf.Geom.make((64, 64, 64, 64), gf.FP32, gf.R12)   # 3.2 GB
     assert ctx.sweep_variant_for(small) == (4, 0)
-    assert ctx.sweep_variant_for(big) == (4, 1)
+    assert ctx.sweep_variant_for(big) == (1, 1)
     assert ctx.sweep_variant_for(big32) == (2, 1)
     # the annealing updates: FP32 one lane per site, FP64 four
     assert ctx.anneal_variant_for(big32) == (1, 1)
