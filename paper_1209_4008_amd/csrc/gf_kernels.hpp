@@ -881,8 +881,18 @@ __device__ __forceinline__ void site_mag_update(v2<T>* __restrict__ U, const Lat
   }
 }
 
+// occupancy request of the MAG kernels: FP64 with 2 lanes per site needs a
+// few registers more than two waves per SIMD allow (the 2048-site tiles put
+// the link components 32 KB apart, beyond the loads' immediate offsets, so
+// each component needs its own address); two waves with a few registers
+// spilled beat one wave
+template <typename T, int TPS>
+struct MagWaves {
+  static constexpr int value = (sizeof(T) == 8 && TPS == 2) ? 2 : 1;
+};
+
 template <typename T, int NC, class Upd, int TPS, int NT, bool TRACK = false>
-__global__ __launch_bounds__(kBlock) void k_mag_half(v2<T>* __restrict__ U, const Lat L,
+__global__ __launch_bounds__(kBlock, (MagWaves<T, TPS>::value)) void k_mag_half(v2<T>* __restrict__ U, const Lat L,
                                                      const int parity, const Upd upd,
                                                      v2<T>* __restrict__ Gx = nullptr) {
   site_mag_update<T, NC, Upd, TPS, NT, TRACK>(U, L, parity, upd, Gx,
