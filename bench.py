@@ -74,6 +74,10 @@ def parse():
                          "each of 16^4, 24^4, 12^3x24 with 2000 annealing steps then the mixed fix; "
                          "scan: 32^4 sweeps and time against the precision switch, omega and the "
                          "stochastic-relaxation probability; mag: 32^4 maximally Abelian gauge")
+    ap.add_argument("--check-log", type=str, default="",
+                    help="write the check logs of the full mixed and FP64 fixes (one JSON "
+                         "line per check: sweeps, precision, F, theta, unitarity deviation, "
+                         "elapsed ms) to this file")
     ap.add_argument("--variant", type=str, default="",
                     help="probe: lanes,nontemporal of the FP64 12-real sweep (the benchmark's "
                          "tuned variant), e.g. 4,2")
@@ -575,22 +579,55 @@ def tune_phases(ctx, gf, canon, pairs, gauge):
     return tuning
 
 
-def mixed_vs_fp64(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi, params, V):
-    """the full mixed fix and the full FP64 fix of the same input, each timed"""
+def monitored(gf, params, n):
+    """a copy of params with the unitarity monitor on and a check log of n records"""
+    import ctypes as C
+    p = type(params).from_buffer_copy(params)
+    log_ = gf.check_log(n)
+    p.flags |= gf.FLAG_MONITOR
+    p.check_log = C.cast(log_, C.POINTER(gf.CheckRecord))
+    p.check_log_cap = n
+    return p, log_
+
+
+def log_summary(gf, r, log_):
+    """records of a fix's check log, and the largest unitarity deviation met at
+    the checks of each precision"""
+    recs = [log_[k].as_dict() for k in range(r.check_log_n)]
+    worst = {}
+    for e in recs:
+        worst[e["precision"]] = max(worst.get(e["precision"], 0.0), e["unitarity"])
+    return recs, {"checks_logged": len(recs),
+                  "unitarity_max_at_checks": {k: float("%.3g" % v) for k, v in worst.items()}}
+
+
+def mixed_vs_fp64(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi, params, V, log_path=None):
+    """the full mixed fix and the full FP64 fix of the same input, each timed,
+    with the unitarity monitor and a check log (written as JSON lines to
+    log_path if given)"""
+    cap = params.max_sweeps * 2 // params.check_every + 8
+    pm, log_m = monitored(gf, params, cap)
     ctx.pack(ghi, canon, U_hi)
-    r, t_mixed = timed_fix(ctx, torch, lambda: ctx.fix_mixed(U_lo, glo, U_hi, ghi, gf.LANDAU,
-                                                             params))
+    r, t_mixed = timed_fix(ctx, torch, lambda: ctx.fix_mixed(U_lo, glo, U_hi, ghi, gf.LANDAU, pm))
     log(f"mixed: {r.sweeps} sweeps ({r.sweeps_lo} FP32) in {t_mixed:.2f} s, theta {r.theta:.3e}")
+    p64, log_64 = monitored(gf, params, cap)
     ctx.pack(ghi, canon, U_hi)
-    r64, t64 = timed_fix(ctx, torch, lambda: ctx.fix(U_hi, ghi, gf.LANDAU, params))
+    r64, t64 = timed_fix(ctx, torch, lambda: ctx.fix(U_hi, ghi, gf.LANDAU, p64))
     log(f"fp64: {r64.sweeps} sweeps in {t64:.2f} s, theta {r64.theta:.3e}")
+    recs_m, sum_m = log_summary(gf, r, log_m)
+    recs_64, sum_64 = log_summary(gf, r64, log_64)
+    if log_path:
+        with open(log_path, "a") as fh:
+            for run, recs in (("mixed", recs_m), ("fp64", recs_64)):
+                for e in recs:
+                    fh.write(json.dumps(dict(run=run, lattice=list(ghi.dims), **e)) + "\n")
     return r, t_mixed, r64, t64, {
         "mixed": {"time_ms": round(1e3 * t_mixed, 1), "sweeps": r.sweeps,
                   "sweeps_fp32": r.sweeps_lo, "status": r.status, "F": r.F, "theta": r.theta,
-                  "site_updates_per_s": round(V * r.sweeps / t_mixed, 0)},
+                  "site_updates_per_s": round(V * r.sweeps / t_mixed, 0), **sum_m},
         "fp64_only": {"time_ms": round(1e3 * t64, 1), "sweeps": r64.sweeps, "status": r64.status,
                       "F": r64.F, "theta": r64.theta,
-                      "site_updates_per_s": round(V * r64.sweeps / t64, 0)},
+                      "site_updates_per_s": round(V * r64.sweeps / t64, 0), **sum_64},
         "mixed_speedup_vs_fp64": round(t64 / t_mixed, 4),
         "final_F_rel_diff_mixed_vs_fp64": abs(r.F - r64.F) / abs(r64.F)}
 
@@ -609,7 +646,7 @@ def landau32_secondary(ctx, torch, gf, inputs, args):
                            max_sweeps=args.max_sweeps, check_every=args.check_every,
                            flags=gf.FLAG_TIMING | gf.FLAG_GRAPH)
     r, t_mixed, r64, t64, out = mixed_vs_fp64(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi,
-                                              params, V)
+                                              params, V, log_path=args.check_log or None)
     tps, nt = ctx.sweep_variant_for(ghi)
     kname = "k_update_half<double,6,0,UpdOR,%d,%d,false>" % (tps, nt)
     roof = kernel_roofline(r64.kernel_ms[1], r64.kernel_launches[1], V, 16 * 12 * 8, kname, dims)
@@ -684,7 +721,7 @@ def headline_main(args):
                                 check_every=args.check_every, flags=flags)
     extras = {}
     r, t_mixed, r64, t64, cmp = mixed_vs_fp64(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi,
-                                              full_params, V)
+                                              full_params, V, log_path=args.check_log or None)
     extras.update(cmp)
     extras["mixed_fp64_phase_roofline"] = kernel_roofline(r.kernel_ms[1], r.kernel_launches[1],
                                                           V, 16 * 12 * 8, kname, dims)

@@ -298,6 +298,14 @@ gf_status gf_autotune_storage(gf_ctx* ctx, const gf_geom* geom, int32_t gauge,
  * stream; time it with events around the call. */
 gf_status gf_stream_probe(gf_ctx* ctx, const void* src, void* dst, size_t bytes, int32_t kind);
 
+/* Unitarity monitor: into dev_out (device, 1 double) the largest
+ * |(U U^dag)_ab - delta_ab| over all links and elements (row 2 of 12-real
+ * links rebuilt first, everything in FP64); +Inf if any link holds a NaN.
+ * SU(3) links give 0 up to rounding; the rounding of the updates makes it
+ * grow between the drivers' reunitarisations, which remove it. Uses the
+ * context's partial-sum buffer. */
+gf_status gf_unitarity(gf_ctx* ctx, const void* U, const gf_geom* geom, double* dev_out);
+
 /* ---- drivers (the while-theta loop of Alg. 1) ------------------------------- */
 #define GF_FLAG_TIMING 1u    /* record hipEvent kernel timings into the result */
 #define GF_FLAG_GRAPH 2u     /* replay the sweeps between checks as a hipGraph */
@@ -312,6 +320,21 @@ gf_status gf_stream_probe(gf_ctx* ctx, const void* src, void* dst, size_t bytes,
  * timeslice only, so the frozen timeslices keep the theta_t they converged
  * with, and the sweeps go to the ones that have not. */
 #define GF_FLAG_FREEZE_TIMESLICES 8u
+/* At every check, before its reunitarisation, measure the field's unitarity
+ * deviation (gf_unitarity): the drift that the sweeps since the previous
+ * check left in the links. Reported in gf_fix_result.unitarity_max and, per
+ * check, in the check log. Not used by gf_batch_run. */
+#define GF_FLAG_MONITOR 16u
+
+/* One check of gf_fix or gf_fix_mixed, written to params.check_log. */
+typedef struct {
+  int32_t sweeps;          /* sweeps of the phase before this check                */
+  int32_t prec;            /* GF_FP32 or GF_FP64: the field checked                */
+  double F, theta;         /* as in gf_fix_result (Coulomb: mean F, max theta)     */
+  double unitarity;        /* GF_FLAG_MONITOR: the field's unitarity deviation
+                              before the check's reunitarisation; else -1          */
+  double elapsed_ms;       /* host time since the call started                     */
+} gf_check_record;
 
 typedef struct {
   double omega;            /* overrelaxation parameter, [1, 2)                         */
@@ -336,6 +359,11 @@ typedef struct {
    * gf_sweep_sr with this probability, sweep index = sweeps of the phase, key
    * = seed; the sweeps are then launched one by one (no graph replay) */
   double sr_prob;
+  /* optional host array of check_log_cap records: the drivers write one per
+   * check, in order, until it is full (gf_fix_result.check_log_n counts them;
+   * NULL: no log). Not used by gf_batch_run. */
+  gf_check_record* check_log;
+  int32_t check_log_cap;
 } gf_fix_params;
 
 typedef struct {
@@ -354,6 +382,9 @@ typedef struct {
   int32_t sa_steps;        /* annealing steps done                                 */
   int32_t frozen_slice_sweeps; /* GF_FLAG_FREEZE_TIMESLICES: sum over sweeps of the
                               number of frozen timeslices (work not done)         */
+  int32_t check_log_n;     /* records written to params.check_log                  */
+  double unitarity_max;    /* GF_FLAG_MONITOR: the largest unitarity deviation of
+                              any check; else -1                                  */
 } gf_fix_result;
 
 /* Runs the annealing schedule of params (if sa_steps > 0), then sweeps U (in

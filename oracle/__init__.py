@@ -61,6 +61,7 @@ def lib():
             "or_theta_K": (C.c_double, [d, i32p, C.c_int, d]),
             "or_reunitarize": (None, [d, C.c_int64]),
             "or_plaquette": (C.c_double, [d, i32p]),
+            "or_unitarity": (C.c_double, [d, i32p]),
             "or_gauge_transform": (C.c_int, [d, i32p, d]),
             "or_fix": (C.c_int, [d, i32p, C.c_int, C.c_double, C.c_int, C.c_double, C.c_int32,
                                  C.c_int32, C.c_int32, i32p, d, d]),
@@ -271,6 +272,11 @@ def reunitarize(U):
 
 def plaquette(U):
     return lib().or_plaquette(_field(U), _dims(dims_of(U)))
+
+
+def unitarity(U):
+    """max over links and elements of |(U U^dag - 1)_ab| (+inf for NaN)"""
+    return lib().or_unitarity(_field(U), _dims(dims_of(U)))
 
 
 def gauge_transform(U, g):

@@ -89,6 +89,9 @@ double or_theta_A(const double* U, const int32_t dims[4], int gauge, double* out
 double or_theta_K(const double* U, const int32_t dims[4], int gauge, double* out);
 /* Gram-Schmidt projection of each link back onto SU(3). */
 void   or_reunitarize(double* U, int64_t n_links);
+/* Unitarity deviation: max over links and elements of |(U U^dag - 1)_ab|;
+ * +Inf if a link holds a NaN. */
+double or_unitarity(const double* U, const int32_t dims[4]);
 /* Average plaquette (1/3) Re tr of the elementary plaquette. */
 double or_plaquette(const double* U, const int32_t dims[4]);
 /* U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger, g[s][3][3] complex128 (eq. (4)). */

@@ -933,6 +933,27 @@ void or_reunitarize(double* U, int64_t n_links) {
   }
 }
 
+/* Unitarity deviation: the largest modulus of an element of U U^dag - 1 over
+ * all links (the definition, with full 3x3 products); NaN gives +Inf. */
+double or_unitarity(const double* U, const int32_t dims[4]) {
+  lat_t L = make_lat(dims);
+  double worst = 0.0;
+  for (int64_t s = 0; s < L.V; ++s)
+    for (int mu = 0; mu < 4; ++mu) {
+      mat3 A = get_link(U, s, mu);
+      mat3 Ad = mat_dag(&A);
+      mat3 P = mat_mul(&A, &Ad);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double re = P.m[a][b].re - (a == b ? 1.0 : 0.0), im = P.m[a][b].im;
+          double m = sqrt(re * re + im * im);
+          if (m != m) return HUGE_VAL;
+          if (m > worst) worst = m;
+        }
+    }
+  return worst;
+}
+
 double or_plaquette(const double* U, const int32_t dims[4]) {
   lat_t L = make_lat(dims);
   double* per_site = (double*)malloc(sizeof(double) * (size_t)L.V);

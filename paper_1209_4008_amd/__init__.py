@@ -16,7 +16,7 @@ ERR_ARG, ERR_UNSUPPORTED, ERR_DEVICE, ERR_HIP, ERR_NONFINITE, ERR_NOMEM = -1, -2
 LANDAU, COULOMB, MAG = 0, 1, 2
 FP32, FP64 = 4, 8
 R12, R18 = 12, 18
-FLAG_TIMING, FLAG_GRAPH, FLAG_NO_TRACK, FLAG_FREEZE_TIMESLICES = 1, 2, 4, 8
+FLAG_TIMING, FLAG_GRAPH, FLAG_NO_TRACK, FLAG_FREEZE_TIMESLICES, FLAG_MONITOR = 1, 2, 4, 8, 16
 
 
 class GFError(RuntimeError):
@@ -43,6 +43,16 @@ class Geom(C.Structure):
         return self.nt * self.nz * self.ny * self.nx
 
 
+class CheckRecord(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("prec", C.c_int32), ("F", C.c_double),
+                ("theta", C.c_double), ("unitarity", C.c_double), ("elapsed_ms", C.c_double)]
+
+    def as_dict(self):
+        return {"sweeps": self.sweeps, "precision": "fp32" if self.prec == FP32 else "fp64",
+                "F": self.F, "theta": self.theta, "unitarity": self.unitarity,
+                "elapsed_ms": self.elapsed_ms}
+
+
 class FixParams(C.Structure):
     _fields_ = [("omega", C.c_double), ("theta_target", C.c_double),
                 ("theta_switch", C.c_double), ("max_sweeps", C.c_int32),
@@ -50,7 +60,8 @@ class FixParams(C.Structure):
                 ("flags", C.c_uint32), ("sa_steps", C.c_int32), ("sa_micro", C.c_int32),
                 ("sa_reunit_every", C.c_int32), ("or_form", C.c_int32),
                 ("sa_T0", C.c_double), ("sa_T1", C.c_double), ("seed", C.c_uint64),
-                ("sr_prob", C.c_double)]
+                ("sr_prob", C.c_double), ("check_log", C.POINTER(CheckRecord)),
+                ("check_log_cap", C.c_int32)]
 
 
 class FixResult(C.Structure):
@@ -58,7 +69,8 @@ class FixResult(C.Structure):
                 ("checks", C.c_int32), ("F", C.c_double), ("theta", C.c_double),
                 ("theta_at_switch", C.c_double), ("wall_ms", C.c_double),
                 ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_int64 * 6),
-                ("sa_steps", C.c_int32), ("frozen_slice_sweeps", C.c_int32)]
+                ("sa_steps", C.c_int32), ("frozen_slice_sweeps", C.c_int32),
+                ("check_log_n", C.c_int32), ("unitarity_max", C.c_double)]
 
     def as_dict(self):
         return {"status": self.status, "sweeps": self.sweeps, "sweeps_lo": self.sweeps_lo,
@@ -66,7 +78,8 @@ class FixResult(C.Structure):
                 "theta_at_switch": self.theta_at_switch, "wall_ms": self.wall_ms,
                 "kernel_ms": list(self.kernel_ms),
                 "kernel_launches": list(self.kernel_launches), "sa_steps": self.sa_steps,
-                "frozen_slice_sweeps": self.frozen_slice_sweeps}
+                "frozen_slice_sweeps": self.frozen_slice_sweeps, "check_log_n": self.check_log_n,
+                "unitarity_max": self.unitarity_max}
 
 
 # every symbol of include/gf.h with its ctypes signature
@@ -90,6 +103,7 @@ SIGNATURES = {
     "gf_theta": (C.c_int32, [_vp, _dp, _gp, C.c_int32, _dp]),
     "gf_measure": (C.c_int32, [_vp, _dp, _gp, C.c_int32, _dp, _dp]),
     "gf_measure_static": (C.c_int32, [_vp, _dp, _gp, C.c_int32, _dp, _dp]),
+    "gf_unitarity": (C.c_int32, [_vp, _dp, _gp, _dp]),
     "gf_reunitarize": (C.c_int32, [_vp, _dp, _gp]),
     "gf_plaquette": (C.c_int32, [_vp, _dp, _gp, _dp]),
     "gf_heatbath_half": (C.c_int32, [_vp, _dp, _gp, C.c_int32, C.c_int32, C.c_double,
@@ -245,6 +259,10 @@ class Context:
     def measure_static(self, U, geom, gauge, F=None, theta=None):
         return self._check(lib().gf_measure_static(self.h, _ptr(U), C.byref(geom), int(gauge),
                                                    _ptr(F), _ptr(theta)))
+
+    def unitarity(self, U, geom, out):
+        """largest |U U^dag - 1| element over all links into out (1 device double)"""
+        return self._check(lib().gf_unitarity(self.h, _ptr(U), C.byref(geom), _ptr(out)))
 
     def functional(self, U, geom, gauge, F):
         return self._check(lib().gf_functional(self.h, _ptr(U), C.byref(geom), int(gauge),
@@ -402,8 +420,21 @@ class Batch:
 
 def fix_params(omega=1.7, theta_target=1e-14, theta_switch=1e-6, max_sweeps=20000,
                check_every=100, reunit_at_check=1, flags=0, sa_steps=0, sa_micro=3,
-               sa_reunit_every=10, sa_T0=1.45, sa_T1=0.01, seed=0, sr_prob=0.0, or_form=0):
-    return FixParams(float(omega), float(theta_target), float(theta_switch), int(max_sweeps),
-                     int(check_every), int(reunit_at_check), int(flags), int(sa_steps),
-                     int(sa_micro), int(sa_reunit_every), int(or_form), float(sa_T0),
-                     float(sa_T1), int(seed), float(sr_prob))
+               sa_reunit_every=10, sa_T0=1.45, sa_T1=0.01, seed=0, sr_prob=0.0, or_form=0,
+               check_log=None):
+    """check_log: None or a (CheckRecord * n)() array the drivers fill, one
+    record per check (kept alive by the returned params)"""
+    p = FixParams(float(omega), float(theta_target), float(theta_switch), int(max_sweeps),
+                  int(check_every), int(reunit_at_check), int(flags), int(sa_steps),
+                  int(sa_micro), int(sa_reunit_every), int(or_form), float(sa_T0),
+                  float(sa_T1), int(seed), float(sr_prob))
+    if check_log is not None:
+        p.check_log = C.cast(check_log, C.POINTER(CheckRecord))
+        p.check_log_cap = len(check_log)
+        p._check_log = check_log
+    return p
+
+
+def check_log(n):
+    """an empty log of n check records for fix_params(check_log=...)"""
+    return (CheckRecord * int(n))()

@@ -136,6 +136,8 @@ gf_status gf_destroy(gf_ctx* c) {
   if (c->gbuf) (void)hipFree(c->gbuf);
   if (c->dev_tmask) (void)hipFree(c->dev_tmask);
   if (c->host_tmask) (void)hipHostFree(c->host_tmask);
+  if (c->dev_mon) (void)hipFree(c->dev_mon);
+  if (c->host_mon) (void)hipHostFree(c->host_mon);
   if (c->capture) (void)hipStreamDestroy(c->capture);
   for (auto& e : c->pool) (void)hipEventDestroy(e);
   for (auto& e : c->ev)

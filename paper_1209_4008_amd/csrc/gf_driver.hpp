@@ -71,6 +71,7 @@ inline gf_status check_params(gf_ctx* c, const gf_fix_params* p) {
   if (!(p->theta_target >= 0.0)) return fail(c, GF_ERR_ARG, "gf_fix: bad theta_target");
   if (p->sa_steps < 0 || p->sa_micro < 0 || p->sa_reunit_every < 0)
     return fail(c, GF_ERR_ARG, "gf_fix: bad annealing parameters");
+  if (p->check_log && p->check_log_cap < 0) return fail(c, GF_ERR_ARG, "gf_fix: bad check_log_cap");
   if (p->or_form < 0 || p->or_form > 3) return fail(c, GF_ERR_ARG, "gf_fix: or_form must be 0..3");
   if (p->or_form != 0 && p->sr_prob > 0.0)
     return fail(c, GF_ERR_UNSUPPORTED, "gf_fix: or_form != 0 with stochastic relaxation");
@@ -105,7 +106,28 @@ struct SweepGraph {
 
 inline void init_result(gf_fix_result* r) {
   memset(r, 0, sizeof *r);
+  r->unitarity_max = -1;
 }
+
+// what a driver records at its checks: the unitarity monitor (GF_FLAG_MONITOR)
+// and the caller's check log (params.check_log), both into the result
+struct CheckLog {
+  const gf_fix_params* p;
+  gf_fix_result* r;
+  std::chrono::steady_clock::time_point t0;
+  bool monitor() const { return (p->flags & GF_FLAG_MONITOR) != 0; }
+  void record(int32_t sweeps, int32_t prec, double F, double theta, double unitarity) {
+    if (monitor() && unitarity > r->unitarity_max) r->unitarity_max = unitarity;
+    if (!p->check_log || r->check_log_n >= p->check_log_cap) return;
+    gf_check_record& e = p->check_log[r->check_log_n++];
+    e.sweeps = sweeps;
+    e.prec = prec;
+    e.F = F;
+    e.theta = theta;
+    e.unitarity = monitor() ? unitarity : -1;
+    e.elapsed_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
 
 inline int32_t clamp_i32(int64_t v) { return v > INT32_MAX ? INT32_MAX : (int32_t)v; }
 

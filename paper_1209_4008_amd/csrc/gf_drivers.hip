@@ -27,10 +27,19 @@ gf_status run_anneal(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const 
 
 // reunitarise (optional), measure F and theta, copy to the host
 gf_status do_check(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, bool reunit, Timer& tm,
-                   Phase& ph) {
+                   Phase& ph, CheckLog& log) {
   gf_status st;
   const int nout = gauge == GF_COULOMB ? g->nt : 1;
   if ((st = ensure_out(c, nout)) != GF_OK) return st;
+  if (log.monitor()) {
+    // the drift the sweeps left, before the reunitarisation removes it
+    if ((st = ensure_mon(c)) != GF_OK) return st;
+    if ((st = tm.begin()) != GF_OK) return st;
+    if ((st = unitarity_launch(c, U, g, c->dev_mon)) != GF_OK) return st;
+    if ((st = tm.end(2, 2)) != GF_OK) return st;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->host_mon, c->dev_mon, sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+  }
   if (reunit) {
     if ((st = tm.begin()) != GF_OK) return st;
     if ((st = gf_reunitarize(c, U, g)) != GF_OK) return st;
@@ -54,6 +63,7 @@ gf_status do_check(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, bool reu
   ph.F = Fsum / nout;
   ph.theta = thmax;
   ph.checks++;
+  log.record(ph.sweeps, g->prec, ph.F, ph.theta, log.monitor() ? c->host_mon[0] : -1);
   return GF_OK;
 }
 
@@ -136,7 +146,7 @@ gf_status update_tmask(gf_ctx* c, const gf_geom* g, double target, int* n_active
 // GF_FLAG_FREEZE_TIMESLICES (Coulomb) until every timeslice has had
 // theta_t < target at a check, each timeslice frozen from that check on
 gf_status run_phase(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const gf_fix_params* p,
-                    double target, bool first_check_reunit, Timer& tm, Phase& ph,
+                    double target, bool first_check_reunit, Timer& tm, Phase& ph, CheckLog& log,
                     void* Gx = nullptr) {
   gf_status st;
   const int cat = g->prec == GF_FP32 ? 0 : 1;
@@ -154,7 +164,7 @@ gf_status run_phase(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const g
   int n_active = g->nt;
   for (;;) {
     const bool reunit = p->reunit_at_check && (ph.sweeps > 0 || first_check_reunit);
-    if ((st = do_check(c, U, g, gauge, reunit, tm, ph)) != GF_OK) return st;
+    if ((st = do_check(c, U, g, gauge, reunit, tm, ph, log)) != GF_OK) return st;
     if (freeze) {
       if ((st = update_tmask(c, g, target, &n_active)) != GF_OK) return st;
       if (n_active == 0) {
@@ -200,8 +210,9 @@ gf_status gf_fix(gf_ctx* c, void* U, const gf_geom* g, int32_t gauge, const gf_f
   const auto t0 = std::chrono::steady_clock::now();
   Timer tm{c, (p->flags & GF_FLAG_TIMING) != 0, r->kernel_ms, r->kernel_launches};
   Phase ph;
+  CheckLog log{p, r, t0};
   st = run_anneal(c, U, g, gauge, p, tm, &r->sa_steps);
-  if (st == GF_OK) st = run_phase(c, U, g, gauge, p, p->theta_target, false, tm, ph);
+  if (st == GF_OK) st = run_phase(c, U, g, gauge, p, p->theta_target, false, tm, ph, log);
   if (st == GF_OK) st = tm.flush();
   r->sweeps = ph.sweeps;
   r->checks = ph.checks;
@@ -258,6 +269,7 @@ gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
   const auto t0 = std::chrono::steady_clock::now();
   Timer tm{c, (p->flags & GF_FLAG_TIMING) != 0, r->kernel_ms, r->kernel_launches};
   Phase lo, hi;
+  CheckLog log{p, r, t0};
   // FP64 input -> FP32 working copy; g = 1
   if ((st = tm.begin()) == GF_OK && (st = gf_convert(c, g_hi, U_hi, g_lo, U_lo, 0)) == GF_OK) {
     if (track)
@@ -268,7 +280,8 @@ gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
   }
   if (st == GF_OK) st = run_anneal(c, U_lo, g_lo, gauge, p, tm, &r->sa_steps, track ? c->gbuf : nullptr);
   if (st == GF_OK)
-    st = run_phase(c, U_lo, g_lo, gauge, p, p->theta_switch, false, tm, lo, track ? c->gbuf : nullptr);
+    st = run_phase(c, U_lo, g_lo, gauge, p, p->theta_switch, false, tm, lo, log,
+                   track ? c->gbuf : nullptr);
   if (st == GF_OK) {
     r->theta_at_switch = lo.theta;
     // back to FP64: either the original field transformed by g (projected onto
@@ -285,7 +298,7 @@ gf_status gf_fix_mixed(gf_ctx* c, void* U_lo, const gf_geom* g_lo, void* U_hi,
       }
     }
     if (st == GF_OK) st = tm.end(3, 1);
-    if (st == GF_OK) st = run_phase(c, U_hi, g_hi, gauge, p, p->theta_target, false, tm, hi);
+    if (st == GF_OK) st = run_phase(c, U_hi, g_hi, gauge, p, p->theta_target, false, tm, hi, log);
   }
   if (st == GF_OK) st = tm.flush();
   r->sweeps_lo = lo.sweeps;

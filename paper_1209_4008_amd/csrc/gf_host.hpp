@@ -51,6 +51,9 @@ struct gf_ctx {
   uint8_t* host_tmask = nullptr;  // pinned
   size_t tmask_cap = 0;
   const uint8_t* tmask = nullptr;
+  // the drivers' unitarity monitor (GF_FLAG_MONITOR): 1 double each
+  double* dev_mon = nullptr;
+  double* host_mon = nullptr;  // pinned
 };
 
 // message of the last failed call made without a context (gf_create)
@@ -171,6 +174,17 @@ static inline gf_status ensure_tmask(gf_ctx* c, size_t n) {
   HIP_OR_FAIL(c, hipMalloc(&c->dev_tmask, n));
   HIP_OR_FAIL(c, hipHostMalloc(&c->host_tmask, n, hipHostMallocDefault));
   c->tmask_cap = n;
+  return GF_OK;
+}
+
+static inline gf_status ensure_mon(gf_ctx* c) {
+  if (c->dev_mon) return GF_OK;
+  HIP_OR_FAIL(c, hipMalloc(&c->dev_mon, sizeof(double)));
+  if (hipHostMalloc(&c->host_mon, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(c->dev_mon);
+    c->dev_mon = nullptr;
+    return fail(c, GF_ERR_HIP, "hipHostMalloc of the monitor output failed");
+  }
   return GF_OK;
 }
 
@@ -488,6 +502,8 @@ gf_status sweep_sr_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32
                            uint64_t sweep);
 gf_status anneal_step_tracked(gf_ctx* c, void* U, void* Gx, const gf_geom* g, int32_t gauge,
                               double T, uint64_t seed, uint64_t sweep, int32_t n_micro);
+// gf_monitor.hip: the unitarity deviation of a field into out (device, 1 double)
+gf_status unitarity_launch(gf_ctx* c, const void* U, const gf_geom* g, double* out);
 
 // validation shared by the tracked entry points
 #define CHECK_TRACKED(c, U, G, g, what)                                                  \

@@ -79,3 +79,37 @@ def test_create_without_gpu_reports_device_error():
     assert b"no GPU" in gf.lib().gf_last_error(None)
     with pytest.raises(gf.GFError):
         gf.Context()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """the ctypes structures of the binding have the sizes and field offsets
+    that a C compiler gives the structs of include/gf.h"""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"gf_geom": gf.Geom, "gf_fix_params": gf.FixParams, "gf_fix_result": gf.FixResult,
+               "gf_check_record": gf.CheckRecord}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gf.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        cname, field, value = line.split()
+        py = structs[cname]
+        got = C.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert got == int(value), (cname, field, got, value)
+        seen += 1
+    assert seen == sum(len(p._fields_) + 1 for p in structs.values())

@@ -509,3 +509,28 @@ def test_coulomb_frozen_driver():
         O.fix_coulomb_frozen(D, 1.7, target, int(t), check_every=20, reunit_at_check=0)
         for ts in np.nonzero(rc["frozen_at"] == t)[0]:
             assert np.array_equal(C[ts, :, :, :, 1:], D[ts, :, :, :, 1:])
+
+
+def test_unitarity_deviation():
+    """or_unitarity against closed forms: 0 for SU(3) links (to rounding) and
+    for a U(3) phase, 2d + d^2 for a row scaled by 1 + d, |e| for row 1 tilted
+    by e times row 0, +inf for a NaN."""
+    dims = (2, 2, 2, 4)
+    U = inputs.config0(dims, 0.4, 9)
+    assert O.unitarity(U) < 1e-14
+    V = U.copy()
+    V[1, 0, 1, 2, 3] *= np.exp(0.7j)  # a phase keeps U U^dag = 1
+    assert O.unitarity(V) < 1e-14
+    d = 3e-4
+    V = U.copy()
+    V[0, 1, 0, 3, 2, 0, :] *= 1 + d
+    assert O.unitarity(V) == pytest.approx(2 * d + d * d, rel=1e-9)
+    e = 2e-5 - 1e-5j
+    V = U.copy()
+    link = V[1, 1, 1, 1, 0]
+    link[1, :] = link[1, :] + e * link[0, :]
+    # (U U^dag)_10 = e <row0, row0> = e; (U U^dag)_11 = 1 + |e|^2
+    assert O.unitarity(V) == pytest.approx(abs(e), rel=1e-6)
+    V = U.copy()
+    V[0, 0, 0, 0, 2, 1, 1] = np.nan
+    assert O.unitarity(V) == math.inf
