@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--variant", type=str, default="",
                     help="probe: lanes,nontemporal of the FP64 12-real sweep (the benchmark's "
                          "tuned variant), e.g. 4,2")
+    ap.add_argument("--all-variants", action="store_true",
+                    help="probe: also 2 sweeps of every lanes x nontemporal variant of the "
+                         "12-real sweeps (counter runs then cover any tuned variant)")
     ap.add_argument("--probe", action="store_true",
                     help="kernel probe for profilers: bandwidth probes of known size, then "
                          "20 sweeps of each storage variant on a generated input")
@@ -505,6 +508,23 @@ def probe_main(args):
         ctx.set_sweep_variant(gf.FP64, gf.R12, tps, nt)
     log("probe: 20 sweeps per storage variant on", dims)
     res["variants"] = variant_rates(ctx, torch, gf, canon, dims, args.omega, n=20)
+    if args.all_variants:
+        # two sweeps of every lanes x nontemporal variant of the 12-real sweeps,
+        # so that counter runs cover whichever variant a tuner picks
+        log("probe: 2 sweeps of each 12-real variant")
+        for prec in (gf.FP32, gf.FP64):
+            g = gf.Geom.make(dims, prec, gf.R12)
+            f = ctx.empty_field(g)
+            ctx.pack(g, canon, f)
+            for tps in (1, 2, 4):
+                for nt in (0, 1, 2):
+                    ctx.set_sweep_variant(prec, gf.R12, tps, nt)
+                    for _ in range(2):
+                        ctx.sweep(f, g, gf.LANDAU, 0, args.omega)
+                        ctx.sweep(f, g, gf.LANDAU, 1, args.omega)
+            ctx.set_sweep_variant(prec, gf.R12, 0, -1)
+            torch.cuda.synchronize()
+            del f
     ctx.close()
     print(json.dumps(res), flush=True)
 
@@ -685,8 +705,23 @@ def headline_main(args):
     glo = gf.Geom.make(dims, gf.FP32, gf.R12)
     ghi = gf.Geom.make(dims, gf.FP64, gf.R12)
     U_lo, U_hi = ctx.empty_field(glo), ctx.empty_field(ghi)
+    axis = {}
+    if not args.no_tune:
+        # the storage axis: each storage's best variant, then the faster storage
+        # (the benchmark runs 12 reals, the configuration's storage, either way);
+        # the variants of the 12-real phases are then tuned once more, as the
+        # benchmark runs them
+        for g in (glo, ghi):
+            best, ms = ctx.autotune_storage(g, gf.LANDAU, canon)
+            axis["fp32" if g.prec == gf.FP32 else "fp64"] = {
+                "fastest": "r12" if best == gf.R12 else "r18",
+                "us_per_half_sweep": {"r12": round(ms[gf.R12] * 1e3, 2),
+                                      "r18": round(ms[gf.R18] * 1e3, 2)}}
+        log("autotune storage axis", axis)
     tuning = {} if args.no_tune else tune_phases(ctx, gf, canon, ((glo, U_lo), (ghi, U_hi)),
                                                  gf.LANDAU)
+    if axis:
+        tuning["storage_axis"] = axis
     flags = gf.FLAG_TIMING | (0 if args.no_graph else gf.FLAG_GRAPH)
     # a step: args.block sweeps of the FP64 fix of the input (theta_target 0:
     # the block always runs in full), checks every check_every sweeps
