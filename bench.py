@@ -263,12 +263,22 @@ def batch_main(args):
             owner.append(k)
     sites = sum(g.volume for g in geoms)
     pristine = [f.clone() for f in fields]
-    # no tuning on a single lattice: every batch launch sweeps all 192 fields
-    # (5.4 GB FP32, 10.8 GB FP64), which the batch's built-in variant is chosen for
     out = {"metric": "Gribov-copy batch: copies/s and best F per base configuration",
            "workload": "64 Haar copies each of 16^4 b5.8, 24^4 b6.0, 12^3x24 b5.9; annealing "
                        "2000 steps (T 1.2->0.01, 3 micro) + mixed fix theta<1e-13, one batch",
            "lattices": len(geoms), "sites": sites}
+    if not args.no_tune:
+        # the batch tuner: both phases' sweeps over all 192 fields (5.4 GB FP32,
+        # 10.8 GB FP64), kept on the context for their size class
+        b = gf.Batch(ctx, geoms, fields)
+        v32, v64, times = b.autotune()
+        b.close()
+        out["autotune"] = {
+            ph: {"lanes_per_site": v[0], "nontemporal": v[1],
+                 "us_per_half_sweep": {f"tps{k[1]}_nt{k[2]}": round(t * 1e3, 1)
+                                       for k, t in times.items() if k[0] == i}}
+            for i, (ph, v) in enumerate((("fp32_tracked", v32), ("fp64", v64)))}
+        log("batch autotune", json.dumps(out["autotune"]))
     for label, sa in (("annealed", 2000), ("overrelaxation_only", 0)):
         for f, p0 in zip(fields, pristine):
             f.copy_(p0)

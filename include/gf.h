@@ -417,9 +417,10 @@ gf_status gf_fix_mixed(gf_ctx* ctx, void* U_lo, const gf_geom* geom_lo, void* U_
  * they hold the inputs and receive the results. The batch allocates its FP32
  * 12-real working fields and FP32 gauge-transformation fields (192 + 48 bytes
  * per site, padded sites included) at creation. Coulomb batches are GF_ERR_UNSUPPORTED.
- * Sweep variant: the context's (gf_set_sweep_variant, gf_autotune); with none
- * set, the built-in one for the total size of the batch's fields of the
- * phase's precision (see gf_set_sweep_variant). */
+ * Sweep variant: the context's (gf_set_sweep_variant, gf_autotune,
+ * gf_batch_autotune); with none set, the built-in one for the total size of
+ * the active lattices' fields of the phase's precision (see
+ * gf_set_sweep_variant). */
 typedef struct gf_batch gf_batch;
 gf_status gf_batch_create(gf_ctx* ctx, int32_t n, const gf_geom* geoms, void* const* U,
                           int32_t gauge, gf_batch** out);
@@ -430,6 +431,20 @@ gf_status gf_batch_create(gf_ctx* ctx, int32_t n, const gf_geom* geoms, void* co
  * on it alone with seed + l ends. results: n host structs (kernel timings
  * are reported in results[0]). Synchronises the context stream. */
 gf_status gf_batch_run(gf_batch* batch, const gf_fix_params* params, gf_fix_result* results);
+/* Tunes the batch's overrelaxation sweeps, both phases: [0] FP32 12-real with
+ * g tracked (on the batch's working fields, as gf_batch_run starts them),
+ * [1] FP64 in the caller's storage (on scratch copies: the caller's fields
+ * are not modified). Every lanes x nontemporal variant runs a block of
+ * RED/BLACK sweep pairs over all lattices, captured as a hipGraph; the nine
+ * blocks are replayed in turn for five rounds and each variant timed by its
+ * median. The fastest of each phase is kept on the context for the phase's
+ * precision and storage and the size class of the batch's fields of that
+ * precision (so it applies while the active lattices' fields stay in that
+ * class) and returned in tps_out[2], nt_out[2] (NULL allowed); ms_out (NULL
+ * or 18 floats, index 9 * phase + 3 * nontemporal + log2(tps)): the time per
+ * half-sweep. Allocates the FP64 scratch copies (the fields' total size) for
+ * the call; synchronises the context stream. */
+gf_status gf_batch_autotune(gf_batch* batch, int32_t* tps_out, int32_t* nt_out, float* ms_out);
 gf_status gf_batch_destroy(gf_batch* batch);
 
 #ifdef __cplusplus

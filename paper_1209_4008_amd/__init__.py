@@ -140,6 +140,8 @@ SIGNATURES = {
     "gf_batch_create": (C.c_int32, [_vp, C.c_int32, C.POINTER(Geom), C.POINTER(C.c_void_p),
                                     C.c_int32, C.POINTER(C.c_void_p)]),
     "gf_batch_run": (C.c_int32, [_vp, C.POINTER(FixParams), C.POINTER(FixResult)]),
+    "gf_batch_autotune": (C.c_int32, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_float)]),
     "gf_batch_destroy": (C.c_int32, [_vp]),
 }
 
@@ -399,6 +401,16 @@ class Batch:
         h = C.c_void_p()
         ctx._check(lib().gf_batch_create(ctx.h, self.n, ga, ua, int(gauge), C.byref(h)))
         self.h = h
+
+    def autotune(self):
+        """gf_batch_autotune: ((tps, nt) of the FP32 phase, (tps, nt) of the FP64
+        phase, {(phase, tps, nt): ms per half-sweep})"""
+        tps = (C.c_int32 * 2)()
+        nt = (C.c_int32 * 2)()
+        ms = (C.c_float * 18)()
+        self.ctx._check(lib().gf_batch_autotune(self.h, tps, nt, ms))
+        times = {(ph, 1 << (k % 3), k // 3): ms[9 * ph + k] for ph in range(2) for k in range(9)}
+        return (tps[0], nt[0]), (tps[1], nt[1]), times
 
     def run(self, params):
         res = (FixResult * self.n)()

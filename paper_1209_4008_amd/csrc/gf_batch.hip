@@ -397,7 +397,154 @@ gf_status batch_anneal(gf_batch* b, const gf_fix_params* p, Timer& tm) {
   return GF_OK;
 }
 
+// The batch tuner for one phase: for each lanes count a table over all
+// lattices in memory of its own (a captured graph keeps the addresses it was
+// given), then the nine variants' blocks of `reps` RED/BLACK pairs captured and
+// replayed in turn for five rounds; times[k] = median ms per half-sweep.
+template <typename T, int NC, bool TRACK>
+gf_status batch_tune_phase(gf_batch* b, bool lo, float times[kVariants]) {
+  gf_ctx* c = b->c;
+  b->active.assign(b->n, 1);
+  struct Dev {
+    void* tab = nullptr;
+    uint32_t* map = nullptr;
+    uint32_t blocks = 0;
+  } dev[3];
+  auto release = [&]() {
+    for (auto& d : dev) {
+      if (d.tab) (void)hipFree(d.tab);
+      if (d.map) (void)hipFree(d.map);
+      d.tab = nullptr;
+      d.map = nullptr;
+    }
+  };
+  gf_status st = GF_OK;
+  for (int i = 0; i < 3 && st == GF_OK; ++i) {
+    const TableSet<T> t = make_table<T>(b, lo, 1 << i);
+    dev[i].blocks = t.blocks;
+    if (hipMalloc(&dev[i].tab, t.h.size() * sizeof(BatchEntry<T>)) != hipSuccess ||
+        hipMalloc((void**)&dev[i].map, t.map.size() * sizeof(uint32_t)) != hipSuccess ||
+        hipMemcpy(dev[i].tab, t.h.data(), t.h.size() * sizeof(BatchEntry<T>), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(dev[i].map, t.map.data(), t.map.size() * sizeof(uint32_t), hipMemcpyHostToDevice) !=
+            hipSuccess)
+      st = fail(c, GF_ERR_HIP, "gf_batch_autotune: launch tables");
+  }
+  if (st != GF_OK) {
+    release();
+    return st;
+  }
+  UpdOR<T> upd;
+  upd.omega = (T)1.7;
+  auto pair = [&](int tps, int nt) -> gf_status {
+    const Dev& d = dev[tps == 1 ? 0 : (tps == 2 ? 1 : 2)];
+    for (int par = 0; par < 2; ++par)
+      launch_batch_update<T, NC, UpdOR<T>, TRACK>(c, tps, nt, (const BatchEntry<T>*)d.tab, d.map,
+                                                  d.blocks, par, upd);
+    return launch_check(c, "gf_batch_autotune: sweeps");
+  };
+  // a block: about 100 ms of work (one pair of the 4-lane cached variant sets it)
+  float ms1 = 0;
+  if ((st = pair(4, 0)) == GF_OK) {
+    (void)hipEventRecord(c->ev[0], c->stream);
+    st = pair(4, 0);
+    (void)hipEventRecord(c->ev[1], c->stream);
+    if (st == GF_OK && (hipEventSynchronize(c->ev[1]) != hipSuccess ||
+                        hipEventElapsedTime(&ms1, c->ev[0], c->ev[1]) != hipSuccess))
+      st = fail(c, GF_ERR_HIP, "gf_batch_autotune: timing");
+  }
+  const int reps = std::max(2, std::min(100, (int)std::ceil(100.0 / std::max(ms1, 1e-3f))));
+  TuneGraph graphs[kVariants];
+  for (int k = 0; k < kVariants && st == GF_OK; ++k)
+    st = capture_block(c, [&]() -> gf_status {
+      for (int r = 0; r < reps; ++r) {
+        gf_status s2 = pair(1 << (k % 3), k / 3);
+        if (s2 != GF_OK) return s2;
+      }
+      return GF_OK;
+    }, graphs[k]);
+  constexpr int kRounds = 5;
+  float t[kVariants][kRounds];
+  for (int k = 0; k < kVariants && st == GF_OK; ++k)
+    if (hipGraphLaunch(graphs[k].exec, c->stream) != hipSuccess)  // warm-up
+      st = fail(c, GF_ERR_HIP, "gf_batch_autotune: replay");
+  for (int r = 0; r < kRounds && st == GF_OK; ++r)
+    for (int k = 0; k < kVariants && st == GF_OK; ++k) st = time_replay(c, graphs[k], &t[k][r]);
+  (void)hipStreamSynchronize(c->stream);
+  release();
+  if (st != GF_OK) return st;
+  for (int k = 0; k < kVariants; ++k) {
+    std::sort(t[k], t[k] + kRounds);
+    times[k] = t[k][kRounds / 2] / (float)(2 * reps);
+  }
+  return GF_OK;
+}
+
 }  // namespace
+
+gf_status gf_batch_autotune(gf_batch* b, int32_t* tps_out, int32_t* nt_out, float* ms_out) {
+  if (!b) return GF_ERR_ARG;
+  gf_ctx* c = b->c;
+  CHECK_CTX(c);
+  const int n = b->n;
+  float times[2][kVariants] = {};
+  gf_status st = GF_OK;
+  // scratch copies of the caller's FP64 fields: the FP64 phase is timed on
+  // them, and the FP32 working fields are converted from them
+  std::vector<size_t> off(n);
+  size_t total = 0;
+  for (int l = 0; l < n; ++l) {
+    off[l] = total;
+    total += (gf_field_bytes(&b->g64[l]) + 255) / 256 * 256;
+  }
+  void* scratch = nullptr;
+  if (hipMalloc(&scratch, total) != hipSuccess)
+    return fail(c, GF_ERR_NOMEM, "gf_batch_autotune: scratch copies (%zu bytes)", total);
+  std::vector<void*> user = b->U64;
+  for (int l = 0; l < n && st == GF_OK; ++l) {
+    b->U64[l] = (char*)scratch + off[l];
+    if (hipMemcpyAsync(b->U64[l], user[l], gf_field_bytes(&b->g64[l]), hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess)
+      st = fail(c, GF_ERR_HIP, "gf_batch_autotune: copy of lattice %d", l);
+  }
+  // the FP32 phase's fields as gf_batch_run starts them: the input in FP32,
+  // g = 1
+  for (int l = 0; l < n && st == GF_OK; ++l) {
+    st = gf_convert(c, &b->g64[l], b->U64[l], &b->g32[l], (char*)b->arena32 + b->off32[l], 0);
+    if (st == GF_OK) {
+      hipLaunchKernelGGL((k_fill_unit<float, 6, 1>), dim3(blocks_for(b->lat[l].vp), 2), dim3(kBlock), 0,
+                         c->stream, (v2<float>*)((char*)b->arenaG + b->offG[l]), b->lat[l].vp);
+      st = launch_check(c, "gf_batch_autotune: init");
+    }
+  }
+  if (st == GF_OK) st = batch_tune_phase<float, 6, true>(b, true, times[0]);
+  if (st == GF_OK) {
+    if (b->storage == GF_R12)
+      st = batch_tune_phase<double, 6, false>(b, false, times[1]);
+    else
+      st = batch_tune_phase<double, 9, false>(b, false, times[1]);
+  }
+  (void)hipStreamSynchronize(c->stream);
+  b->U64 = user;
+  (void)hipFree(scratch);
+  if (st != GF_OK) return st;
+  for (int ph = 0; ph < 2; ++ph) {
+    const bool lo = ph == 0;
+    int best = 0;
+    for (int k = 1; k < kVariants; ++k)
+      if (times[ph][k] < times[ph][best]) best = k;
+    b->active.assign(n, 1);
+    const gf_geom& g = lo ? b->g32[0] : b->g64[0];
+    const int cls = size_class(active_bytes(b, lo));
+    ctx_var(c, kSweepKind, g.prec, g.storage, cls).tps = 1 << (best % 3);
+    ctx_var(c, kSweepKind, g.prec, g.storage, cls).nt = best / 3;
+    if (tps_out) tps_out[ph] = 1 << (best % 3);
+    if (nt_out) nt_out[ph] = best / 3;
+    if (ms_out)
+      for (int k = 0; k < kVariants; ++k) ms_out[9 * ph + k] = times[ph][k];
+  }
+  return GF_OK;
+}
 
 gf_status gf_batch_run(gf_batch* b, const gf_fix_params* p, gf_fix_result* res) {
   if (!b) return GF_ERR_ARG;

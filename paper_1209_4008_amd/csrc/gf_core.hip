@@ -438,48 +438,6 @@ gf_status gf_get_sweep_variant(gf_ctx* c, int32_t prec, int32_t storage, int32_t
 
 namespace {
 
-// One captured block of timing work per variant, replayed from a hipGraph as
-// the drivers replay their sweep blocks.
-struct TuneGraph {
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  ~TuneGraph() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-  }
-};
-
-// capture `enqueue` (which launches on c->stream) into g on the context's
-// capture stream
-template <class F>
-gf_status capture_block(gf_ctx* c, F&& enqueue, TuneGraph& g) {
-  if (!c->capture) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
-  hipStream_t saved = c->stream;
-  c->stream = c->capture;
-  hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) {
-    c->stream = saved;
-    return fail(c, GF_ERR_HIP, "autotune: hipStreamBeginCapture: %s", hipGetErrorString(e));
-  }
-  gf_status st = enqueue();
-  e = hipStreamEndCapture(c->capture, &g.graph);
-  c->stream = saved;
-  if (st != GF_OK) return st;
-  if (e != hipSuccess) return fail(c, GF_ERR_HIP, "autotune: hipStreamEndCapture: %s", hipGetErrorString(e));
-  HIP_OR_FAIL(c, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
-  return GF_OK;
-}
-
-// time one replay of g on the context stream (ms)
-gf_status time_replay(gf_ctx* c, const TuneGraph& g, float* ms) {
-  HIP_OR_FAIL(c, hipEventRecord(c->ev[0], c->stream));
-  HIP_OR_FAIL(c, hipGraphLaunch(g.exec, c->stream));
-  HIP_OR_FAIL(c, hipEventRecord(c->ev[1], c->stream));
-  HIP_OR_FAIL(c, hipEventSynchronize(c->ev[1]));
-  HIP_OR_FAIL(c, hipEventElapsedTime(ms, c->ev[0], c->ev[1]));
-  return GF_OK;
-}
-
 // The autotuner's timing, done the way the drivers run the kernels: for each
 // of the nine variants (lanes per site 1, 2, 4 x nontemporal mode 0, 1, 2) a
 // block of `reps` units of work (`unit` enqueues one: a RED/BLACK sweep pair,

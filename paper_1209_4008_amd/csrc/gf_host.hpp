@@ -485,6 +485,51 @@ static inline gf_status update_tracked(gf_ctx* c, void* U, void* Gx, const gf_ge
 }
 
 // ---------------------------------------------------------------------------
+// tuner timing (gf_core.hip: single fields, gf_batch.hip: batches)
+// ---------------------------------------------------------------------------
+// One captured block of timing work per variant, replayed from a hipGraph as
+// the drivers replay their sweep blocks.
+struct TuneGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~TuneGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+// capture `enqueue` (which launches on c->stream) into g on the context's
+// capture stream
+template <class F>
+inline gf_status capture_block(gf_ctx* c, F&& enqueue, TuneGraph& g) {
+  if (!c->capture) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+  hipStream_t saved = c->stream;
+  c->stream = c->capture;
+  hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    c->stream = saved;
+    return fail(c, GF_ERR_HIP, "autotune: hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  gf_status st = enqueue();
+  e = hipStreamEndCapture(c->capture, &g.graph);
+  c->stream = saved;
+  if (st != GF_OK) return st;
+  if (e != hipSuccess) return fail(c, GF_ERR_HIP, "autotune: hipStreamEndCapture: %s", hipGetErrorString(e));
+  HIP_OR_FAIL(c, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+  return GF_OK;
+}
+
+// time one replay of g on the context stream (ms)
+inline gf_status time_replay(gf_ctx* c, const TuneGraph& g, float* ms) {
+  HIP_OR_FAIL(c, hipEventRecord(c->ev[0], c->stream));
+  HIP_OR_FAIL(c, hipGraphLaunch(g.exec, c->stream));
+  HIP_OR_FAIL(c, hipEventRecord(c->ev[1], c->stream));
+  HIP_OR_FAIL(c, hipEventSynchronize(c->ev[1]));
+  HIP_OR_FAIL(c, hipEventElapsedTime(ms, c->ev[0], c->ev[1]));
+  return GF_OK;
+}
+
+// ---------------------------------------------------------------------------
 // internal functions shared between the units (C++ linkage)
 // ---------------------------------------------------------------------------
 // gf_core.hip: F and theta of a field into F, th (either may be NULL)

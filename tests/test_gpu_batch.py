@@ -80,6 +80,40 @@ def test_batch_variants_equal_individual_runs(ctx, tps, mode):
             ctx.set_sweep_variant(prec, gf.R12, 0, -1)
 
 
+@pytest.mark.parametrize("storage", [gf.R12, gf.R18])
+def test_batch_autotune(ctx, storage):
+    """gf_batch_autotune: the caller's fields are untouched, each phase keeps
+    the fastest of its nine timed variants on the context (these small
+    lattices are in the first size class), and the batch then gives what
+    each lattice gives alone in that variant"""
+    Us = _inputs()
+    fields, geoms = [], []
+    for U in Us:
+        f, g = upload(ctx, U, gf.FP64, storage)
+        fields.append(f)
+        geoms.append(g)
+    before = [download(ctx, f, g) for f, g in zip(fields, geoms)]
+    b = gf.Batch(ctx, geoms, fields)
+    try:
+        v32, v64, times = b.autotune()
+    finally:
+        b.close()
+    try:
+        say("batch autotune", storage, "FP32", v32, "FP64", v64)
+        for ph, v in ((0, v32), (1, v64)):
+            mine = {k[1:]: t for k, t in times.items() if k[0] == ph}
+            assert len(mine) == 9 and all(t > 0 for t in mine.values())
+            assert mine[v] == min(mine.values())
+        assert ctx.get_sweep_variant(gf.FP32, gf.R12) == v32
+        assert ctx.get_sweep_variant(gf.FP64, storage) == v64
+        for f, g, want in zip(fields, geoms, before):
+            assert np.array_equal(download(ctx, f, g), want)
+        batch_vs_alone(ctx, Us, storage, 0)
+    finally:
+        ctx.set_sweep_variant(gf.FP32, gf.R12, 0, -1)
+        ctx.set_sweep_variant(gf.FP64, storage, 0, -1)
+
+
 def test_batch_of_many_small_lattices(ctx):
     """72 lattices of 2^4 ... 4^4 (the table search over the lattices runs
     seven levels deep) against the lattices alone"""
