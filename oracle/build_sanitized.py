@@ -1,6 +1,6 @@
 """Build the oracle with AddressSanitizer and UndefinedBehaviorSanitizer into
 oracle/liboracle_san.so (test infrastructure: a CPU test runs the oracle's
-pins against this build, see tests/test_oracle_sanitized.py). Host code only;
+pins against the sanitized library, see tests/test_oracle_sanitized.py). Host code only;
 plain gcc, the same flags as oracle/build.py plus the sanitizers."""
 import os
 import subprocess
