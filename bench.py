@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--omega", type=float, default=1.7)
     ap.add_argument("--theta-switch", type=float, default=1e-6)
+    ap.add_argument("--late-switch", type=float, default=1e-12,
+                    help="landau48/landau32: one more full mixed fix that leaves FP32 at this "
+                         "theta (0: skip)")
     ap.add_argument("--theta-target", type=float, default=1e-14)
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--max-sweeps", type=int, default=20000)
@@ -662,6 +665,22 @@ def mixed_vs_fp64(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi, params, V, log_pa
         "final_F_rel_diff_mixed_vs_fp64": abs(r.F - r64.F) / abs(r64.F)}
 
 
+def late_switch(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi, params, switch, r64, t64):
+    """the full mixed fix of the same input with the FP32 phase run on to theta
+    < switch: time, sweeps and final F against the FP64 fix (r64, t64)"""
+    p = type(params).from_buffer_copy(params)
+    p.theta_switch = switch
+    ctx.pack(ghi, canon, U_hi)
+    r, t = timed_fix(ctx, torch, lambda: ctx.fix_mixed(U_lo, glo, U_hi, ghi, gf.LANDAU, p))
+    log(f"mixed, switch {switch:g}: {r.sweeps} sweeps ({r.sweeps_lo} FP32) in {t:.2f} s, "
+        f"theta {r.theta:.3e}")
+    return {"theta_switch": switch, "time_ms": round(1e3 * t, 1), "sweeps": r.sweeps,
+            "sweeps_fp32": r.sweeps_lo, "theta_at_switch": r.theta_at_switch,
+            "status": r.status, "F": r.F, "theta": r.theta,
+            "F_rel_diff_vs_fp64": abs(r.F - r64.F) / abs(r64.F),
+            "speedup_vs_fp64": round(t64 / t, 4)}
+
+
 def landau32_secondary(ctx, torch, gf, inputs, args):
     """32^4 beta 6.0 (300 sweeps, seed 2): mixed and FP64 fixes to theta < 1e-14
     and the FP64 sweep kernel's rate, which the Infinity Cache assists here."""
@@ -677,6 +696,9 @@ def landau32_secondary(ctx, torch, gf, inputs, args):
                            flags=gf.FLAG_TIMING | gf.FLAG_GRAPH)
     r, t_mixed, r64, t64, out = mixed_vs_fp64(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi,
                                               params, V, log_path=args.check_log or None)
+    if args.late_switch > 0:
+        out["mixed_late_switch"] = late_switch(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi, params,
+                                               args.late_switch, r64, t64)
     tps, nt = ctx.sweep_variant_for(ghi)
     kname = "k_update_half<double,6,0,UpdOR,%d,%d,false>" % (tps, nt)
     roof = kernel_roofline(r64.kernel_ms[1], r64.kernel_launches[1], V, 16 * 12 * 8, kname, dims)
@@ -770,6 +792,9 @@ def headline_main(args):
     extras.update(cmp)
     extras["mixed_fp64_phase_roofline"] = kernel_roofline(r.kernel_ms[1], r.kernel_launches[1],
                                                           V, 16 * 12 * 8, kname, dims)
+    if args.late_switch > 0:
+        extras["mixed_late_switch"] = late_switch(ctx, torch, gf, canon, glo, ghi, U_lo, U_hi,
+                                                  full_params, args.late_switch, r64, t64)
     del U_lo, U_hi
     if not args.no_extras:
         extras["variants"] = variant_rates(ctx, torch, gf, canon, dims, args.omega, n=50)
@@ -811,9 +836,10 @@ def headline_main(args):
         "config": {"workload": "landau-gauge-fix 48x48x48x48 wilson-heatbath beta=6.2 (400 sweeps, "
                                "seed 3): each step %d sweeps of the fp64-r12 fix (omega %g, check "
                                "every %d, hipGraph); beside it the full mixed fp32-r12 -> fp64-r12 "
-                               "(switch %g) and pure fp64-r12 fixes to theta<%g"
+                               "(switch %g) and pure fp64-r12 fixes to theta<%g, and the mixed "
+                               "fix with the switch at %g"
                                % (args.block, args.omega, args.check_every, args.theta_switch,
-                                  args.theta_target),
+                                  args.theta_target, args.late_switch),
                    "lattice": list(dims), "beta": beta, "omega": args.omega,
                    "check_every": args.check_every, "plaquette": round(plaq, 6),
                    "sweeps_per_step": sweeps / args.steps,

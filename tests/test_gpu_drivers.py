@@ -54,19 +54,22 @@ def _mixed(ctx, U, gauge, flags, target=1e-14, switch=1e-6, max_sweeps=4000, che
     return r, P0.item(), P1.item(), fhi, ghi
 
 
+@pytest.mark.parametrize("switch", [1e-6, 1e-12])
 @pytest.mark.parametrize("gauge", [gf.LANDAU, gf.COULOMB])
-def test_fix_mixed_matches_fp64_oracle(ctx, gauge):
+def test_fix_mixed_matches_fp64_oracle(ctx, gauge, switch):
     """FP32 phase with tracked g, FP64 phase on the original orbit: final F
-    equals the FP64 oracle's to 1e-10, the plaquette is unchanged to 1e-13."""
+    equals the FP64 oracle's to 1e-10, the plaquette is unchanged to 1e-13;
+    also with the FP32 phase run on to theta < 1e-12 (the tracked g is then
+    applied at FP32 precision, and the FP64 phase removes that)."""
     dims = (8, 8, 8, 8) if gauge == gf.LANDAU else (8, 6, 6, 6)
     U = inputs.config0(dims, 0.3, 1)
-    r, P0, P1, fhi, ghi = _mixed(ctx, U, gauge, gf.FLAG_TIMING)
+    r, P0, P1, fhi, ghi = _mixed(ctx, U, gauge, gf.FLAG_TIMING, switch=switch)
     ref = oracle_input(U, gf.FP64, gf.R12)
     ro = O.fix(ref, gauge, 1.7, 1e-14, 4000, 100, 1)
-    say("mixed", gauge, r.as_dict(), ro)
+    say("mixed", gauge, "switch", switch, r.as_dict(), ro)
     assert r.status == gf.OK and ro["converged"]
     assert r.sweeps_lo > 0 and r.sweeps > r.sweeps_lo
-    assert r.theta_at_switch < 1e-6 and r.theta < 1e-14
+    assert r.theta_at_switch < switch and r.theta < 1e-14
     assert r.F == pytest.approx(ro["F"], rel=1e-10)
     assert P1 == pytest.approx(P0, abs=1e-13)
     assert r.kernel_launches[0] == 2 * r.sweeps_lo
