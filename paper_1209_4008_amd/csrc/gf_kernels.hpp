@@ -388,13 +388,12 @@ __device__ __forceinline__ HBDraws<float> split_draws(const UpdHB<float>& u, uin
   return d;
 }
 
-// Gram-Schmidt on rows 0 and 1 in the field's precision. A 12-real link
-// rebuilds row 2 = conj(row0 x row1), so a norm error of the stored rows
-// reappears, doubled, in row 2; a forward update G U mixes row 2 back into
-// rows 0 and 1, and under strongly mixing updates (hot annealing) the error
-// grows geometrically. Projecting the two stored rows of every forward-updated
-// link keeps it at the rounding level (each link is a forward link once per
-// sweep).
+// Gram-Schmidt on rows 0 and 1. A 12-real link rebuilds row 2 =
+// conj(row0 x row1), so a norm error of the stored rows reappears, doubled, in
+// row 2; a forward update G U mixes row 2 back into rows 0 and 1, and under
+// strongly mixing updates (hot annealing) the error grows geometrically.
+// Projecting the two stored rows of every forward-updated link keeps it at the
+// rounding level (each link is a forward link once per sweep).
 template <typename T>
 __device__ __forceinline__ void orthonormalize_rows01(Su3<T>& A) {
   T n0 = 0;
@@ -417,6 +416,27 @@ __device__ __forceinline__ void orthonormalize_rows01(Su3<T>& A) {
   n1 = rsqrt_t(n1);
 #pragma unroll
   for (int b = 0; b < 3; ++b) A.e[1][b] = cx(A.e[1][b].re * n1, A.e[1][b].im * n1);
+}
+
+// FP32 links are projected in FP64 and rounded once. Done in FP32 arithmetic,
+// the projection's rounding is not neutral: it moves a link by a small amount
+// that is not a gauge transformation and that the next update, which maximises
+// the local functional, does not undo, so an FP32 12-real field walked off its
+// gauge orbit (measured on a 32^4 beta = 6.0 configuration: plaquette +2.4e-5
+// after 10 300 overrelaxation sweeps, against a few 1e-7 either way for the
+// 18-real field, which is not projected, and for this form). The sites' g of
+// the tracked updates is projected the same way.
+__device__ __forceinline__ void orthonormalize_rows01(Su3<float>& A) {
+  Su3<double> D;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) D.e[a][b] = cx<double>(A.e[a][b].re, A.e[a][b].im);
+  orthonormalize_rows01<double>(D);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) A.e[a][b] = cx<float>((float)D.e[a][b].re, (float)D.e[a][b].im);
 }
 
 // Stochastic relaxation (Sec. 1): per site and subgroup, with probability

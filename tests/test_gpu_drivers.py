@@ -111,6 +111,36 @@ def test_fix_mixed_untracked_carries_fp32_rounding(ctx):
     assert abs(P1 - P0) > 1e-12
 
 
+@pytest.mark.parametrize("storage", [gf.R12, gf.R18])
+def test_fp32_sweeps_stay_on_the_gauge_orbit(ctx, storage):
+    """A gauge transformation (eq. (4)) leaves the plaquette unchanged, so 2600
+    FP32 overrelaxation sweeps (the FP32 phase of the mixed 32^4 fix) may move
+    it only by accumulated FP32 rounding, which averages out over the 6V
+    plaquettes: here a few 1e-7. A projection of the 12-real links whose
+    rounding is not neutral walks the field off its orbit instead (+5.7e-6
+    over these sweeps when the rows were projected in FP32 arithmetic)."""
+    import torch
+    dims = (32, 32, 32, 32)
+    canon = inputs.gpu_heatbath(dims, 6.0, 300, 2)
+    g = gf.Geom.make(dims, gf.FP32, storage)
+    U = ctx.empty_field(g)
+    ctx.pack(g, canon, U)
+    P0, P1 = ctx.empty_out(1), ctx.empty_out(1)
+    ctx.plaquette(U, g, P0)
+    for _ in range(26):
+        for _ in range(100):
+            ctx.sweep(U, g, gf.LANDAU, 0, 1.7)
+            ctx.sweep(U, g, gf.LANDAU, 1, 1.7)
+        ctx.reunitarize(U, g)
+    ctx.plaquette(U, g, P1)
+    F, th = ctx.empty_out(1), ctx.empty_out(1)
+    ctx.measure(U, g, gf.LANDAU, F, th)
+    torch.cuda.synchronize()
+    say("FP32 orbit", storage, "plaquette change", P1.item() - P0.item(), "theta", th.item())
+    assert th.item() < 1e-5  # the sweeps did fix the gauge
+    assert abs(P1.item() - P0.item()) < 1e-6
+
+
 @pytest.mark.parametrize("prec,storage", [(gf.FP64, gf.R18), (gf.FP64, gf.R12)])
 def test_fix_coulomb_matches_oracle(ctx, prec, storage):
     dims = (8, 4, 6, 4)
