@@ -418,25 +418,45 @@ __device__ __forceinline__ void orthonormalize_rows01(Su3<T>& A) {
   for (int b = 0; b < 3; ++b) A.e[1][b] = cx(A.e[1][b].re * n1, A.e[1][b].im * n1);
 }
 
-// FP32 links are projected in FP64 and rounded once. Done in FP32 arithmetic,
-// the projection's rounding is not neutral: it moves a link by a small amount
-// that is not a gauge transformation and that the next update, which maximises
-// the local functional, does not undo, so an FP32 12-real field walked off its
-// gauge orbit (measured on a 32^4 beta = 6.0 configuration: plaquette +2.4e-5
-// after 10 300 overrelaxation sweeps, against a few 1e-7 either way for the
-// 18-real field, which is not projected, and for this form). The sites' g of
-// the tracked updates is projected the same way.
+// FP32 rows: the squared norm is summed in FP64 from the FP32 elements (the
+// products are exact), and each element moves by x * c with c = 1/|row| - 1
+// in one rounding, fmaf(x, c, x). Done wholly in FP32 arithmetic, the
+// projection's rounding is not neutral: near unit norm the rounded squared
+// norm and the rounded scale factor sit on a grid coarser than the correction
+// they carry, so each update moved the link by a small amount that is not a
+// gauge transformation and that the next update, which maximises the local
+// functional, did not undo; an FP32 12-real field walked off its gauge orbit
+// (measured on a 32^4 beta = 6.0 configuration: plaquette +2.4e-5 after
+// 10 300 overrelaxation sweeps, against a few 1e-7 either way for the 18-real
+// field, which is not projected, and for this form). The sites' g of the
+// tracked updates is projected the same way.
+__device__ __forceinline__ float unit_scale_minus_one(const Cx<float>* row) {
+  double s = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const double x = row[b].re, y = row[b].im;
+    s = fma(x, x, fma(y, y, s));
+  }
+  const double d = s - 1.0;
+  double c = d * fma(0.375, d, -0.5);  // (1 + d)^(-1/2) - 1 up to O(d^3)
+  if (fabs(d) >= 0x1p-12) c = rsqrt_t(s) - 1.0;
+  return (float)c;
+}
+
 __device__ __forceinline__ void orthonormalize_rows01(Su3<float>& A) {
-  Su3<double> D;
+  const float c0 = unit_scale_minus_one(A.e[0]);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int b = 0; b < 3; ++b)
+    A.e[0][b] = cx<float>(fmaf(A.e[0][b].re, c0, A.e[0][b].re), fmaf(A.e[0][b].im, c0, A.e[0][b].im));
+  Cx<float> ip = cx<float>(0, 0);  // sum conj(row0) row1
 #pragma unroll
-    for (int b = 0; b < 3; ++b) D.e[a][b] = cx<double>(A.e[a][b].re, A.e[a][b].im);
-  orthonormalize_rows01<double>(D);
+  for (int b = 0; b < 3; ++b) ip = cmac_cb(ip, A.e[1][b], A.e[0][b]);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int b = 0; b < 3; ++b) A.e[1][b] = csub(A.e[1][b], cmul(ip, A.e[0][b]));
+  const float c1 = unit_scale_minus_one(A.e[1]);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) A.e[a][b] = cx<float>((float)D.e[a][b].re, (float)D.e[a][b].im);
+  for (int b = 0; b < 3; ++b)
+    A.e[1][b] = cx<float>(fmaf(A.e[1][b].re, c1, A.e[1][b].re), fmaf(A.e[1][b].im, c1, A.e[1][b].im));
 }
 
 // Stochastic relaxation (Sec. 1): per site and subgroup, with probability
