@@ -17,12 +17,23 @@ LIB_PATH = os.path.join(HERE, "libgfinputs.so")
 _lib = None
 
 
+def _torch_hip_first():
+    """PyTorch carries its own HIP runtime. If this library, built against the
+    system ROCm, is loaded into a process first, libgf later finds no GPU
+    (gf_create: no GPU device available), so torch's runtime is started
+    before the library is loaded (on a machine without a GPU this only asks
+    torch, which answers no)."""
+    import torch
+    torch.cuda.is_available()
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
+        _torch_hip_first()
         L = C.CDLL(LIB_PATH)
         d = C.POINTER(C.c_double)
         i32p = C.POINTER(C.c_int32)

@@ -149,11 +149,15 @@ _lib = None
 
 
 def lib():
-    """Load libgf.so (built by paper_1209_4008_amd/build.py)."""
+    """Load libgf.so (built by paper_1209_4008_amd/build.py). PyTorch's own HIP
+    runtime is started first: with a library built against the system ROCm
+    loaded into the process before it, gf_create finds no GPU."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run paper_1209_4008_amd/build.py")
+        import torch
+        torch.cuda.is_available()
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
