@@ -124,8 +124,11 @@ gf_status gf_convert(gf_ctx* ctx, const gf_geom* src, const void* U_src, const g
  * subgroups (0,1), (0,2), (1,2) in turn the local maximum of eq. (6) raised to
  * the power omega (Sec. 2; the 19-flop form s = (c r0, b c r) with
  * b = (omega r0^2 + |r|^2)/(r0^2 + |r|^2), c = (r0^2 + b^2 |r|^2)^(-1/2)),
- * and the product transformation applied to the 8 links in place.
- * omega in [1, 2) (1 = plain relaxation); otherwise GF_ERR_ARG. */
+ * and the product transformation applied to the 8 links in place. With 12-real
+ * storage the two stored rows of each updated forward link are then
+ * re-orthonormalised by Gram-Schmidt (in an FP32 field with the squared norms
+ * summed in FP64 and one rounding per element, which keeps the field on its
+ * gauge orbit). omega in [1, 2) (1 = plain relaxation); otherwise GF_ERR_ARG. */
 gf_status gf_sweep(gf_ctx* ctx, void* U, const gf_geom* geom, int32_t gauge, int32_t parity,
                    double omega);
 /* gf_sweep with another form of the power g^omega (Sec. 2: the power is taken
@@ -215,7 +218,7 @@ gf_status gf_gauge_unpack(gf_ctx* ctx, const gf_geom* geom, const void* G, doubl
 /* gf_sweep, gf_heatbath_half and gf_micro_half on an FP32 field that also
  * accumulate each updated site's whole transformation Gtot (the product of
  * its three subgroup factors) into G: g(x) <- Gtot g(x), rows 0 and 1 then
- * re-orthonormalised in FP32. Starting from G = 1, any sequence of such calls
+ * re-orthonormalised as 12-real FP32 links are (gf_sweep). Starting from G = 1, any sequence of such calls
  * leaves U equal to the input transformed by G (eq. (4)), up to FP32
  * rounding. geom must be FP32 (else GF_ERR_UNSUPPORTED); G (gf_gauge_bytes of
  * geom) must not overlap U. The heatbath and microcanonical calls reject
