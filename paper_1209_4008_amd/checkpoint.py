@@ -67,7 +67,7 @@ def geom_of(header):
 def save(ctx, path, U, geom, **state):
     """Write the device field U (geometry geom) and the run state to path."""
     torch = ctx.torch
-    canon = torch.empty(geom.volume * 72, dtype=torch.float64, device="cuda")
+    canon = torch.empty(geom.volume * 72, dtype=torch.float64, device=ctx.stream.device)
     ctx.unpack(geom, U, canon)
     ctx.stream.synchronize()
     write(path, canon.cpu().numpy(), geom.dims, geom.prec, geom.storage, state)
@@ -83,8 +83,8 @@ def load(ctx, path, U=None):
         U = ctx.empty_field(geom)
     elif U.numel() * U.element_size() < field_bytes(geom):
         raise GFError(ERR_ARG, "checkpoint: the buffer is smaller than the field")
-    canon = torch.from_numpy(links).to("cuda")
-    torch.cuda.current_stream().synchronize()
+    canon = torch.from_numpy(links).to(ctx.stream.device)
+    torch.cuda.current_stream(ctx.stream.device).synchronize()
     ctx.pack(geom, canon, U)
     ctx.stream.synchronize()
     return U, geom, header["state"]
